@@ -1,0 +1,188 @@
+/*
+ * chfsi.h - C ABI of the MI355X (gfx950) Chebyshev-filtered subspace
+ * iteration library.
+ *
+ * The library solves the dense Hermitian generalized eigenproblem
+ *     H x = lambda S x      (H Hermitian, S Hermitian positive definite)
+ * for the nev smallest eigenpairs, following Algorithm 1 of Berljafa & Di
+ * Napoli, "A Parallel and Scalable Iterative Solver for Sequences of Dense
+ * Eigenproblems Arising in FLAPW" (arXiv 1305.5120): reduction to standard
+ * form (Section 3), a Lanczos estimate of the spectrum's upper end, then
+ * repeated Chebyshev filtering (eq. (3)), QR re-orthonormalization,
+ * Rayleigh-Ritz and locking of converged pairs.  Solving a sequence of
+ * correlated problems (Section 2) warm-starts each solve from the previous
+ * solution, which the context keeps on the device.
+ *
+ * Conventions for every entry point
+ *   - complex numbers are complex128: two IEEE doubles (re, im), 16 bytes,
+ *     the layout of C99 `double _Complex`, `hipDoubleComplex` and
+ *     torch.complex128;
+ *   - matrices are column-major with a leading dimension `ld* >= rows`;
+ *     H and S are read in full (S only in its lower triangle);
+ *   - pointers documented as "device" must be device memory of the GPU that
+ *     was current when the context was created; "host" pointers are ordinary
+ *     host memory;
+ *   - the caller owns every buffer it passes; the library neither frees nor
+ *     keeps caller pointers after a call returns; the context owns its own
+ *     device workspace (about 4 n^2 + 8 n k complex numbers) and releases it
+ *     in chfsi_release;
+ *   - work is queued on the stream given at creation; calls return after
+ *     their results are complete (they synchronize that stream);
+ *   - errors are returned as chfsi_status; nothing is thrown or aborted;
+ *     chfsi_last_error() gives a message for the last failure of a context;
+ *     a failed call leaves the context usable;
+ *   - a context is not thread-safe: one host thread at a time.
+ */
+#ifndef CHFSI_H
+#define CHFSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chfsi_ctx_s* chfsi_ctx;
+
+typedef enum {
+  CHFSI_OK = 0,
+  CHFSI_EINVAL = -1,  /* invalid argument (sizes, leading dimensions, null pointers, tol <= 0) */
+  CHFSI_ENOTPD = -2,  /* S is not positive definite (column in chfsi_last_error) */
+  CHFSI_ENOCONV = -3, /* max_iter reached; outputs hold the converged prefix (info.converged) */
+  CHFSI_ENAN = -4,    /* non-finite value in the iteration (e.g. NaN in H) */
+  CHFSI_ENOMEM = -5,  /* device allocation failed */
+  CHFSI_EHIP = -6     /* HIP runtime error */
+} chfsi_status;
+
+typedef struct {
+  int32_t degree;        /* Chebyshev filter degree m (default 20) */
+  int32_t max_iter;      /* outer iterations before CHFSI_ENOCONV (default 1000) */
+  int32_t lanczos_steps; /* Lanczos steps for the spectral bound (default 10, at most 96) */
+  int32_t precision;     /* 0: FP64 throughout (the only mode of this version) */
+  uint64_t seed;         /* Philox4x32-10 seed of the random start vectors (default 0) */
+  int32_t profile;       /* 1: time every filter kernel launch with device events */
+  int32_t reserved[7];
+} chfsi_opts;
+
+typedef struct {
+  int32_t iterations;      /* outer iterations of Algorithm 1 */
+  int32_t converged;       /* locked eigenpairs (>= nev on success) */
+  int32_t warm_start;      /* 1 when the start block came from previous vectors */
+  int32_t filter_launches; /* filter kernel launches (degree steps) */
+  double filter_flops;     /* algorithmic filter work: sum over steps of 8 n^2 k_active */
+  double filter_kernel_seconds; /* summed filter kernel durations (profile = 1, else 0) */
+  double t_reduce, t_lanczos, t_filter, t_qr, t_rr, t_resid, t_total; /* seconds per phase */
+  double b_upper;          /* Lanczos upper bound of the standard-form spectrum */
+  double theta_min;        /* smallest Lanczos Ritz value */
+  double h_H;              /* Lanczos estimate of ||H||_2 (lower bound); scale of the lock test */
+  double a0, a;            /* filter scale point and lower end of the damped interval at exit */
+  double max_rel_residual; /* max_j ||H x_j - lambda_j S x_j||_2 / h_H over returned pairs */
+} chfsi_info;
+
+/* Fill *opts with the defaults listed above. */
+void chfsi_default_opts(chfsi_opts* opts);
+
+/* Human-readable name of a status code (static string). */
+const char* chfsi_status_string(chfsi_status s);
+
+/* Create a context for problems of size n on the current HIP device.
+ * stream: a hipStream_t (0 = the null stream).  opts may be NULL (defaults).
+ * CHFSI_EINVAL if n < 1 or an option is out of range. */
+chfsi_status chfsi_create(chfsi_ctx* out, int64_t n, const chfsi_opts* opts, void* stream);
+
+/* Free every device buffer owned by ctx.  NULL-safe. */
+void chfsi_release(chfsi_ctx ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
+const char* chfsi_last_error(chfsi_ctx ctx);
+
+/* Forget the warm state kept from the previous solve (next solve starts cold). */
+chfsi_status chfsi_reset(chfsi_ctx ctx);
+
+/* Reduction to standard form (Section 3): S = L L^H (Cholesky) and
+ * A = L^{-1} H L^{-H}, made exactly Hermitian.  H, S: device n x n.
+ * S == NULL reuses the factor of the previous call (CHFSI_EINVAL if none).
+ * The factors stay in ctx (chfsi_copy_factors reads them). */
+chfsi_status chfsi_reduce(chfsi_ctx ctx, const void* H, int64_t ldh, const void* S, int64_t lds);
+
+/* Solve H x = lambda S x for the nev smallest eigenpairs with a search block
+ * of k = nev + nex vectors (Algorithm 1 with locking).
+ *   H, S    device n x n; S == NULL reuses the cached factor of S (sequences
+ *           with a fixed overlap matrix);
+ *   V_warm  device n x kw approximate eigenvectors of the generalized problem
+ *           (e.g. the previous solution), 0 <= kw <= k, may be NULL.  When
+ *           NULL, the vectors and filter bounds kept from the previous solve
+ *           on this context are used if their shape matches, else a seeded
+ *           random block;
+ *   tol     convergence: ||H x - lambda S x||_2 <= tol * h_H for each pair;
+ *   evals   host, nev doubles, ascending;
+ *   X       device n x nev, S-orthonormal eigenvectors (may be NULL);
+ *   info    may be NULL.
+ * CHFSI_ENOCONV leaves the converged prefix in evals/X (NaN beyond it). */
+chfsi_status chfsi_solve(chfsi_ctx ctx, const void* H, int64_t ldh, const void* S, int64_t lds, int64_t nev, int64_t nex,
+                         const void* V_warm, int64_t ldv, int64_t kw, double tol, double* evals, void* X, int64_t ldx,
+                         chfsi_info* info);
+
+/* ---- Step entry points ------------------------------------------------------
+ * Each runs one step of Algorithm 1 on caller device buffers (n = the
+ * context's size), on the context's stream, for testing and composition. */
+
+/* Copy the factors of the last reduction: A (standard form), L (Cholesky
+ * factor, zero upper triangle), Linv = L^{-1}.  Any pointer may be NULL. */
+chfsi_status chfsi_copy_factors(chfsi_ctx ctx, void* A, int64_t lda, void* L, int64_t ldl, void* Linv, int64_t ldi);
+
+/* Chebyshev filter (eq. (3), scaled and shifted): Y (device n x k) is
+ * overwritten with p(A) Y, p(t) = C_m((t - c)/e) / C_m((a0 - c)/e),
+ * c = (a + b)/2, e = (b - a)/2.  Requires b > a, m >= 1. */
+chfsi_status chfsi_filter(chfsi_ctx ctx, const void* A, int64_t lda, void* Y, int64_t ldy, int64_t k, int32_t m, double a,
+                          double b, double a0);
+
+/* Householder QR: Y (device n x k, k <= n) is overwritten with the explicit
+ * orthonormal factor Q; R has a real diagonal with the sign opposite to the
+ * pivot's real part (LAPACK convention). */
+chfsi_status chfsi_qr(chfsi_ctx ctx, void* Y, int64_t ldy, int64_t k);
+
+/* Hermitian eigensolver (Jacobi): G (device k x k, read only) = Z diag(w) Z^H,
+ * w host (k, ascending), Z device k x k. */
+chfsi_status chfsi_eigh(chfsi_ctx ctx, const void* G, int64_t ldg, int64_t k, double* w, void* Z, int64_t ldz);
+
+/* Rayleigh-Ritz on an orthonormal block: G = Y^H A Y, G = Z diag(mu) Z^H,
+ * Y <- Y Z.  Y device n x k, mu host k (ascending). */
+chfsi_status chfsi_rayleigh_ritz(chfsi_ctx ctx, const void* A, int64_t lda, void* Y, int64_t ldy, int64_t k, double* mu);
+
+/* Generalized residual norms rho_j = ||L (A y_j - mu_j y_j)||_2
+ * (= ||H x_j - mu_j S x_j|| for x = L^{-H} y).  A, L, Y device; mu, rho host. */
+chfsi_status chfsi_residuals(chfsi_ctx ctx, const void* A, int64_t lda, const void* L, int64_t ldl, const void* Y,
+                             int64_t ldy, int64_t k, const double* mu, double* rho);
+
+/* Lanczos with full re-orthogonalization on A (device n x n) from the random
+ * vector of (seed, stream_id): out (host, 3) = {smallest Ritz value, largest
+ * Ritz value, largest + ||last residual||} (the upper bound). */
+chfsi_status chfsi_lanczos(chfsi_ctx ctx, const void* A, int64_t lda, int32_t steps, uint64_t seed, uint32_t stream_id,
+                           double* out);
+
+/* Random start block: Y(i, j) (device, n x k) = complex Gaussian number
+ * i + (j + col0) n of Philox4x32-10 stream `stream_id` under `seed`
+ * (counter (idx lo, idx hi, stream_id, 0), key (seed lo, seed hi); two 53-bit
+ * uniforms, Box-Muller). */
+chfsi_status chfsi_random_block(chfsi_ctx ctx, uint64_t seed, uint32_t stream_id, int64_t col0, void* Y, int64_t ldy,
+                                int64_t k);
+
+/* Raw Philox4x32-10 blocks: ctr (device, 4 count u32), key (device, 2 count),
+ * out (device, 4 count). */
+chfsi_status chfsi_philox(chfsi_ctx ctx, const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count);
+
+/* The library's complex GEMM with its three-term epilogue:
+ *   C = alpha op(A) op(B) + beta X + gamma Z,   op in {0: none, 1: conj-transpose}
+ * op(A) M x K, op(B) K x N; X, Z may be NULL; C may alias X or Z.
+ * flags: 1 op(A) lower-triangular, 2 op(A) upper, 4 op(B) lower, 8 op(B)
+ * upper (zeros stored), 16 only tiles meeting the lower triangle of C. */
+chfsi_status chfsi_zgemm(chfsi_ctx ctx, int32_t opA, int32_t opB, int64_t M, int64_t N, int64_t K, double alpha,
+                         const void* A, int64_t lda, const void* B, int64_t ldb, double beta, const void* X, int64_t ldx,
+                         double gamma, const void* Z, int64_t ldz, void* C, int64_t ldc, int32_t flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHFSI_H */

@@ -1,0 +1,346 @@
+"""Python binding of the gfx950 ChFSI library (``libchfsi.so``).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  PyTorch supplies device memory (complex128 CUDA/HIP tensors)
+and the current stream.  The function names mirror the C ABI in
+``include/chfsi.h`` without the ``chfsi_`` prefix.
+
+Layout: the C ABI is column-major.  A torch matrix that is not already
+column-major is converted (``t.mT.contiguous().mT``) before the call, so a
+row-major tensor is never silently read as its (conjugate) transpose.
+Results come back as column-major tensors of the logical shape.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchfsi.so")
+_lib = None
+
+c_i64, c_i32, c_u32, c_u64, c_dbl, c_vp = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
+                                           ctypes.c_double, ctypes.c_void_p)
+
+STATUS = {0: "CHFSI_OK", -1: "CHFSI_EINVAL", -2: "CHFSI_ENOTPD", -3: "CHFSI_ENOCONV", -4: "CHFSI_ENAN",
+          -5: "CHFSI_ENOMEM", -6: "CHFSI_EHIP"}
+
+
+class ChfsiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("degree", c_i32), ("max_iter", c_i32), ("lanczos_steps", c_i32), ("precision", c_i32),
+                ("seed", c_u64), ("profile", c_i32), ("reserved", c_i32 * 7)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", c_i32), ("converged", c_i32), ("warm_start", c_i32), ("filter_launches", c_i32),
+                ("filter_flops", c_dbl), ("filter_kernel_seconds", c_dbl),
+                ("t_reduce", c_dbl), ("t_lanczos", c_dbl), ("t_filter", c_dbl), ("t_qr", c_dbl), ("t_rr", c_dbl),
+                ("t_resid", c_dbl), ("t_total", c_dbl), ("b_upper", c_dbl), ("theta_min", c_dbl), ("h_H", c_dbl),
+                ("a0", c_dbl), ("a", c_dbl), ("max_rel_residual", c_dbl)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def load():
+    """Load libchfsi.so.  Raises if it has not been built: there is no
+    fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1305_5120_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.chfsi_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.chfsi_status_string.restype = ctypes.c_char_p
+    L.chfsi_create.argtypes = [ctypes.POINTER(c_vp), c_i64, ctypes.POINTER(Opts), c_vp]
+    L.chfsi_release.argtypes = [c_vp]
+    L.chfsi_last_error.argtypes = [c_vp]
+    L.chfsi_last_error.restype = ctypes.c_char_p
+    L.chfsi_reset.argtypes = [c_vp]
+    L.chfsi_reduce.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64]
+    L.chfsi_solve.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64, c_dbl, c_vp, c_vp, c_i64,
+                              ctypes.POINTER(Info)]
+    L.chfsi_copy_factors.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64]
+    L.chfsi_filter.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_i32, c_dbl, c_dbl, c_dbl]
+    L.chfsi_qr.argtypes = [c_vp, c_vp, c_i64, c_i64]
+    L.chfsi_eigh.argtypes = [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64]
+    L.chfsi_rayleigh_ritz.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp]
+    L.chfsi_residuals.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp]
+    L.chfsi_lanczos.argtypes = [c_vp, c_vp, c_i64, c_i32, c_u64, c_u32, c_vp]
+    L.chfsi_random_block.argtypes = [c_vp, c_u64, c_u32, c_i64, c_vp, c_i64, c_i64]
+    L.chfsi_philox.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64]
+    L.chfsi_zgemm.argtypes = [c_vp, c_i32, c_i32, c_i64, c_i64, c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_dbl, c_vp,
+                              c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_i32]
+    for name in ("chfsi_create", "chfsi_reset", "chfsi_reduce", "chfsi_solve", "chfsi_copy_factors", "chfsi_filter",
+                 "chfsi_qr", "chfsi_eigh", "chfsi_rayleigh_ritz", "chfsi_residuals", "chfsi_lanczos",
+                 "chfsi_random_block", "chfsi_philox", "chfsi_zgemm"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def default_opts(**kw):
+    o = Opts()
+    load().chfsi_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+# --------------------------------------------------------------------------
+# tensor marshalling
+# --------------------------------------------------------------------------
+
+def _check_dev(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device (cuda/hip) tensor")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128")
+    if t.dim() != 2:
+        raise TypeError(f"{name} must be a matrix")
+
+
+def colmajor(t):
+    """(tensor whose storage is the column-major matrix, leading dimension)."""
+    rows = t.shape[0]
+    if t.stride(0) == 1 and (t.shape[1] <= 1 or t.stride(1) >= max(rows, 1)):
+        return t, max(t.stride(1), rows, 1)
+    c = t.mT.contiguous().mT
+    return c, max(rows, 1)
+
+
+def empty_colmajor(rows, cols, device):
+    import torch
+    return torch.empty((cols, rows), dtype=torch.complex128, device=device).mT
+
+
+def _stream():
+    import torch
+    return c_vp(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """Owns one chfsi_ctx (one problem size n, one stream)."""
+
+    def __init__(self, n, opts=None, **kw):
+        self.lib = load()
+        o = opts if opts is not None else default_opts(**kw)
+        h = c_vp()
+        st = self.lib.chfsi_create(ctypes.byref(h), int(n), ctypes.byref(o), _stream())
+        if st != 0:
+            raise ChfsiError(st, "chfsi_create failed")
+        self.h = h
+        self.n = int(n)
+        self.opts = o
+
+    def _raise(self, st):
+        if st != 0:
+            msg = self.lib.chfsi_last_error(self.h)
+            raise ChfsiError(st, msg.decode() if msg else "")
+
+    def release(self):
+        if getattr(self, "h", None):
+            self.lib.chfsi_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def reset(self):
+        self._raise(self.lib.chfsi_reset(self.h))
+
+
+def create(n, **kw):
+    return Context(n, **kw)
+
+
+def release(ctx):
+    ctx.release()
+
+
+def reset(ctx):
+    ctx.reset()
+
+
+def reduce(ctx, H, S=None):
+    _check_dev(H, "H")
+    Hc, ldh = colmajor(H)
+    if S is not None:
+        _check_dev(S, "S")
+        Sc, lds = colmajor(S)
+        sp = Sc.data_ptr()
+    else:
+        Sc, lds, sp = None, ctx.n, None
+    ctx._raise(ctx.lib.chfsi_reduce(ctx.h, Hc.data_ptr(), ldh, sp, lds))
+
+
+def copy_factors(ctx):
+    """Returns (A, L, Linv) of the last reduction as column-major tensors."""
+    import torch
+    dev = torch.device("cuda")
+    A = empty_colmajor(ctx.n, ctx.n, dev)
+    L = empty_colmajor(ctx.n, ctx.n, dev)
+    Li = empty_colmajor(ctx.n, ctx.n, dev)
+    ctx._raise(ctx.lib.chfsi_copy_factors(ctx.h, A.data_ptr(), ctx.n, L.data_ptr(), ctx.n, Li.data_ptr(), ctx.n))
+    return A, L, Li
+
+
+def solve(ctx, H, S, nev, nex, V_warm=None, tol=1e-10, want_vectors=True, raise_on_noconv=True):
+    """Algorithm 1 on (H, S).  Returns (evals numpy (nev,), X tensor n x nev
+    or None, info dict, status)."""
+    _check_dev(H, "H")
+    Hc, ldh = colmajor(H)
+    if S is not None:
+        _check_dev(S, "S")
+        Sc, lds = colmajor(S)
+        sp = Sc.data_ptr()
+    else:
+        Sc, lds, sp = None, ctx.n, None
+    if V_warm is not None:
+        _check_dev(V_warm, "V_warm")
+        Vc, ldv = colmajor(V_warm)
+        vp, kw = Vc.data_ptr(), V_warm.shape[1]
+    else:
+        Vc, ldv, vp, kw = None, ctx.n, None, 0
+    evals = np.zeros(nev)
+    X = empty_colmajor(ctx.n, nev, H.device) if want_vectors else None
+    info = Info()
+    st = ctx.lib.chfsi_solve(ctx.h, Hc.data_ptr(), ldh, sp, lds, int(nev), int(nex), vp, ldv, int(kw), float(tol),
+                             evals.ctypes.data_as(c_vp), X.data_ptr() if X is not None else None, ctx.n,
+                             ctypes.byref(info))
+    if st != 0 and (raise_on_noconv or st != -3):
+        ctx._raise(st)
+    return evals, X, info.as_dict(), st
+
+
+def filter(ctx, A, Y, m, a, b, a0):
+    """Y <- p(A) Y (in place on Y, a complex128 device matrix)."""
+    _check_dev(A, "A")
+    _check_dev(Y, "Y")
+    Ac, lda = colmajor(A)
+    Yc, ldy = colmajor(Y)
+    ctx._raise(ctx.lib.chfsi_filter(ctx.h, Ac.data_ptr(), lda, Yc.data_ptr(), ldy, Y.shape[1], int(m), float(a),
+                                    float(b), float(a0)))
+    if Yc.data_ptr() != Y.data_ptr():
+        Y.copy_(Yc)
+    return Y
+
+
+def qr(ctx, Y):
+    """Y <- Q (Householder), in place."""
+    _check_dev(Y, "Y")
+    Yc, ldy = colmajor(Y)
+    ctx._raise(ctx.lib.chfsi_qr(ctx.h, Yc.data_ptr(), ldy, Y.shape[1]))
+    if Yc.data_ptr() != Y.data_ptr():
+        Y.copy_(Yc)
+    return Y
+
+
+def eigh(ctx, G):
+    """(w numpy ascending, Z tensor) of a Hermitian device matrix."""
+    _check_dev(G, "G")
+    Gc, ldg = colmajor(G)
+    k = G.shape[0]
+    w = np.zeros(k)
+    Z = empty_colmajor(k, k, G.device)
+    ctx._raise(ctx.lib.chfsi_eigh(ctx.h, Gc.data_ptr(), ldg, k, w.ctypes.data_as(c_vp), Z.data_ptr(), k))
+    return w, Z
+
+
+def rayleigh_ritz(ctx, A, Y):
+    """(mu numpy ascending, Y <- Y Z in place)."""
+    _check_dev(A, "A")
+    _check_dev(Y, "Y")
+    Ac, lda = colmajor(A)
+    Yc, ldy = colmajor(Y)
+    k = Y.shape[1]
+    mu = np.zeros(k)
+    ctx._raise(ctx.lib.chfsi_rayleigh_ritz(ctx.h, Ac.data_ptr(), lda, Yc.data_ptr(), ldy, k, mu.ctypes.data_as(c_vp)))
+    if Yc.data_ptr() != Y.data_ptr():
+        Y.copy_(Yc)
+    return mu, Y
+
+
+def residuals(ctx, A, L, Y, mu):
+    _check_dev(A, "A")
+    _check_dev(L, "L")
+    _check_dev(Y, "Y")
+    Ac, lda = colmajor(A)
+    Lc, ldl = colmajor(L)
+    Yc, ldy = colmajor(Y)
+    k = Y.shape[1]
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    rho = np.zeros(k)
+    ctx._raise(ctx.lib.chfsi_residuals(ctx.h, Ac.data_ptr(), lda, Lc.data_ptr(), ldl, Yc.data_ptr(), ldy, k,
+                                       mu.ctypes.data_as(c_vp), rho.ctypes.data_as(c_vp)))
+    return rho
+
+
+def lanczos(ctx, A, steps, seed, stream_id):
+    _check_dev(A, "A")
+    Ac, lda = colmajor(A)
+    out = np.zeros(3)
+    ctx._raise(ctx.lib.chfsi_lanczos(ctx.h, Ac.data_ptr(), lda, int(steps), int(seed), int(stream_id),
+                                     out.ctypes.data_as(c_vp)))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def random_block(ctx, seed, stream_id, k, col0=0):
+    import torch
+    Y = empty_colmajor(ctx.n, k, torch.device("cuda"))
+    ctx._raise(ctx.lib.chfsi_random_block(ctx.h, int(seed), int(stream_id), int(col0), Y.data_ptr(), ctx.n, int(k)))
+    return Y
+
+
+def philox(ctx, ctr, key):
+    """Raw Philox4x32-10 blocks for rows of ctr (count x 4) and key (count x 2)."""
+    import torch
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    cnt = ctr.shape[0]
+    dc = torch.from_numpy(ctr.view(np.int32).copy()).cuda()
+    dk = torch.from_numpy(key.view(np.int32).copy()).cuda()
+    do = torch.zeros((cnt, 4), dtype=torch.int32, device="cuda")
+    ctx._raise(ctx.lib.chfsi_philox(ctx.h, dc.data_ptr(), dk.data_ptr(), do.data_ptr(), cnt))
+    return do.cpu().numpy().view(np.uint32)
+
+
+def zgemm(ctx, opA, opB, A, B, alpha=1.0, beta=0.0, X=None, gamma=0.0, Z=None, C=None, flags=0, M=None, N=None, K=None):
+    """C = alpha op(A) op(B) + beta X + gamma Z with the library's kernel."""
+    _check_dev(A, "A")
+    _check_dev(B, "B")
+    Ac, lda = colmajor(A)
+    Bc, ldb = colmajor(B)
+    M = M if M is not None else (A.shape[0] if opA == 0 else A.shape[1])
+    K = K if K is not None else (A.shape[1] if opA == 0 else A.shape[0])
+    N = N if N is not None else (B.shape[1] if opB == 0 else B.shape[0])
+    if C is None:
+        C = empty_colmajor(M, N, A.device)
+    Cc, ldc = colmajor(C)
+    xp = zp = None
+    ldx = ldz = M
+    if X is not None:
+        Xc, ldx = colmajor(X)
+        xp = Xc.data_ptr()
+    if Z is not None:
+        Zc, ldz = colmajor(Z)
+        zp = Zc.data_ptr()
+    ctx._raise(ctx.lib.chfsi_zgemm(ctx.h, int(opA), int(opB), int(M), int(N), int(K), float(alpha), Ac.data_ptr(),
+                                   lda, Bc.data_ptr(), ldb, float(beta), xp, ldx, float(gamma), zp, ldz,
+                                   Cc.data_ptr(), ldc, int(flags)))
+    if Cc.data_ptr() != C.data_ptr():
+        C.copy_(Cc)
+    return C

@@ -1,0 +1,65 @@
+// Internal interface of the complex GEMM kernels (FP64 and FP32).
+#pragma once
+
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace chfsi {
+
+enum { OP_N = 0, OP_C = 1 };
+
+// Structure flags.  TRI_*: op(A) / op(B) is triangular with explicit zeros
+// stored in the other triangle, so each tile may skip the K range that only
+// meets zeros.  OUT_LOWER: only tiles touching the lower triangle of the
+// output are computed (the rest of the output is left untouched).
+enum {
+  GEMM_TRI_A_LOWER = 1,  // op(A)[m,k] = 0 for k > m
+  GEMM_TRI_A_UPPER = 2,  // op(A)[m,k] = 0 for k < m
+  GEMM_TRI_B_LOWER = 4,  // op(B)[k,n] = 0 for k < n
+  GEMM_TRI_B_UPPER = 8,  // op(B)[k,n] = 0 for k > n
+  GEMM_OUT_LOWER = 16,
+};
+
+// out = alpha * op(A) op(B) + beta * X + gamma * Z, op(A) M x K, op(B) K x N.
+// X / Z may be null; out may alias X or Z (each element is read and written
+// by the same thread) but must not alias A or B.
+struct GemmOp {
+  int opA = OP_N, opB = OP_N;
+  int64_t M = 0, N = 0, K = 0;
+  const zc* A = nullptr; int64_t lda = 0, sA = 0;
+  const zc* B = nullptr; int64_t ldb = 0, sB = 0;
+  zc* C = nullptr; int64_t ldc = 0, sC = 0;
+  const zc* X = nullptr; int64_t ldx = 0, sX = 0;
+  const zc* Z = nullptr; int64_t ldz = 0, sZ = 0;
+  double alpha = 1.0, beta = 0.0, gamma = 0.0;
+  int flags = 0;
+  int batch = 1;            // strided batch count (s* are the strides)
+  bool allow_splitk = true;
+  bool filter_step = false;  // launch under the Chebyshev-step kernel symbol
+};
+
+// Scratch for split-K partial tiles.
+struct GemmWork {
+  zc* P = nullptr;
+  size_t P_elems = 0;
+};
+
+struct ZGemmParams {
+  int64_t M, N, K;
+  const zc* A; int64_t lda, sA;
+  const zc* B; int64_t ldb, sB;
+  zc* C; int64_t ldc, sC;
+  const zc* X; int64_t ldx, sX;
+  const zc* Z; int64_t ldz, sZ;
+  double alpha, beta, gamma;
+  int flags;
+  int splitk;
+  int64_t kchunk;
+  zc* P;
+  int tiles_m, tiles_n;
+};
+
+void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st);
+
+}  // namespace chfsi

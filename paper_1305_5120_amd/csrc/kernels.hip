@@ -1,0 +1,886 @@
+// Non-GEMM kernels of the ChFSI library (gfx950): start vectors, Cholesky
+// diagonal blocks, Householder column steps, the Jacobi eigensolver of the
+// Rayleigh-Ritz step, residual norms and the Lanczos pieces.  All of these are
+// latency- or bandwidth-bound; the dense products live in zgemm.hip.
+#include "kernels.hpp"
+
+namespace chfsi {
+
+namespace {
+
+constexpr int NT = 256;
+
+inline dim3 grid1(int64_t total, int nt = NT) { return dim3((unsigned)std::max<int64_t>(1, cdiv(total, nt))); }
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC 2011) and Box-Muller Gaussians
+// --------------------------------------------------------------------------
+__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t y0 = hi1 ^ c[1] ^ k0, y2 = hi0 ^ c[3] ^ k1;
+    c[0] = y0; c[1] = lo1; c[2] = y2; c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__global__ void k_philox_raw(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  uint32_t c[4] = {ctr[4 * e], ctr[4 * e + 1], ctr[4 * e + 2], ctr[4 * e + 3]};
+  philox10(c, key[2 * e], key[2 * e + 1]);
+  for (int i = 0; i < 4; i++) out[4 * e + i] = c[i];
+}
+
+__global__ void k_random_block(uint64_t seed, uint32_t stream, int64_t n, int64_t k, int64_t col0, zc* Y, int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  const int64_t i = e % n, j = e / n;
+  const uint64_t idx = (uint64_t)i + (uint64_t)(j + col0) * (uint64_t)n;
+  uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), stream, 0u};
+  philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t q1 = (((uint64_t)c[0] << 32) | c[1]) >> 11;
+  const uint64_t q2 = (((uint64_t)c[2] << 32) | c[3]) >> 11;
+  const double u1 = ((double)q1 + 0.5) * 0x1p-53;
+  const double u2 = ((double)q2 + 0.5) * 0x1p-53;
+  const double r = sqrt(-2.0 * log(u1));
+  const double t = 6.283185307179586476925286766559 * u2;
+  Y[i + j * ldy] = zmk(r * cos(t), r * sin(t));
+}
+
+// --------------------------------------------------------------------------
+// elementwise
+// --------------------------------------------------------------------------
+__global__ void k_fill_i32(int* p, int64_t count, int v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) p[e] = v;
+}
+
+__global__ void k_copy2d(const zc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  const int64_t i = e % m, j = e / m;
+  dst[i + j * ldd] = src[i + j * lds];
+}
+
+__global__ void k_set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  const int64_t i = e % m, j = e / m;
+  Y[i + j * ldy] = zmk(i == j ? 1.0 : 0.0, 0.0);
+}
+
+__global__ void k_zero_strict_upper(zc* A, int64_t lda, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e % n, j = e / n;
+  if (i < j) A[i + j * lda] = zmk(0.0, 0.0);
+}
+
+__global__ void k_hermitize(zc* A, int64_t lda, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e % n, j = e / n;
+  if (i < j) return;
+  if (i == j) {
+    A[i + i * lda].y = 0.0;
+    return;
+  }
+  const zc x = A[i + j * lda], y = A[j + i * lda];
+  const zc m = zmk(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+  A[i + j * lda] = m;
+  A[j + i * lda] = zconj(m);
+}
+
+__global__ void k_residual(const zc* W, int64_t ldw, const zc* Y, int64_t ldy, const double* mu, zc* R, int64_t ldr, int64_t n,
+                           int64_t k) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  const int64_t i = e % n, j = e / n;
+  R[i + j * ldr] = zsub(W[i + j * ldw], zscale(mu[j], Y[i + j * ldy]));
+}
+
+__global__ void k_column_norms(const zc* R, int64_t ldr, int64_t n, double* out) {
+  __shared__ double red[16];
+  const int64_t j = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += zabs2(R[i + j * ldr]);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[j] = sqrt(s);
+}
+
+__global__ void k_nonfinite(const zc* A, int64_t lda, int64_t n, int64_t k, int* flag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  const zc v = A[(e % n) + (e / n) * lda];
+  if (!isfinite(v.x) || !isfinite(v.y)) *flag = 1;
+}
+
+// --------------------------------------------------------------------------
+// Cholesky diagonal block: unblocked right-looking factorization in LDS and
+// the inverse of the factor (forward substitution, one column per thread).
+// --------------------------------------------------------------------------
+constexpr int CNB = CHOL_NB;
+constexpr int CLD = CNB + 1;
+
+__global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi,
+                                                    int64_t j0, int nb, int* info) {
+  extern __shared__ zc smem[];
+  zc* Ls = smem;             // [CNB][CLD] row-major: Ls[i * CLD + c]
+  zc* Xs = smem + CNB * CLD;  // inverse
+  __shared__ int failed;
+  const int tid = threadIdx.x;
+  if (tid == 0) failed = -1;
+  for (int e = tid; e < nb * nb; e += blockDim.x) {
+    const int i = e % nb, c = e / nb;
+    Ls[i * CLD + c] = (i >= c) ? W[(j0 + i) + (j0 + c) * ldw] : zmk(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; j++) {
+    if (tid == 0) {
+      const double d = Ls[j * CLD + j].x;
+      if (!(d > 0.0)) failed = j;
+      else Ls[j * CLD + j] = zmk(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    if (failed >= 0) break;
+    const double inv = 1.0 / Ls[j * CLD + j].x;
+    for (int i = j + 1 + tid; i < nb; i += blockDim.x) Ls[i * CLD + j] = zscale(inv, Ls[i * CLD + j]);
+    __syncthreads();
+    const int m = nb - j - 1;  // trailing size
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      const int i = j + 1 + e % m, c = j + 1 + e / m;
+      if (c <= i) Ls[i * CLD + c] = zsub(Ls[i * CLD + c], zmul(Ls[i * CLD + j], zconj(Ls[c * CLD + j])));
+    }
+    __syncthreads();
+  }
+  if (failed >= 0) {
+    if (tid == 0) atomicMin(info, (int)(j0 + failed + 1));
+    return;
+  }
+  // inverse: column c solved by thread c
+  if (tid < nb) {
+    const int c = tid;
+    for (int i = 0; i < nb; i++) {
+      zc x;
+      if (i < c) x = zmk(0.0, 0.0);
+      else if (i == c) x = zmk(1.0 / Ls[c * CLD + c].x, 0.0);
+      else {
+        zc s = zmk(0.0, 0.0);
+        for (int q = c; q < i; q++) s = zadd(s, zmul(Ls[i * CLD + q], Xs[q * CLD + c]));
+        x = zscale(-1.0 / Ls[i * CLD + i].x, s);
+      }
+      Xs[i * CLD + c] = x;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nb * nb; e += blockDim.x) {
+    const int i = e % nb, c = e / nb;
+    L[(j0 + i) + (j0 + c) * ldl] = (i >= c) ? Ls[i * CLD + c] : zmk(0.0, 0.0);
+    Linv[(j0 + i) + (j0 + c) * ldi] = (i >= c) ? Xs[i * CLD + c] : zmk(0.0, 0.0);
+  }
+}
+
+// --------------------------------------------------------------------------
+// Householder panel.  Reflector j: H = I - tau v v^H with v(j) = 1 and
+// H^H x = beta e_j, beta real with the sign opposite to Re x(j).  Each
+// workgroup owns a fixed block of rows; a launch applies reflector j to the
+// panel and, from the updated rows, forms the partial inner products that
+// the next column's reflector needs: one launch per column.
+//   partial sums  s[c] = sum_{i > j} conj(F(i, j)) F(i, c),  c in [j, j1)
+//   top row       F(j, c)
+// --------------------------------------------------------------------------
+constexpr int HNB = HH_NB;
+
+// Block-reduce acc[0..HNB) (only entries [c0, cnt) meaningful) into dst.
+__device__ inline void reduce_partials(zc (&acc)[HNB], int c0, int cnt, zc* dst, double* red /* 4*HNB*2 */) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < HNB; c++) {
+    if (c >= c0 && c < cnt) {
+      const double re = wave_sum(acc[c].x), im = wave_sum(acc[c].y);
+      if (lane == 0) {
+        red[(w * HNB + c) * 2] = re;
+        red[(w * HNB + c) * 2 + 1] = im;
+      }
+    }
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < HNB) {
+    zc s = zmk(0.0, 0.0);
+    if (c >= c0 && c < cnt)
+      for (int q = 0; q < (int)(blockDim.x >> 6); q++) s = zadd(s, zmk(red[(q * HNB + c) * 2], red[(q * HNB + c) * 2 + 1]));
+    dst[c] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_hh_first(HHPanel p) {
+  __shared__ double red[4 * HNB * 2];
+  const int64_t j = p.j0;
+  const int cnt = (int)(p.j1 - p.j0);
+  const int64_t rbeg = p.j0 + (int64_t)blockIdx.x * p.rows_per_blk;
+  const int64_t rend = min(p.n, rbeg + p.rows_per_blk);
+  zc acc[HNB];
+#pragma unroll
+  for (int c = 0; c < HNB; c++) acc[c] = zmk(0.0, 0.0);
+  for (int64_t i = rbeg + threadIdx.x; i < rend; i += blockDim.x) {
+    const zc* row = p.F + i;
+    if (i == j) {
+#pragma unroll
+      for (int c = 0; c < HNB; c++)
+        if (c < cnt) p.top[c] = row[(p.j0 + c) * p.ldf];
+    } else if (i > j) {
+      const zc x = row[j * p.ldf];
+#pragma unroll
+      for (int c = 0; c < HNB; c++)
+        if (c < cnt) acc[c] = zadd(acc[c], zcmul(x, row[(p.j0 + c) * p.ldf]));
+    }
+  }
+  reduce_partials(acc, 0, cnt, p.part + (int64_t)blockIdx.x * HNB, red);
+}
+
+__global__ void __launch_bounds__(256) k_hh_column(HHPanel p, int64_t j) {
+  __shared__ double red[4 * HNB * 2];
+  __shared__ zc s_tot[HNB], f[HNB];
+  __shared__ double sh_beta;
+  __shared__ zc sh_scal;
+  __shared__ int sh_identity;
+  const int cnt = (int)(p.j1 - p.j0);
+  const int jl = (int)(j - p.j0);
+  const int cur = jl & 1, nxt = cur ^ 1;
+  const zc* part_cur = p.part + (int64_t)cur * p.nblk * HNB;
+  zc* part_nxt = p.part + (int64_t)nxt * p.nblk * HNB;
+  const zc* top_cur = p.top + cur * HNB;
+  zc* top_nxt = p.top + nxt * HNB;
+  const int tid = threadIdx.x;
+  if (tid >= jl && tid < cnt) {
+    zc s = zmk(0.0, 0.0);
+    for (int b = 0; b < p.nblk; b++) s = zadd(s, part_cur[(int64_t)b * HNB + tid]);
+    s_tot[tid] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const zc alpha = top_cur[jl];
+    const double xnorm2 = s_tot[jl].x;
+    if (xnorm2 == 0.0 && alpha.y == 0.0) {
+      sh_identity = 1;
+      sh_beta = alpha.x;
+      sh_scal = zmk(0.0, 0.0);
+      if (blockIdx.x == 0) p.tau[j] = zmk(0.0, 0.0);
+      for (int c = jl + 1; c < cnt; c++) f[c] = zmk(0.0, 0.0);
+    } else {
+      sh_identity = 0;
+      const double nrm = sqrt(zabs2(alpha) + xnorm2);
+      const double beta = alpha.x >= 0.0 ? -nrm : nrm;
+      const zc tau = zmk((beta - alpha.x) / beta, -alpha.y / beta);
+      const zc den = zmk(alpha.x - beta, alpha.y);
+      const double dd = zabs2(den);
+      const zc scal = zmk(den.x / dd, -den.y / dd);  // 1 / (alpha - beta)
+      sh_beta = beta;
+      sh_scal = scal;
+      if (blockIdx.x == 0) p.tau[j] = tau;
+      for (int c = jl + 1; c < cnt; c++) {
+        // v^H y_c = y_jc + conj(scal) s[c]
+        const zc w = zadd(top_cur[c], zcmul(scal, s_tot[c]));
+        f[c] = zcmul(tau, w);  // conj(tau) w
+      }
+    }
+  }
+  __syncthreads();
+  const bool ident = sh_identity != 0;
+  const double beta = sh_beta;
+  const zc scal = sh_scal;
+  const int64_t rbeg = p.j0 + (int64_t)blockIdx.x * p.rows_per_blk;
+  const int64_t rend = min(p.n, rbeg + p.rows_per_blk);
+  zc acc[HNB];
+#pragma unroll
+  for (int c = 0; c < HNB; c++) acc[c] = zmk(0.0, 0.0);
+  for (int64_t i = rbeg + tid; i < rend; i += blockDim.x) {
+    if (i < j) continue;
+    zc* row = p.F + i;
+    zc vals[HNB];
+#pragma unroll
+    for (int c = 0; c < HNB; c++)
+      if (c >= jl && c < cnt) vals[c] = row[(p.j0 + c) * p.ldf];
+    // (register arrays are only indexed with unrolled constants)
+    if (!ident) {
+      zc xj = zmk(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < HNB; c++)
+        if (c == jl) xj = vals[c];
+      const zc v = (i == j) ? zmk(1.0, 0.0) : zmul(xj, scal);
+      const zc vj = (i == j) ? zmk(beta, 0.0) : v;
+#pragma unroll
+      for (int c = 0; c < HNB; c++) {
+        if (c == jl) vals[c] = vj;
+        else if (c > jl && c < cnt) vals[c] = zsub(vals[c], zmul(v, f[c]));
+      }
+#pragma unroll
+      for (int c = 0; c < HNB; c++)
+        if (c >= jl && c < cnt) row[(p.j0 + c) * p.ldf] = vals[c];
+    }
+    if (jl + 1 < cnt) {
+      if (i == j + 1) {
+#pragma unroll
+        for (int c = 0; c < HNB; c++)
+          if (c > jl && c < cnt) top_nxt[c] = vals[c];
+      } else if (i > j + 1) {
+        zc x = zmk(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < HNB; c++)
+          if (c == jl + 1) x = vals[c];
+#pragma unroll
+        for (int c = 0; c < HNB; c++)
+          if (c > jl && c < cnt) acc[c] = zadd(acc[c], zcmul(x, vals[c]));
+      }
+    }
+  }
+  if (jl + 1 < cnt) reduce_partials(acc, jl + 1, cnt, part_nxt + (int64_t)blockIdx.x * HNB, red);
+}
+
+__global__ void k_hh_extract_v(const zc* F, int64_t ldf, int64_t n, int64_t j0, int64_t j1, zc* Vp, int64_t ldv) {
+  const int64_t cnt = j1 - j0, rows = n - j0;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cnt) return;
+  const int64_t r = e % rows, c = e / rows;
+  const int64_t i = j0 + r, col = j0 + c;
+  zc v;
+  if (i == col) v = zmk(1.0, 0.0);
+  else if (i < col) v = zmk(0.0, 0.0);
+  else v = F[i + col * ldf];
+  Vp[r + c * ldv] = v;
+}
+
+__global__ void k_hh_build_t(const zc* gram, const zc* tau, int64_t cnt, zc* T) {
+  // gram: cnt x cnt (ld cnt) = V^H V;  T: HNB x HNB column-major (ld HNB), upper
+  __shared__ zc Ts[HNB][HNB + 1];
+  const int r = threadIdx.x;
+  for (int e = r; e < HNB * HNB; e += blockDim.x) Ts[e % HNB][e / HNB] = zmk(0.0, 0.0);
+  __syncthreads();
+  for (int i = 0; i < (int)cnt; i++) {
+    const zc ti = tau[i];
+    zc val = zmk(0.0, 0.0);
+    if (r < i) {
+      zc s = zmk(0.0, 0.0);
+      for (int q = r; q < i; q++) s = zadd(s, zmul(Ts[r][q], gram[q + (int64_t)i * cnt]));
+      val = zmul(zmk(-ti.x, -ti.y), s);
+    }
+    __syncthreads();
+    if (r < i) Ts[r][i] = val;
+    if (r == i) Ts[i][i] = ti;
+    __syncthreads();
+  }
+  for (int e = r; e < HNB * HNB; e += blockDim.x) T[e] = Ts[e % HNB][e / HNB];
+}
+
+// --------------------------------------------------------------------------
+// Jacobi eigensolver (Hermitian).  Parallel (round-robin) ordering: in each
+// round the index pairs are disjoint, so all rotations of a round apply at
+// once, G <- J^H G J, Z <- Z J.  Rotation of pair (p, q), p < q, with
+// g = G(p, q) = |g| u: real symmetric Jacobi on [[G_pp, |g|], [|g|, G_qq]],
+// t = sign(tau)/(|tau| + sqrt(1 + tau^2)), tau = (G_qq - G_pp)/(2|g|),
+// c = 1/sqrt(1 + t^2), s = t c, and J = [[u c, u s], [-s, c]] on columns p, q.
+// A rotation is skipped when |g|^2 <= 1e-36 ||G||_F^2.
+// --------------------------------------------------------------------------
+struct Rot {
+  double c, s, ur, ui, tg;  // tg = t |g|
+  int active;
+};
+
+__device__ inline void round_pair(int64_t K2, int64_t round, int64_t t, int64_t& p, int64_t& q) {
+  const int64_t a = t, b = K2 - 1 - t;
+  auto player = [&](int64_t pos) -> int64_t { return pos == 0 ? 0 : ((pos - 1 + round) % (K2 - 1)) + 1; };
+  const int64_t x = player(a), y = player(b);
+  p = x < y ? x : y;
+  q = x < y ? y : x;
+}
+
+__device__ inline Rot make_rot(zc gpp, zc gqq, zc gpq, double skip2) {
+  Rot R;
+  R.c = 1.0; R.s = 0.0; R.ur = 1.0; R.ui = 0.0; R.tg = 0.0; R.active = 0;
+  const double ag2 = zabs2(gpq);
+  if (ag2 <= skip2 || ag2 == 0.0) return R;
+  const double ag = sqrt(ag2);
+  const double tau = (gqq.x - gpp.x) / (2.0 * ag);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  R.c = 1.0 / sqrt(1.0 + t * t);
+  R.s = t * R.c;
+  R.ur = gpq.x / ag;
+  R.ui = gpq.y / ag;
+  R.tg = t * ag;
+  R.active = 1;
+  return R;
+}
+
+// 2x2 block update  B <- Jr^H B Js  where J = [[u c, u s], [-s, c]]
+__device__ inline void rot_block(const Rot& r, const Rot& s, zc& b00, zc& b01, zc& b10, zc& b11) {
+  const zc us = zmk(s.ur, s.ui), ur = zmk(r.ur, r.ui);
+  const zc s00 = zscale(s.c, us), s01 = zscale(s.s, us);
+  const double s10 = -s.s, s11 = s.c;
+  // B Js
+  const zc c00 = zadd(zmul(b00, s00), zscale(s10, b01));
+  const zc c01 = zadd(zmul(b00, s01), zscale(s11, b01));
+  const zc c10 = zadd(zmul(b10, s00), zscale(s10, b11));
+  const zc c11 = zadd(zmul(b10, s01), zscale(s11, b11));
+  const zc r00 = zscale(r.c, ur), r01 = zscale(r.s, ur);
+  const double r10 = -r.s, r11 = r.c;
+  // Jr^H (B Js): row0 = conj(r00) row0 + r10 row1 ; row1 = conj(r01) row0 + r11 row1
+  b00 = zadd(zcmul(r00, c00), zscale(r10, c10));
+  b01 = zadd(zcmul(r00, c01), zscale(r10, c11));
+  b10 = zadd(zcmul(r01, c00), zscale(r11, c10));
+  b11 = zadd(zcmul(r01, c01), zscale(r11, c11));
+}
+
+__device__ inline void rot_cols(const Rot& s, zc& zp, zc& zq) {
+  const zc us = zmk(s.ur, s.ui);
+  const zc s00 = zscale(s.c, us), s01 = zscale(s.s, us);
+  const zc np = zadd(zmul(zp, s00), zscale(-s.s, zq));
+  const zc nq = zadd(zmul(zp, s01), zscale(s.c, zq));
+  zp = np;
+  zq = nq;
+}
+
+__global__ void __launch_bounds__(1024) k_jacobi_small(const zc* G, int64_t ldg, int k, double* w, zc* Zout, int64_t ldz,
+                                                      zc* Z, int* sweeps_out) {
+  extern __shared__ zc Gs[];  // k x k, column-major ld k
+  __shared__ double red[16];
+  __shared__ Rot prm[JACOBI_LDS_MAX / 2 + 1];
+  __shared__ int pidx[JACOBI_LDS_MAX / 2 + 1], qidx[JACOBI_LDS_MAX / 2 + 1];
+  __shared__ int rotated;
+  const int tid = threadIdx.x;
+  const int K2 = k + (k & 1), half = K2 / 2;
+  double f = 0.0;
+  for (int e = tid; e < k * k; e += blockDim.x) {
+    const int i = e % k, j = e / k;
+    zc v = G[i + (int64_t)j * ldg];
+    if (i == j) v.y = 0.0;
+    Gs[e] = v;
+    Z[e] = zmk(i == j ? 1.0 : 0.0, 0.0);
+    f += zabs2(v);
+  }
+  const double fro2 = block_sum(f, red);
+  const double skip2 = 1e-36 * fro2;
+  int sweep = 0;
+  for (; sweep < 100; sweep++) {
+    double o = 0.0;
+    for (int e = tid; e < k * k; e += blockDim.x)
+      if (e % k != e / k) o += zabs2(Gs[e]);
+    const double off2 = block_sum(o, red);
+    if (off2 <= 1e-32 * fro2 || off2 == 0.0) break;
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < K2 - 1; r++) {
+      if (tid < half) {
+        int64_t p, q;
+        round_pair(K2, r, tid, p, q);
+        pidx[tid] = (int)p;
+        qidx[tid] = (int)q;
+        Rot R;
+        if (q >= k) {
+          R.c = 1.0; R.s = 0.0; R.ur = 1.0; R.ui = 0.0; R.tg = 0.0; R.active = 0;
+        } else {
+          R = make_rot(Gs[p + p * k], Gs[q + q * k], Gs[p + q * k], skip2);
+          if (R.active) rotated = 1;
+        }
+        prm[tid] = R;
+      }
+      __syncthreads();
+      for (int e = tid; e < half * half; e += blockDim.x) {
+        const int rt = e % half, st = e / half;
+        const Rot& Rr = prm[rt];
+        const Rot& Rs = prm[st];
+        if (!Rr.active && !Rs.active) continue;
+        const int pr = pidx[rt], qr = qidx[rt], ps = pidx[st], qs = qidx[st];
+        const bool qrv = qr < k, qsv = qs < k;
+        zc b00 = Gs[pr + ps * k];
+        zc b01 = qsv ? Gs[pr + qs * k] : zmk(0.0, 0.0);
+        zc b10 = qrv ? Gs[qr + ps * k] : zmk(0.0, 0.0);
+        zc b11 = (qrv && qsv) ? Gs[qr + qs * k] : zmk(0.0, 0.0);
+        if (rt == st) {
+          const double app = b00.x, aqq = b11.x;
+          b00 = zmk(app - Rr.tg, 0.0);
+          b11 = zmk(aqq + Rr.tg, 0.0);
+          b01 = zmk(0.0, 0.0);
+          b10 = zmk(0.0, 0.0);
+        } else {
+          rot_block(Rr, Rs, b00, b01, b10, b11);
+        }
+        Gs[pr + ps * k] = b00;
+        if (qsv) Gs[pr + qs * k] = b01;
+        if (qrv) Gs[qr + ps * k] = b10;
+        if (qrv && qsv) Gs[qr + qs * k] = b11;
+      }
+      for (int e = tid; e < k * half; e += blockDim.x) {
+        const int i = e % k, st = e / k;
+        const Rot& Rs = prm[st];
+        if (!Rs.active) continue;
+        const int ps = pidx[st], qs = qidx[st];
+        zc zp = Z[i + ps * k], zq = Z[i + qs * k];
+        rot_cols(Rs, zp, zq);
+        Z[i + ps * k] = zp;
+        Z[i + qs * k] = zq;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+  }
+  // stable ascending sort of the diagonal, columns of Z permuted alike
+  for (int i = tid; i < k; i += blockDim.x) {
+    const double di = Gs[i + i * k].x;
+    int rank = 0;
+    for (int j = 0; j < k; j++) {
+      const double dj = Gs[j + j * k].x;
+      if (dj < di || (dj == di && j < i)) rank++;
+    }
+    w[rank] = di;
+    for (int r = 0; r < k; r++) Zout[r + (int64_t)rank * ldz] = Z[r + i * k];
+  }
+  if (tid == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+__global__ void k_jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int64_t i = e % k, j = e / k;
+  zc v = G[i + j * ldg];
+  if (i == j) v.y = 0.0;
+  G0[e] = v;
+  Z0[e] = zmk(i == j ? 1.0 : 0.0, 0.0);
+}
+
+__global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
+                               int* rotated) {
+  const int64_t K2 = k + (k & 1), half = K2 / 2;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double skip2 = 1e-36 * fro2[0];
+  auto rot_of = [&](int64_t t, int64_t& p, int64_t& q) -> Rot {
+    round_pair(K2, round, t, p, q);
+    if (q >= k) {
+      Rot R;
+      R.c = 1.0; R.s = 0.0; R.ur = 1.0; R.ui = 0.0; R.tg = 0.0; R.active = 0;
+      return R;
+    }
+    return make_rot(Gin[p + p * k], Gin[q + q * k], Gin[p + q * k], skip2);
+  };
+  if (e < half * half) {
+    const int64_t rt = e % half, st = e / half;
+    int64_t pr, qr, ps, qs;
+    const Rot Rr = rot_of(rt, pr, qr);
+    const Rot Rs = rot_of(st, ps, qs);
+    const bool qrv = qr < k, qsv = qs < k;
+    zc b00 = Gin[pr + ps * k];
+    zc b01 = qsv ? Gin[pr + qs * k] : zmk(0.0, 0.0);
+    zc b10 = qrv ? Gin[qr + ps * k] : zmk(0.0, 0.0);
+    zc b11 = (qrv && qsv) ? Gin[qr + qs * k] : zmk(0.0, 0.0);
+    if (Rr.active || Rs.active) {
+      if (rt == st) {
+        const double app = b00.x, aqq = b11.x;
+        b00 = zmk(app - Rr.tg, 0.0);
+        b11 = zmk(aqq + Rr.tg, 0.0);
+        b01 = zmk(0.0, 0.0);
+        b10 = zmk(0.0, 0.0);
+        *rotated = 1;
+      } else {
+        rot_block(Rr, Rs, b00, b01, b10, b11);
+      }
+    }
+    Gout[pr + ps * k] = b00;
+    if (qsv) Gout[pr + qs * k] = b01;
+    if (qrv) Gout[qr + ps * k] = b10;
+    if (qrv && qsv) Gout[qr + qs * k] = b11;
+    return;
+  }
+  const int64_t e2 = e - half * half;
+  if (e2 >= k * half) return;
+  const int64_t i = e2 % k, st = e2 / k;
+  int64_t ps, qs;
+  const Rot Rs = rot_of(st, ps, qs);
+  zc zp = Zin[i + ps * k];
+  zc zq = qs < k ? Zin[i + qs * k] : zmk(0.0, 0.0);
+  if (Rs.active) rot_cols(Rs, zp, zq);
+  Zout[i + ps * k] = zp;
+  if (qs < k) Zout[i + qs * k] = zq;
+}
+
+__global__ void k_jacobi_norms_part(const zc* G, int64_t k, double* part) {
+  __shared__ double red[16];
+  double off = 0.0, all = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < k * k; e += (int64_t)gridDim.x * blockDim.x) {
+    const double a = zabs2(G[e]);
+    all += a;
+    if (e % k != e / k) off += a;
+  }
+  off = block_sum(off, red);
+  all = block_sum(all, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = off;
+    part[2 * blockIdx.x + 1] = all;
+  }
+}
+
+__global__ void k_jacobi_norms_final(const double* part, int nb, double* out) {
+  if (threadIdx.x == 0) {
+    double off = 0.0, all = 0.0;
+    for (int b = 0; b < nb; b++) {
+      off += part[2 * b];
+      all += part[2 * b + 1];
+    }
+    out[0] = off;
+    out[1] = all;
+  }
+}
+
+__global__ void k_jacobi_rank(const zc* G, int64_t k, int* rank, double* w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const double di = G[i + i * k].x;
+  int r = 0;
+  for (int64_t j = 0; j < k; j++) {
+    const double dj = G[j + j * k].x;
+    if (dj < di || (dj == di && j < i)) r++;
+  }
+  rank[i] = r;
+  w[r] = di;
+}
+
+__global__ void k_jacobi_permute(const zc* Z, int64_t k, const int* rank, zc* Zout, int64_t ldz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int64_t r = e % k, i = e / k;
+  Zout[r + (int64_t)rank[i] * ldz] = Z[e];
+}
+
+// --------------------------------------------------------------------------
+// Lanczos pieces
+// --------------------------------------------------------------------------
+constexpr int MV_SPLITS = 32;
+
+__global__ void k_gemv_part(const zc* A, int64_t lda, int64_t n, const zc* x, zc* part) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  const int64_t cs = cdiv(n, MV_SPLITS);
+  const int64_t c0 = s * cs, c1 = min(n, c0 + cs);
+  if (i >= n) return;
+  zc acc = zmk(0.0, 0.0);
+  for (int64_t c = c0; c < c1; c++) acc = zadd(acc, zmul(A[i + c * lda], x[c]));
+  part[(int64_t)s * n + i] = acc;
+}
+
+__global__ void k_gemv_reduce(const zc* part, int64_t n, zc* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  zc acc = zmk(0.0, 0.0);
+  for (int s = 0; s < MV_SPLITS; s++) acc = zadd(acc, part[(int64_t)s * n + i]);
+  y[i] = acc;
+}
+
+__global__ void k_multi_dot(const zc* V, int64_t ldv, int64_t n, const zc* w, zc* out) {
+  __shared__ double red[16];
+  const int64_t p = blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const zc t = zcmul(V[i + p * ldv], w[i]);
+    re += t.x;
+    im += t.y;
+  }
+  re = block_sum(re, red);
+  im = block_sum(im, red);
+  if (threadIdx.x == 0) out[p] = zmk(re, im);
+}
+
+__global__ void k_sub_combination(const zc* V, int64_t ldv, int64_t n, int64_t cnt, const zc* h, zc* w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  zc acc = w[i];
+  for (int64_t p = 0; p < cnt; p++) acc = zsub(acc, zmul(V[i + p * ldv], h[p]));
+  w[i] = acc;
+}
+
+__global__ void k_three_term(zc* w, const zc* V, int64_t ldv, int64_t n, int64_t j, double* alpha, const double* beta,
+                             const zc* h) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double a = h[0].x;
+  if (i == 0) alpha[j] = a;
+  if (i >= n) return;
+  zc acc = zsub(w[i], zscale(a, V[i + j * ldv]));
+  if (j > 0) acc = zsub(acc, zscale(beta[j], V[i + (j - 1) * ldv]));
+  w[i] = acc;
+}
+
+__global__ void k_norm(const zc* w, int64_t n, double* out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += zabs2(w[i]);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+
+__global__ void k_scale_inv(const zc* w, int64_t n, const double* nrm, zc* v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double b = nrm[0];
+  v[i] = b > 0.0 ? zscale(1.0 / b, w[i]) : zmk(0.0, 0.0);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define LAUNCH(kern, grid, block, shm, st, ...)                          \
+  do {                                                                  \
+    hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);        \
+    CHFSI_CHECK_LAUNCH();                                               \
+  } while (0)
+
+void random_block(uint64_t seed, uint32_t stream, int64_t n, int64_t k, int64_t col0, zc* Y, int64_t ldy, hipStream_t st) {
+  if (n * k == 0) return;
+  LAUNCH(k_random_block, grid1(n * k), dim3(NT), 0, st, seed, stream, n, k, col0, Y, ldy);
+}
+
+void philox_raw(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count, hipStream_t st) {
+  if (count == 0) return;
+  LAUNCH(k_philox_raw, grid1(count), dim3(NT), 0, st, ctr, key, out, count);
+}
+
+void fill_i32(int* p, int64_t count, int v, hipStream_t st) {
+  if (count == 0) return;
+  LAUNCH(k_fill_i32, grid1(count), dim3(NT), 0, st, p, count, v);
+}
+
+void copy2d(const zc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st) {
+  if (m * n == 0) return;
+  LAUNCH(k_copy2d, grid1(m * n), dim3(NT), 0, st, src, lds, dst, ldd, m, n);
+}
+
+void set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st) {
+  if (m * n == 0) return;
+  LAUNCH(k_set_identity, grid1(m * n), dim3(NT), 0, st, Y, ldy, m, n);
+}
+
+void zero_strict_upper(zc* A, int64_t lda, int64_t n, hipStream_t st) {
+  LAUNCH(k_zero_strict_upper, grid1(n * n), dim3(NT), 0, st, A, lda, n);
+}
+
+void hermitize(zc* A, int64_t lda, int64_t n, hipStream_t st) {
+  LAUNCH(k_hermitize, grid1(n * n), dim3(NT), 0, st, A, lda, n);
+}
+
+void residual_block(const zc* W, int64_t ldw, const zc* Y, int64_t ldy, const double* mu, zc* R, int64_t ldr, int64_t n,
+                    int64_t k, hipStream_t st) {
+  if (n * k == 0) return;
+  LAUNCH(k_residual, grid1(n * k), dim3(NT), 0, st, W, ldw, Y, ldy, mu, R, ldr, n, k);
+}
+
+void column_norms(const zc* R, int64_t ldr, int64_t n, int64_t k, double* out, hipStream_t st) {
+  if (k == 0) return;
+  LAUNCH(k_column_norms, dim3((unsigned)k), dim3(NT), 0, st, R, ldr, n, out);
+}
+
+void nonfinite_check(const zc* A, int64_t lda, int64_t n, int64_t k, int* flag, hipStream_t st) {
+  if (n * k == 0) return;
+  LAUNCH(k_nonfinite, grid1(n * k), dim3(NT), 0, st, A, lda, n, k, flag);
+}
+
+void chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi, int64_t j0, int64_t nb, int* info,
+               hipStream_t st) {
+  static bool attr = false;
+  const size_t shm = 2 * (size_t)CNB * CLD * sizeof(zc);
+  if (!attr) {
+    CHFSI_HIP(hipFuncSetAttribute((const void*)k_chol_diag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    attr = true;
+  }
+  if (nb < 1 || nb > CNB) throw Error(ST_EINVAL, "chol_diag: block size out of range");
+  LAUNCH(k_chol_diag, dim3(1), dim3(256), shm, st, W, ldw, L, ldl, Linv, ldi, j0, (int)nb, info);
+}
+
+void hh_panel_setup(HHPanel& p) {
+  const int64_t rows = p.n - p.j0;
+  int64_t nb = std::min<int64_t>(cdiv(rows, 256), 240);
+  if (nb < 1) nb = 1;
+  p.rows_per_blk = 256 * cdiv(cdiv(rows, nb), 256);
+  p.nblk = (int)cdiv(rows, p.rows_per_blk);
+  if (p.nblk < 1) p.nblk = 1;
+}
+
+void hh_first_partials(const HHPanel& p, hipStream_t st) {
+  LAUNCH(k_hh_first, dim3((unsigned)p.nblk), dim3(256), 0, st, p);
+}
+
+void hh_column(const HHPanel& p, int64_t j, hipStream_t st) {
+  LAUNCH(k_hh_column, dim3((unsigned)p.nblk), dim3(256), 0, st, p, j);
+}
+
+void hh_extract_v(const zc* F, int64_t ldf, int64_t n, int64_t j0, int64_t j1, zc* Vp, int64_t ldv, hipStream_t st) {
+  const int64_t tot = (n - j0) * (j1 - j0);
+  if (tot == 0) return;
+  LAUNCH(k_hh_extract_v, grid1(tot), dim3(NT), 0, st, F, ldf, n, j0, j1, Vp, ldv);
+}
+
+void hh_build_t(const zc* gram, const zc* tau, int64_t cnt, zc* T, hipStream_t st) {
+  LAUNCH(k_hh_build_t, dim3(1), dim3(64), 0, st, gram, tau, cnt, T);
+}
+
+void jacobi_small(const zc* G, int64_t ldg, int64_t k, double* w, zc* Z, int64_t ldz, zc* Ztmp, int* sweeps_out,
+                  hipStream_t st) {
+  if (k < 1 || k > JACOBI_LDS_MAX) throw Error(ST_EINVAL, "jacobi_small: size out of range");
+  static bool attr = false;
+  const size_t shm = (size_t)JACOBI_LDS_MAX * JACOBI_LDS_MAX * sizeof(zc);
+  if (!attr) {
+    CHFSI_HIP(hipFuncSetAttribute((const void*)k_jacobi_small, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    attr = true;
+  }
+  LAUNCH(k_jacobi_small, dim3(1), dim3(1024), (size_t)k * k * sizeof(zc), st, G, ldg, (int)k, w, Z, ldz, Ztmp, sweeps_out);
+}
+
+void jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0, hipStream_t st) {
+  LAUNCH(k_jacobi_init, grid1(k * k), dim3(NT), 0, st, G, ldg, k, G0, Z0);
+}
+
+void jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
+                  int* rotated, hipStream_t st) {
+  const int64_t half = (k + (k & 1)) / 2;
+  LAUNCH(k_jacobi_round, grid1(half * half + k * half), dim3(NT), 0, st, Gin, Gout, Zin, Zout, k, round, fro2, rotated);
+}
+
+void jacobi_norms(const zc* G, int64_t k, double* part, double* out, hipStream_t st) {
+  const int nb = (int)std::min<int64_t>(256, std::max<int64_t>(1, cdiv(k * k, 1024)));
+  LAUNCH(k_jacobi_norms_part, dim3(nb), dim3(NT), 0, st, G, k, part);
+  LAUNCH(k_jacobi_norms_final, dim3(1), dim3(64), 0, st, part, nb, out);
+}
+
+void jacobi_sort(const zc* G, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz, hipStream_t st) {
+  LAUNCH(k_jacobi_rank, grid1(k), dim3(NT), 0, st, G, k, rank, w);
+  LAUNCH(k_jacobi_permute, grid1(k * k), dim3(NT), 0, st, Z, k, rank, Zout, ldz);
+}
+
+void zgemv(const zc* A, int64_t lda, int64_t n, const zc* x, zc* y, zc* part, hipStream_t st) {
+  LAUNCH(k_gemv_part, dim3((unsigned)cdiv(n, NT), MV_SPLITS), dim3(NT), 0, st, A, lda, n, x, part);
+  LAUNCH(k_gemv_reduce, grid1(n), dim3(NT), 0, st, part, n, y);
+}
+
+void multi_dot(const zc* V, int64_t ldv, int64_t n, int64_t cnt, const zc* w, zc* out, hipStream_t st) {
+  if (cnt == 0) return;
+  LAUNCH(k_multi_dot, dim3((unsigned)cnt), dim3(NT), 0, st, V, ldv, n, w, out);
+}
+
+void sub_combination(const zc* V, int64_t ldv, int64_t n, int64_t cnt, const zc* h, zc* w, hipStream_t st) {
+  if (cnt == 0) return;
+  LAUNCH(k_sub_combination, grid1(n), dim3(NT), 0, st, V, ldv, n, cnt, h, w);
+}
+
+void lanczos_three_term(zc* w, const zc* V, int64_t ldv, int64_t n, int64_t j, double* alpha, const double* beta,
+                        const zc* h, hipStream_t st) {
+  LAUNCH(k_three_term, grid1(n), dim3(NT), 0, st, w, V, ldv, n, j, alpha, beta, h);
+}
+
+void normalize(const zc* w, int64_t n, zc* v, double* beta_out, hipStream_t st) {
+  LAUNCH(k_norm, dim3(1), dim3(1024), 0, st, w, n, beta_out);
+  LAUNCH(k_scale_inv, grid1(n), dim3(NT), 0, st, w, n, beta_out, v);
+}
+
+}  // namespace chfsi

@@ -1,0 +1,83 @@
+// Launchers of the non-GEMM kernels of the ChFSI library.
+#pragma once
+
+#include "common.hpp"
+
+namespace chfsi {
+
+// ---- random start vectors: Philox4x32-10 + Box-Muller ---------------------
+// Y(i, j) = complex Gaussian number (i + (j + col0) * n) of `stream` under `seed`.
+void random_block(uint64_t seed, uint32_t stream, int64_t n, int64_t k, int64_t col0, zc* Y, int64_t ldy, hipStream_t st);
+// Raw Philox blocks, for known-answer checks: ctr/key/out are device arrays of
+// 4*count, 2*count, 4*count uint32.
+void philox_raw(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count, hipStream_t st);
+
+// ---- elementwise / layout --------------------------------------------------
+void fill_i32(int* p, int64_t count, int v, hipStream_t st);
+void copy2d(const zc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st);
+void set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st);
+void zero_strict_upper(zc* A, int64_t lda, int64_t n, hipStream_t st);
+void hermitize(zc* A, int64_t lda, int64_t n, hipStream_t st);  // A <- (A + A^H)/2, in place
+// R(:, j) = W(:, j) - mu[j] Y(:, j)
+void residual_block(const zc* W, int64_t ldw, const zc* Y, int64_t ldy, const double* mu, zc* R, int64_t ldr, int64_t n,
+                    int64_t k, hipStream_t st);
+// out[j] = ||R(:, j)||_2
+void column_norms(const zc* R, int64_t ldr, int64_t n, int64_t k, double* out, hipStream_t st);
+// flag[0] = 1 if any entry of the n x k block is not finite (else untouched)
+void nonfinite_check(const zc* A, int64_t lda, int64_t n, int64_t k, int* flag, hipStream_t st);
+
+// ---- Cholesky --------------------------------------------------------------
+// Factor the nb x nb diagonal block W(j0:j0+nb, j0:j0+nb) (lower triangle
+// read) into L's block and its inverse into Linv's block.  On a pivot that
+// is not positive, info[0] receives min(info[0], j0 + column + 1) (info is
+// initialised to a huge value by the caller).
+void chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi, int64_t j0, int64_t nb, int* info,
+               hipStream_t st);
+constexpr int CHOL_NB = 64;
+
+// ---- Householder QR --------------------------------------------------------
+constexpr int HH_NB = 32;
+struct HHPanel {
+  zc* F; int64_t ldf; int64_t n;  // matrix being factored (n rows)
+  int64_t j0, j1;                 // panel columns [j0, j1)
+  int nblk;                       // workgroups (row blocks)
+  int64_t rows_per_blk;           // multiple of 256
+  zc* part;                       // 2 x nblk x HH_NB partial sums
+  zc* top;                        // 2 x HH_NB top rows
+  zc* tau;                        // k reflector scalars
+};
+void hh_panel_setup(HHPanel& p);
+void hh_first_partials(const HHPanel& p, hipStream_t st);
+void hh_column(const HHPanel& p, int64_t j, hipStream_t st);
+// Vp(0:n-j0, 0:nb): explicit unit lower-trapezoidal V of the panel
+void hh_extract_v(const zc* F, int64_t ldf, int64_t n, int64_t j0, int64_t j1, zc* Vp, int64_t ldv, hipStream_t st);
+// T (nb x nb, ld nb) of H_j0 ... H_{j1-1} = I - V T V^H from the Gram V^H V
+void hh_build_t(const zc* gram, const zc* tau, int64_t cnt, zc* T, hipStream_t st);
+
+// ---- Jacobi eigensolver for Hermitian k x k --------------------------------
+constexpr int JACOBI_LDS_MAX = 96;
+// Single-workgroup solver (k <= JACOBI_LDS_MAX): w ascending, Z (ld ldz).
+void jacobi_small(const zc* G, int64_t ldg, int64_t k, double* w, zc* Z, int64_t ldz, zc* Ztmp, int* sweeps_out,
+                  hipStream_t st);
+// Multi-launch pieces for larger k.
+void jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0, hipStream_t st);
+void jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
+                  int* rotated, hipStream_t st);
+// out[0] = sum |G_ij|^2 off the diagonal, out[1] = sum over all (two-stage)
+void jacobi_norms(const zc* G, int64_t k, double* part, double* out, hipStream_t st);
+void jacobi_sort(const zc* G, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz, hipStream_t st);
+
+// ---- Lanczos pieces ---------------------------------------------------------
+// y = A x (A n x n, lda); part: work of JMV_SPLITS * n
+void zgemv(const zc* A, int64_t lda, int64_t n, const zc* x, zc* y, zc* part, hipStream_t st);
+// out[p] = V(:, p)^H w for p < cnt
+void multi_dot(const zc* V, int64_t ldv, int64_t n, int64_t cnt, const zc* w, zc* out, hipStream_t st);
+// w -= V(:, 0:cnt) h
+void sub_combination(const zc* V, int64_t ldv, int64_t n, int64_t cnt, const zc* h, zc* w, hipStream_t st);
+// w -= alpha[j] v_j + beta[j] v_{j-1}; alpha[j] = Re(h[0]) read from device
+void lanczos_three_term(zc* w, const zc* V, int64_t ldv, int64_t n, int64_t j, double* alpha, const double* beta,
+                        const zc* h, hipStream_t st);
+// beta_out = ||w||, v = w / beta (0 if beta == 0)
+void normalize(const zc* w, int64_t n, zc* v, double* beta_out, hipStream_t st);
+
+}  // namespace chfsi

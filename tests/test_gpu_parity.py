@@ -1,0 +1,398 @@
+"""Parity of the gfx950 library (through its C ABI) with the CPU oracle.
+
+Every step of Algorithm 1 is compared element by element with the oracle on
+the same seeded inputs, at sizes that span several tiles and leave ragged
+tails; the whole solve is compared on the n=512 configuration and on a short
+warm-started sequence.  Tolerances (FP64 throughout):
+  * single dense steps (filter, products, QR, reduction): relative Frobenius
+    error <= 1e-12 (the two sides sum in different orders; cond(L) ~ 1);
+  * eigenvalues: |dlam| <= 1e-10 |lam| or <= 1e-12 ||H||_2;
+  * residuals: ||H x - lam S x|| <= 1e-10 ||H||_2 (the paper's tolerance).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+import oracle
+import workloads
+from tests import _checks
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    """numpy matrix -> column-major complex128 device tensor of the same shape."""
+    import torch
+    a = np.asarray(a, dtype=np.complex128)
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to("cuda").mT
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _rng(s):
+    return np.random.default_rng(s)
+
+
+def _cg(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.fixture(scope="module")
+def lib(gpu):
+    from paper_1305_5120_amd import chfsi
+    return chfsi
+
+
+# --------------------------------------------------------------------------
+# generator
+# --------------------------------------------------------------------------
+
+def test_philox_known_answers_bit_exact(lib):
+    import os
+    rows = [l.split() for l in open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    v = np.array([[int(x, 16) for x in r] for r in rows], dtype=np.uint64)
+    ctx = lib.create(8)
+    out = lib.philox(ctx, v[:, 0:4].astype(np.uint32), v[:, 4:6].astype(np.uint32))
+    assert np.array_equal(out, v[:, 6:10].astype(np.uint32))
+    # and the oracle's generator on a batch of counters
+    rng = _rng(1)
+    ctr = rng.integers(0, 2**32, size=(64, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(64, 2), dtype=np.uint64).astype(np.uint32)
+    out = lib.philox(ctx, ctr, key)
+    for i in range(64):
+        assert np.array_equal(out[i], oracle.philox4x32_10(ctr[i], key[i]))
+
+
+def test_random_block_matches_oracle(lib):
+    n, k = 333, 7
+    ctx = lib.create(n)
+    Y = _np(lib.random_block(ctx, 12345, 3, k, col0=5))
+    ref = oracle.gauss_block(12345, 3, n, k, col0=5)
+    # same Philox bits; log / sin / cos may differ in the last bit
+    assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+# --------------------------------------------------------------------------
+# dense products (the filter's kernel in all its modes)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("opA,opB", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("M,N,K", [(77, 45, 131), (200, 130, 70), (20, 20, 3000), (1, 1, 1)])
+def test_zgemm_against_definition(lib, opA, opB, M, N, K):
+    rng = _rng(M + N + K + opA * 2 + opB)
+    A = _cg(rng, (M, K) if opA == 0 else (K, M))
+    B = _cg(rng, (K, N) if opB == 0 else (N, K))
+    X = _cg(rng, (M, N))
+    Z = _cg(rng, (M, N))
+    ctx = lib.create(8)
+    C = lib.zgemm(ctx, opA, opB, _t(A), _t(B), alpha=0.7, beta=-0.3, X=_t(X), gamma=1.9, Z=_t(Z))
+    opa = A if opA == 0 else A.conj().T
+    opb = B if opB == 0 else B.conj().T
+    ref = 0.7 * (opa @ opb) - 0.3 * X + 1.9 * Z
+    assert _rel(_np(C), ref) <= 1e-13
+
+
+def test_zgemm_triangular_structure_flags(lib):
+    rng = _rng(9)
+    n = 150
+    Lm = np.tril(_cg(rng, (n, n)))
+    B = _cg(rng, (n, 40))
+    ctx = lib.create(8)
+    for opA, flag, opa in ((0, 1, Lm), (1, 2, Lm.conj().T)):
+        C = lib.zgemm(ctx, opA, 0, _t(Lm), _t(B), flags=flag)
+        assert _rel(_np(C), opa @ B) <= 1e-13
+    Bl = np.tril(_cg(rng, (n, n)))
+    Am = _cg(rng, (60, n))
+    C = lib.zgemm(ctx, 0, 0, _t(Am), _t(Bl), flags=4)
+    assert _rel(_np(C), Am @ Bl) <= 1e-13
+    C = lib.zgemm(ctx, 0, 1, _t(Am), _t(Bl), flags=8)
+    assert _rel(_np(C), Am @ Bl.conj().T) <= 1e-13
+
+
+def test_zgemm_in_place_epilogue(lib):
+    """out aliasing Z (the filter writes Y_{i+1} over Y_{i-1})."""
+    import torch
+    rng = _rng(10)
+    A = _cg(rng, (130, 130))
+    Y = _cg(rng, (130, 33))
+    P = _cg(rng, (130, 33))
+    ctx = lib.create(8)
+    Pt = _t(P)
+    lib.zgemm(ctx, 0, 0, _t(A), _t(Y), alpha=2.0, beta=-1.0, X=_t(Y), gamma=-0.5, Z=Pt, C=Pt)
+    assert _rel(_np(Pt), 2.0 * A @ Y - Y - 0.5 * P) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# steps of Algorithm 1 against the oracle
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,k,m", [(300, 37, 7), (130, 64, 1), (64, 5, 20)])
+def test_filter_matches_oracle(lib, n, k, m):
+    p = workloads.make_problem(n, 70 + n)
+    rng = _rng(n)
+    Y = _cg(rng, (n, k))
+    lam = np.sort(p.lam)
+    a, b, a0 = float(lam[k]), float(lam[-1] * 1.05), float(lam[0])
+    ref = oracle.chebyshev_filter(p.A, Y, m, a, b, a0)
+    ctx = lib.create(n)
+    Yt = _t(Y)
+    lib.filter(ctx, _t(p.A), Yt, m, a, b, a0)
+    assert _rel(_np(Yt), ref) <= 1e-12
+
+
+def test_filter_closed_form_on_diagonal(lib):
+    n, k, m = 100, 6, 9
+    t = np.linspace(-1.0, 3.0, n)
+    a, b, a0 = 0.5, 3.0, -1.0
+    rng = _rng(3)
+    Y = _cg(rng, (n, k))
+    ctx = lib.create(n)
+    Yt = _t(Y)
+    lib.filter(ctx, _t(np.diag(t).astype(complex)), Yt, m, a, b, a0)
+    e, c = (b - a) / 2, (b + a) / 2
+    x = (t - c) / e
+    cm = np.where(np.abs(x) <= 1, np.cos(m * np.arccos(np.clip(x, -1, 1))),
+                  np.sign(x) ** m * np.cosh(m * np.arccosh(np.maximum(np.abs(x), 1))))
+    x0 = (a0 - c) / e
+    p0 = (-1) ** m * math.cosh(m * math.acosh(-x0))
+    assert _rel(_np(Yt), (cm / p0)[:, None] * Y) <= 1e-12
+
+
+@pytest.mark.parametrize("n,k", [(300, 70), (96, 96), (257, 1), (1000, 40)])
+def test_qr_matches_oracle(lib, n, k):
+    rng = _rng(n * k)
+    Y = _cg(rng, (n, k))
+    Qr, R = oracle.householder_qr(Y)
+    ctx = lib.create(n)
+    Yt = _t(Y)
+    lib.qr(ctx, Yt)
+    Q = _np(Yt)
+    assert np.abs(Q.conj().T @ Q - np.eye(k)).max() <= 1e-13
+    # same reflector convention: Q agrees column by column, phases included
+    assert _rel(Q, Qr) <= 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 40, 96, 97, 130])
+def test_eigh_matches_oracle(lib, k):
+    rng = _rng(k)
+    M = _cg(rng, (k, k))
+    G = (M + M.conj().T) / 2
+    w_ref, Z_ref, _ = oracle.jacobi_eigh(G)
+    ctx = lib.create(max(k, 8))
+    w, Z = lib.eigh(ctx, _t(G))
+    Z = _np(Z)
+    gn = np.linalg.norm(G)
+    assert np.abs(w - w_ref).max() <= 1e-13 * gn
+    assert np.abs(G @ Z - Z * w).max() <= 1e-12 * gn
+    assert np.abs(Z.conj().T @ Z - np.eye(k)).max() <= 1e-12
+    # eigenvectors of separated eigenvalues agree up to a phase
+    gaps = np.minimum(np.diff(np.r_[-np.inf, w_ref]), np.diff(np.r_[w_ref, np.inf]))
+    sep = gaps > 1e-3 * gn
+    ov = np.abs(np.sum(Z.conj() * Z_ref, axis=0))
+    assert np.all(np.abs(ov[sep] - 1) <= 1e-9)
+
+
+def test_eigh_clustered_spectrum(lib):
+    rng = _rng(44)
+    k = 120
+    lam = np.sort(np.concatenate([rng.uniform(-1, 1, k - 8), 0.3 + np.linspace(-5e-4, 5e-4, 4),
+                                  -0.6 + np.linspace(-5e-4, 5e-4, 4)]))
+    Q, _ = np.linalg.qr(_cg(rng, (k, k)))
+    G = (Q * lam) @ Q.conj().T
+    G = (G + G.conj().T) / 2
+    ctx = lib.create(k)
+    w, Z = lib.eigh(ctx, _t(G))
+    assert np.abs(w - lam).max() <= 1e-14 * k
+
+
+@pytest.mark.parametrize("n", [200, 64, 333])
+def test_reduce_matches_oracle(lib, n):
+    p = workloads.make_problem(n, 5 + n)
+    L_ref, bad = oracle.cholesky(p.S)
+    assert bad == 0
+    A_ref = oracle.reduce(p.H, L_ref)
+    ctx = lib.create(n)
+    lib.reduce(ctx, _t(p.H), _t(p.S))
+    A, L, Li = (_np(x) for x in lib.copy_factors(ctx))
+    assert np.abs(L - L_ref).max() <= 1e-14
+    assert np.all(np.triu(L, 1) == 0) and np.all(np.triu(Li, 1) == 0)
+    assert np.abs(Li @ L_ref - np.eye(n)).max() <= 1e-13
+    assert _rel(A, A_ref) <= 1e-13
+    assert np.array_equal(A, A.conj().T)
+    # S == NULL reuses the factor
+    lib.reduce(ctx, _t(2 * p.H), None)
+    A2 = _np(lib.copy_factors(ctx)[0])
+    assert _rel(A2, 2 * A_ref) <= 1e-13
+
+
+def test_reduce_reports_not_positive_definite(lib):
+    p = workloads.make_problem(150, 3)
+    S = p.S.copy()
+    S[100, 100] = -5.0
+    ctx = lib.create(150)
+    with pytest.raises(lib.ChfsiError) as e:
+        lib.reduce(ctx, _t(p.H), _t(S))
+    assert e.value.status == -2
+    assert "column" in str(e.value)
+
+
+@pytest.mark.parametrize("n,steps", [(256, 10), (8, 8), (500, 30)])
+def test_lanczos_matches_oracle(lib, n, steps):
+    p = workloads.make_problem(n, 30 + n)
+    v0 = oracle.gauss_block(77, 1, n, 1)[:, 0]
+    ref = oracle.lanczos(p.A, steps, v0)
+    ctx = lib.create(n)
+    got = lib.lanczos(ctx, _t(p.A), steps, 77, 1)
+    assert np.allclose(got[:2], ref[:2], rtol=1e-10, atol=1e-12 * abs(ref[1]))
+    assert abs(got[2] - ref[2]) <= 1e-8 * abs(ref[2])
+    # the bound is safe (exact to rounding when steps == n)
+    assert got[2] >= p.lam.max() * (1 - 1e-13)
+
+
+def test_rayleigh_ritz_and_residuals_match_oracle(lib):
+    n, k = 300, 40
+    p = workloads.make_problem(n, 17)
+    rng = _rng(17)
+    Y, _ = np.linalg.qr(_cg(rng, (n, k)))
+    mu_ref, Yr = oracle.rayleigh_ritz(p.A, Y)
+    ctx = lib.create(n)
+    Yt = _t(Y)
+    mu, _ = lib.rayleigh_ritz(ctx, _t(p.A), Yt)
+    assert np.abs(mu - mu_ref).max() <= 1e-12 * np.abs(p.lam).max()
+    Yg = _np(Yt)
+    # Ritz vectors agree up to phases (random block: separated Ritz values)
+    ov = np.abs(np.sum(Yg.conj() * Yr, axis=0))
+    assert np.abs(ov - 1).max() <= 1e-8
+    rho_ref = oracle.residuals(p.A, p.L, Yr, mu_ref)
+    rho = lib.residuals(ctx, _t(p.A), _t(p.L), _t(Yr), mu_ref)
+    assert np.abs(rho - rho_ref).max() <= 1e-12 * rho_ref.max()
+
+
+# --------------------------------------------------------------------------
+# whole solve
+# --------------------------------------------------------------------------
+
+def _check_solution(p, evals, X, nev, tol=1e-10):
+    hn = _checks.spectral_norm(p.H)
+    lam = np.sort(p.lam)
+    ok, dmax = _checks.eig_ok(evals, lam[:nev], hn)
+    assert ok, dmax
+    r = _checks.gen_residuals(p.H, p.S, X, evals)
+    assert r.max() <= tol * hn, r.max() / hn
+    assert _checks.s_orth_err(p.S, X) <= 1e-12
+    Y = _checks.standard_vectors(p.L, X)
+    ok, worst, ratio = _checks.subspace_check(Y, _checks.exact_standard_vectors(p.Q, p.lam), p.lam, p.A, evals, nev)
+    assert ok, (worst, ratio)
+
+
+def test_solve_config0_matches_oracle(lib):
+    """n=512, nev=51, nex=13, degree 10, tol 1e-10 (the small configuration)."""
+    p = workloads.make_problem(512, 0)
+    ref = oracle.solve(p.H, p.S, 51, 13, tol=1e-10, degree=10, seed=0)
+    ctx = lib.create(512, degree=10, seed=0)
+    ev, X, info, st = lib.solve(ctx, _t(p.H), _t(p.S), 51, 13, tol=1e-10)
+    assert st == 0 and info["converged"] >= 51
+    assert np.abs(ev - ref["evals"]).max() <= 1e-12 * 100
+    _check_solution(p, ev, _np(X), 51)
+    assert info["b_upper"] >= p.lam.max()
+    assert info["filter_flops"] > 0 and info["iterations"] > 1
+
+
+def test_solve_ragged_sizes_against_brute_force(lib):
+    n, nev, nex = 333, 17, 6
+    p = workloads.make_problem(n, 41)
+    ctx = lib.create(n, degree=12, seed=3)
+    ev, X, info, st = lib.solve(ctx, _t(p.H), _t(p.S), nev, nex, tol=1e-10)
+    ref = sl.eigh(p.H, p.S, eigvals_only=True)[:nev]
+    hn = _checks.spectral_norm(p.H)
+    assert _checks.eig_ok(ev, ref, hn)[0]
+    _check_solution(p, ev, _np(X), nev)
+
+
+def test_solve_warm_sequence(lib):
+    """A correlated sequence: S fixed and cached, each solve warm-started from
+    the context's state; results checked against a dense library solver."""
+    seq = list(workloads.make_sequence(400, 3, 11))
+    nev, nex = 30, 6
+    ctx = lib.create(400, degree=12, seed=1)
+    iters = []
+    for ell, p in enumerate(seq):
+        S = _t(p.S) if ell == 0 else None
+        ev, X, info, st = lib.solve(ctx, _t(p.H), S, nev, nex, tol=1e-10)
+        assert st == 0
+        assert info["warm_start"] == (1 if ell > 0 else 0)
+        hn = _checks.spectral_norm(p.H)
+        ref = sl.eigh(p.H, p.S, eigvals_only=True)[:nev]
+        assert _checks.eig_ok(ev, ref, hn)[0]
+        r = _checks.gen_residuals(p.H, p.S, _np(X), ev)
+        assert r.max() <= 1e-10 * hn
+        iters.append(info["iterations"])
+    cold = lib.create(400, degree=12, seed=1)
+    _, _, info_c, _ = lib.solve(cold, _t(seq[-1].H), _t(seq[-1].S), nev, nex, tol=1e-10)
+    assert iters[-1] <= info_c["iterations"]
+
+
+def test_solve_explicit_warm_vectors_with_new_overlap(lib):
+    """V_warm given in the generalized space while S is passed again."""
+    seq = list(workloads.make_sequence(256, 2, 21))
+    nev, nex = 20, 4
+    ctx = lib.create(256, degree=10)
+    ev0, X0, _, _ = lib.solve(ctx, _t(seq[0].H), _t(seq[0].S), nev, nex)
+    ctx2 = lib.create(256, degree=10)
+    ev1, X1, info, st = lib.solve(ctx2, _t(seq[1].H), _t(seq[1].S), nev, nex, V_warm=X0)
+    assert st == 0 and info["warm_start"] == 1
+    p = seq[1]
+    hn = _checks.spectral_norm(p.H)
+    assert _checks.eig_ok(ev1, sl.eigh(p.H, p.S, eigvals_only=True)[:nev], hn)[0]
+
+
+def test_solve_error_paths(lib):
+    import torch
+    p = workloads.make_problem(128, 8)
+    ctx = lib.create(128, degree=6, max_iter=2)
+    ev, X, info, st = lib.solve(ctx, _t(p.H), _t(p.S), 20, 5, raise_on_noconv=False)
+    assert st == -3 and info["converged"] < 20
+    c = info["converged"]
+    assert np.all(np.isnan(ev[c:]))
+    # NaN in H
+    H = p.H.copy()
+    H[3, 7] = np.nan
+    H[7, 3] = np.nan
+    ctx2 = lib.create(128, degree=6)
+    with pytest.raises(lib.ChfsiError) as e:
+        lib.solve(ctx2, _t(H), _t(p.S), 10, 4)
+    assert e.value.status == -4
+    # the context stays usable after a failure
+    ev, X, info, st = lib.solve(ctx2, _t(p.H), _t(p.S), 10, 4)
+    assert st == 0
+    # invalid arguments
+    with pytest.raises(lib.ChfsiError) as e:
+        lib.solve(ctx2, _t(p.H), _t(p.S), 100, 40)
+    assert e.value.status == -1
+    S = p.S.copy()
+    S[0, 0] = -1
+    with pytest.raises(lib.ChfsiError) as e:
+        lib.solve(ctx2, _t(p.H), _t(S), 10, 4)
+    assert e.value.status == -2
+
+
+def test_row_major_input_is_not_transposed(lib):
+    """A row-major torch tensor must be read as the matrix it represents."""
+    import torch
+    p = workloads.make_problem(96, 2)
+    Hr = torch.from_numpy(p.H.copy(order="C")).cuda()   # row-major
+    Sr = torch.from_numpy(p.S.copy(order="C")).cuda()
+    ctx = lib.create(96, degree=8)
+    ev, X, info, st = lib.solve(ctx, Hr, Sr, 8, 4)
+    Xn = _np(X)
+    r = _checks.gen_residuals(p.H, p.S, Xn, ev)
+    assert r.max() <= 1e-10 * _checks.spectral_norm(p.H)
