@@ -61,7 +61,11 @@ typedef struct {
   int32_t precision;     /* 0: FP64 throughout (the only mode of this version) */
   uint64_t seed;         /* Philox4x32-10 seed of the random start vectors (default 0) */
   int32_t profile;       /* 1: time every filter kernel launch with device events */
-  int32_t reserved[7];
+  int32_t qr_mode;       /* re-orthonormalization: 0 = CholeskyQR2, Householder when a Gram
+                            matrix is not positive definite (default); 1 = Householder always */
+  int32_t filter_tile;   /* filter kernel tile configuration (chfsi_zgemm's numbering; 0 = automatic) */
+  int32_t filter_splitk; /* filter K split (0 = automatic, 1 = none, up to 16) */
+  int32_t reserved[4];
 } chfsi_opts;
 
 typedef struct {
@@ -69,6 +73,8 @@ typedef struct {
   int32_t converged;       /* locked eigenpairs (>= nev on success) */
   int32_t warm_start;      /* 1 when the start block came from previous vectors */
   int32_t filter_launches; /* filter kernel launches (degree steps) */
+  int32_t qr_householder;  /* re-orthonormalizations that used Householder QR */
+  int32_t reserved_i;
   double filter_flops;     /* algorithmic filter work: sum over steps of 8 n^2 k_active */
   double filter_kernel_seconds; /* summed filter kernel durations (profile = 1, else 0) */
   double t_reduce, t_lanczos, t_filter, t_qr, t_rr, t_resid, t_total; /* seconds per phase */
@@ -142,6 +148,12 @@ chfsi_status chfsi_filter(chfsi_ctx ctx, const void* A, int64_t lda, void* Y, in
  * pivot's real part (LAPACK convention). */
 chfsi_status chfsi_qr(chfsi_ctx ctx, void* Y, int64_t ldy, int64_t k);
 
+/* The solver's re-orthonormalization (Algorithm 1): Y (device n x k) is
+ * overwritten with an orthonormal basis of its span, by CholeskyQR2 or, when
+ * a Gram matrix is not numerically positive definite (or opts.qr_mode = 1),
+ * by Householder QR.  *used_householder (may be NULL) tells which. */
+chfsi_status chfsi_orthonormalize(chfsi_ctx ctx, void* Y, int64_t ldy, int64_t k, int32_t* used_householder);
+
 /* Hermitian eigensolver (Jacobi): G (device k x k, read only) = Z diag(w) Z^H,
  * w host (k, ascending), Z device k x k. */
 chfsi_status chfsi_eigh(chfsi_ctx ctx, const void* G, int64_t ldg, int64_t k, double* w, void* Z, int64_t ldz);
@@ -175,8 +187,11 @@ chfsi_status chfsi_philox(chfsi_ctx ctx, const uint32_t* ctr, const uint32_t* ke
 /* The library's complex GEMM with its three-term epilogue:
  *   C = alpha op(A) op(B) + beta X + gamma Z,   op in {0: none, 1: conj-transpose}
  * op(A) M x K, op(B) K x N; X, Z may be NULL; C may alias X or Z.
- * flags: 1 op(A) lower-triangular, 2 op(A) upper, 4 op(B) lower, 8 op(B)
- * upper (zeros stored), 16 only tiles meeting the lower triangle of C. */
+ * flags bits 0-4: 1 op(A) lower-triangular, 2 op(A) upper, 4 op(B) lower,
+ * 8 op(B) upper (zeros stored), 16 only tiles meeting the lower triangle of C;
+ * bits 8-15: tile configuration (0 = automatic choice; 1 64x64x16, 2 32x32x16,
+ * 3 64x64x8, 4 128x64x8, 5 64x128x8, 6 128x128x8, 7 64x32x16; 3-6 only with
+ * op = none on both sides); bits 16-23: K split (0 = automatic, 1 = none). */
 chfsi_status chfsi_zgemm(chfsi_ctx ctx, int32_t opA, int32_t opB, int64_t M, int64_t N, int64_t K, double alpha,
                          const void* A, int64_t lda, const void* B, int64_t ldb, double beta, const void* X, int64_t ldx,
                          double gamma, const void* Z, int64_t ldz, void* C, int64_t ldc, int32_t flags);

@@ -36,11 +36,13 @@ class ChfsiError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("degree", c_i32), ("max_iter", c_i32), ("lanczos_steps", c_i32), ("precision", c_i32),
-                ("seed", c_u64), ("profile", c_i32), ("reserved", c_i32 * 7)]
+                ("seed", c_u64), ("profile", c_i32), ("qr_mode", c_i32),
+                ("filter_tile", c_i32), ("filter_splitk", c_i32), ("reserved", c_i32 * 4)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iterations", c_i32), ("converged", c_i32), ("warm_start", c_i32), ("filter_launches", c_i32),
+                ("qr_householder", c_i32), ("reserved_i", c_i32),
                 ("filter_flops", c_dbl), ("filter_kernel_seconds", c_dbl),
                 ("t_reduce", c_dbl), ("t_lanczos", c_dbl), ("t_filter", c_dbl), ("t_qr", c_dbl), ("t_rr", c_dbl),
                 ("t_resid", c_dbl), ("t_total", c_dbl), ("b_upper", c_dbl), ("theta_min", c_dbl), ("h_H", c_dbl),
@@ -72,6 +74,7 @@ def load():
     L.chfsi_copy_factors.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64]
     L.chfsi_filter.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_i32, c_dbl, c_dbl, c_dbl]
     L.chfsi_qr.argtypes = [c_vp, c_vp, c_i64, c_i64]
+    L.chfsi_orthonormalize.argtypes = [c_vp, c_vp, c_i64, c_i64, ctypes.POINTER(c_i32)]
     L.chfsi_eigh.argtypes = [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64]
     L.chfsi_rayleigh_ritz.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp]
     L.chfsi_residuals.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp]
@@ -81,7 +84,7 @@ def load():
     L.chfsi_zgemm.argtypes = [c_vp, c_i32, c_i32, c_i64, c_i64, c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_dbl, c_vp,
                               c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_i32]
     for name in ("chfsi_create", "chfsi_reset", "chfsi_reduce", "chfsi_solve", "chfsi_copy_factors", "chfsi_filter",
-                 "chfsi_qr", "chfsi_eigh", "chfsi_rayleigh_ritz", "chfsi_residuals", "chfsi_lanczos",
+                 "chfsi_qr", "chfsi_orthonormalize", "chfsi_eigh", "chfsi_rayleigh_ritz", "chfsi_residuals", "chfsi_lanczos",
                  "chfsi_random_block", "chfsi_philox", "chfsi_zgemm"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -247,6 +250,18 @@ def qr(ctx, Y):
     if Yc.data_ptr() != Y.data_ptr():
         Y.copy_(Yc)
     return Y
+
+
+def orthonormalize(ctx, Y):
+    """Y <- orthonormal basis of span(Y), in place (the solver's step).
+    Returns True when Householder QR was used."""
+    _check_dev(Y, "Y")
+    Yc, ldy = colmajor(Y)
+    used = c_i32(0)
+    ctx._raise(ctx.lib.chfsi_orthonormalize(ctx.h, Yc.data_ptr(), ldy, Y.shape[1], ctypes.byref(used)))
+    if Yc.data_ptr() != Y.data_ptr():
+        Y.copy_(Yc)
+    return bool(used.value)
 
 
 def eigh(ctx, G):

@@ -129,7 +129,7 @@ struct chfsi_ctx_s {
     mu.release(); mu.ensure((size_t)kk * sizeof(double));
     rho.release(); rho.ensure((size_t)kk * sizeof(double));
     rank.release(); rank.ensure((size_t)kk * sizeof(int));
-    P_elems = 8 * (size_t)kk * kk + 2048 * (size_t)kk + ((size_t)1 << 16);
+    P_elems = 8 * (size_t)kk * kk + (size_t)std::max(4, opts.filter_splitk) * n * kk + ((size_t)1 << 16);
     P.release();
     P.ensure(P_elems * sizeof(zc));
     const int64_t npan = cdiv(kk, HH_NB);
@@ -188,8 +188,11 @@ struct chfsi_ctx_s {
   // ------------------------------------------------------------------------
   void gemm(int opA, int opB, int64_t M, int64_t N, int64_t K, double alpha, const zc* Ap, int64_t lda, const zc* Bp,
             int64_t ldb, zc* Cp, int64_t ldc, double beta = 0.0, const zc* X = nullptr, int64_t ldx = 0, double gamma = 0.0,
-            const zc* Zp = nullptr, int64_t ldz = 0, int flags_ = 0, bool splitk = true, bool filter_step = false) {
+            const zc* Zp = nullptr, int64_t ldz = 0, int flags_ = 0, bool splitk = true, bool filter_step = false,
+            int cfg = 0, int nsplit = 0) {
     GemmOp g;
+    g.cfg = cfg;
+    g.splitk = nsplit;
     g.filter_step = filter_step;
     g.opA = opA; g.opB = opB; g.M = M; g.N = N; g.K = K;
     g.A = Ap; g.lda = lda; g.B = Bp; g.ldb = ldb; g.C = Cp; g.ldc = ldc;
@@ -203,47 +206,57 @@ struct chfsi_ctx_s {
   // ------------------------------------------------------------------------
   // Reduction to standard form
   // ------------------------------------------------------------------------
-  void cholesky(const zc* S, int64_t lds) {
+  // Blocked Cholesky of the m x m Hermitian matrix src (lower triangle read)
+  // into Lb (strict upper triangle zero) and Lib = Lb^{-1}; Wb is m x m work;
+  // all with leading dimension ld.  Returns 0, or the 1-based column of the
+  // first pivot that is not positive (then Lb / Lib are incomplete).
+  int chol_factor(int64_t m, const zc* src, int64_t lds, zc* Wb, zc* Lb, zc* Lib, int64_t ld) {
     const int64_t NB = CHOL_NB;
-    copy2d(S, lds, W.z(), n, n, n, st);
+    copy2d(src, lds, Wb, ld, m, m, st);
     fill_i32(flags.i(), 1, INT_MAX, st);
-    for (int64_t j0 = 0; j0 < n; j0 += NB) {
-      const int64_t nb = std::min(NB, n - j0), r = n - j0 - nb;
-      chol_diag(W.z(), n, L.z(), n, Linv.z(), n, j0, nb, flags.i(), st);
+    for (int64_t j0 = 0; j0 < m; j0 += NB) {
+      const int64_t nb = std::min(NB, m - j0), r = m - j0 - nb;
+      chol_diag(Wb, ld, Lb, ld, Lib, ld, j0, nb, flags.i(), st);
       if (r > 0) {
         // L21 = W21 L11^{-H}
-        gemm(OP_N, OP_C, r, nb, nb, 1.0, W.z() + (j0 + nb) + j0 * n, n, Linv.z() + j0 + j0 * n, n,
-             L.z() + (j0 + nb) + j0 * n, n, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER, false);
+        gemm(OP_N, OP_C, r, nb, nb, 1.0, Wb + (j0 + nb) + j0 * ld, ld, Lib + j0 + j0 * ld, ld, Lb + (j0 + nb) + j0 * ld,
+             ld, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER, false);
         // W22 -= L21 L21^H (lower tiles)
-        zc* W22 = W.z() + (j0 + nb) + (j0 + nb) * n;
-        const zc* L21 = L.z() + (j0 + nb) + j0 * n;
-        gemm(OP_N, OP_C, r, r, nb, -1.0, L21, n, L21, n, W22, n, 1.0, W22, n, 0.0, nullptr, 0, GEMM_OUT_LOWER, false);
+        zc* W22 = Wb + (j0 + nb) + (j0 + nb) * ld;
+        const zc* L21 = Lb + (j0 + nb) + j0 * ld;
+        gemm(OP_N, OP_C, r, r, nb, -1.0, L21, ld, L21, ld, W22, ld, 1.0, W22, ld, 0.0, nullptr, 0, GEMM_OUT_LOWER, false);
       }
     }
-    zero_strict_upper(L.z(), n, n, st);
+    zero_strict_upper(Lb, ld, m, st);
     CHFSI_HIP(hipMemcpyAsync(hbuf, flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
     sync();
     int info;
     std::memcpy(&info, hbuf, sizeof(int));
-    if (info != INT_MAX) {
-      have_factors = false;
-      throw Error(ST_ENOTPD, "S is not positive definite: pivot of column " + std::to_string(info - 1) + " is not positive");
-    }
-    // Linv: off-diagonal blocks by recursive doubling,
+    if (info != INT_MAX) return info;
+    // Lib: off-diagonal blocks by recursive doubling,
     //   inv([[L11, 0], [L21, L22]]) = [[X11, 0], [-X22 L21 X11, X22]]
-    for (int64_t s = NB; s < n; s *= 2) {
-      for (int64_t i0 = 0; i0 + s < n; i0 += 2 * s) {
-        const int64_t b = std::min(s, n - i0 - s);
-        const zc* L21 = L.z() + (i0 + s) + i0 * n;
-        const zc* X11 = Linv.z() + i0 + i0 * n;
-        const zc* X22 = Linv.z() + (i0 + s) + (i0 + s) * n;
-        zc* T = W.z();
-        gemm(OP_N, OP_N, b, s, s, 1.0, L21, n, X11, n, T, n, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_LOWER);
-        gemm(OP_N, OP_N, b, s, b, -1.0, X22, n, T, n, Linv.z() + (i0 + s) + i0 * n, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+    for (int64_t s = NB; s < m; s *= 2) {
+      for (int64_t i0 = 0; i0 + s < m; i0 += 2 * s) {
+        const int64_t b = std::min(s, m - i0 - s);
+        const zc* L21 = Lb + (i0 + s) + i0 * ld;
+        const zc* X11 = Lib + i0 + i0 * ld;
+        const zc* X22 = Lib + (i0 + s) + (i0 + s) * ld;
+        zc* T = Wb;
+        gemm(OP_N, OP_N, b, s, s, 1.0, L21, ld, X11, ld, T, ld, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_LOWER);
+        gemm(OP_N, OP_N, b, s, b, -1.0, X22, ld, T, ld, Lib + (i0 + s) + i0 * ld, ld, 0.0, nullptr, 0, 0.0, nullptr, 0,
              GEMM_TRI_A_LOWER);
       }
     }
-    zero_strict_upper(Linv.z(), n, n, st);
+    zero_strict_upper(Lib, ld, m, st);
+    return 0;
+  }
+
+  void cholesky(const zc* S, int64_t lds) {
+    const int info = chol_factor(n, S, lds, W.z(), L.z(), Linv.z(), n);
+    if (info) {
+      have_factors = false;
+      throw Error(ST_ENOTPD, "S is not positive definite: pivot of column " + std::to_string(info - 1) + " is not positive");
+    }
     have_factors = true;
   }
 
@@ -336,6 +349,36 @@ struct chfsi_ctx_s {
   }
 
   // ------------------------------------------------------------------------
+  // One CholeskyQR pass: G = Yin^H Yin = Lg Lg^H, Qo = Yin Lg^{-H}.  False
+  // when the Gram matrix is not numerically positive definite.
+  // ------------------------------------------------------------------------
+  bool cholqr_pass(const zc* Yin, int64_t ldy, int64_t k, zc* Qo, int64_t ldq) {
+    gemm(OP_C, OP_N, k, k, n, 1.0, Yin, ldy, Yin, ldy, G.z(), k);
+    hermitize(G.z(), k, k, st);
+    if (chol_factor(k, G.z(), k, G2.z(), Z2.z(), Ztmp.z(), k) != 0) return false;
+    gemm(OP_N, OP_C, n, k, k, 1.0, Yin, ldy, Ztmp.z(), k, Qo, ldq, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER);
+    return true;
+  }
+
+  // Orthonormal basis of span(F) (F: n x k, ld n, destroyed) into Qo.
+  // CholeskyQR2 (two passes; orthogonal to working precision while
+  // cond(F) is below ~1e7); if a Gram matrix is not positive definite the
+  // block is too ill-conditioned for it and Householder QR takes over on
+  // the best basis at hand.  Returns true when Householder was used.
+  bool orthonormalize(zc* Fp, int64_t k, zc* Qo, int64_t ldq) {
+    if (opts.qr_mode == 0) {
+      zc* mid = Wk.z();
+      if (cholqr_pass(Fp, n, k, mid, n)) {
+        if (cholqr_pass(mid, n, k, Qo, ldq)) return false;
+        qr(mid, n, k, Qo, ldq);
+        return true;
+      }
+    }
+    qr(Fp, n, k, Qo, ldq);
+    return true;
+  }
+
+  // ------------------------------------------------------------------------
   // Chebyshev filter on Y (n x ka); Yb same shape as work.  Returns the
   // buffer holding the result (Y or Yb).
   // ------------------------------------------------------------------------
@@ -356,7 +399,8 @@ struct chfsi_ctx_s {
     auto step = [&](int i, const zc* cur, int64_t ldc, zc* out, int64_t ldo, double al, double be, double ga,
                     const zc* prev, int64_t ldp) {
       if (prof) CHFSI_HIP(hipEventRecord(fev[i].a, st));
-      gemm(OP_N, OP_N, n, ka, n, al, Ap, lda, cur, ldc, out, ldo, be, cur, ldc, ga, prev, ldp, 0, false, true);
+      gemm(OP_N, OP_N, n, ka, n, al, Ap, lda, cur, ldc, out, ldo, be, cur, ldc, ga, prev, ldp, 0, true, true,
+           opts.filter_tile, opts.filter_splitk);
       if (prof) CHFSI_HIP(hipEventRecord(fev[i].b, st));
     };
     // Y_1 = (sigma1/e)(A - cI) Y_0
@@ -573,7 +617,7 @@ void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds,
     random_block(o.seed, 3u, n, k, 0, Y, n, st);
   }
   copy2d(Y, n, F, n, n, k, st);
-  c->qr(F, n, k, Qb, n);
+  inf.qr_householder += c->orthonormalize(F, k, Qb, n) ? 1 : 0;
   double a0, a;
   const double b = inf.b_upper;
   if (warm && c->warm_valid && c->warm_k == k) {
@@ -610,7 +654,7 @@ void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds,
     CHFSI_HIP(hipEventRecord(ev[1], st));
     if (cl > 0) copy2d(Y, n, F, n, n, cl, st);
     copy2d(res, n, F + cl * n, n, n, ka, st);
-    c->qr(F, n, k, Qb, n);
+    inf.qr_householder += c->orthonormalize(F, k, Qb, n) ? 1 : 0;
     CHFSI_HIP(hipEventRecord(ev[2], st));
     c->rayleigh_ritz(c->A.z(), n, Qb + cl * n, n, ka, Y + cl * n, n, mu_d, Wk, Wz);
     CHFSI_HIP(hipEventRecord(ev[3], st));
@@ -694,6 +738,7 @@ void chfsi_default_opts(chfsi_opts* o) {
   o->precision = 0;
   o->seed = 0;
   o->profile = 0;
+  o->qr_mode = 0;
 }
 
 const char* chfsi_status_string(chfsi_status s) {
@@ -716,7 +761,9 @@ chfsi_status chfsi_create(chfsi_ctx* out, int64_t n, const chfsi_opts* opts, voi
   chfsi_opts o;
   chfsi_default_opts(&o);
   if (opts) o = *opts;
-  if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX || o.precision != 0)
+  if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX || o.precision != 0 ||
+      (o.qr_mode != 0 && o.qr_mode != 1) || o.filter_tile < 0 || o.filter_tile >= zgemm_num_configs() ||
+      o.filter_splitk < 0 || o.filter_splitk > 16)
     return CHFSI_EINVAL;
   chfsi_ctx c = new (std::nothrow) chfsi_ctx_s();
   if (!c) return CHFSI_ENOMEM;
@@ -781,6 +828,11 @@ chfsi_status chfsi_filter(chfsi_ctx c, const void* A, int64_t lda, void* Y, int6
     c->ensure_small();
     c->ensure_k(k);
     c->filt_kernel_s = 0;
+    if (c->opts.filter_splitk > 1 && c->P_elems < (size_t)c->opts.filter_splitk * c->n * k) {
+      c->P_elems = (size_t)c->opts.filter_splitk * c->n * k;
+      c->P.release();
+      c->P.ensure(c->P_elems * sizeof(zc));
+    }
     zc* res = c->filter((const zc*)A, lda, (zc*)Y, ldy, c->Yb.z(), c->n, k, m, a, b, a0);
     if (res != (zc*)Y) copy2d(res, c->n, (zc*)Y, ldy, c->n, k, c->st);
     c->sync();
@@ -798,6 +850,20 @@ chfsi_status chfsi_qr(chfsi_ctx c, void* Y, int64_t ldy, int64_t k) {
     copy2d((zc*)Y, ldy, c->F.z(), c->n, c->n, k, c->st);
     c->qr(c->F.z(), c->n, k, (zc*)Y, ldy);
     c->sync();
+  });
+}
+
+chfsi_status chfsi_orthonormalize(chfsi_ctx c, void* Y, int64_t ldy, int64_t k, int32_t* used_householder) {
+  return guarded(c, [&] {
+    check_ptr(Y, "Y");
+    check_ld(ldy, c->n, "ldy");
+    if (k < 1 || k > c->n) throw Error(ST_EINVAL, "orthonormalize: need 1 <= k <= n");
+    c->ensure_small();
+    c->ensure_k(k);
+    copy2d((zc*)Y, ldy, c->F.z(), c->n, c->n, k, c->st);
+    const bool hh = c->orthonormalize(c->F.z(), k, (zc*)Y, ldy);
+    c->sync();
+    if (used_householder) *used_householder = hh ? 1 : 0;
   });
 }
 
@@ -908,7 +974,9 @@ chfsi_status chfsi_zgemm(chfsi_ctx c, int32_t opA, int32_t opB, int64_t M, int64
                          const void* A, int64_t lda, const void* B, int64_t ldb, double beta, const void* X, int64_t ldx,
                          double gamma, const void* Z, int64_t ldz, void* C, int64_t ldc, int32_t flags) {
   return guarded(c, [&] {
-    if (M < 0 || N < 0 || K < 0 || (opA != 0 && opA != 1) || (opB != 0 && opB != 1) || (flags & ~31))
+    const int structure = flags & 31, cfg = (flags >> 8) & 0xff, nsplit = (flags >> 16) & 0xff;
+    if (M < 0 || N < 0 || K < 0 || (opA != 0 && opA != 1) || (opB != 0 && opB != 1) || (flags & 0xff0000e0) ||
+        cfg >= zgemm_num_configs())
       throw Error(ST_EINVAL, "zgemm: bad sizes, ops or flags");
     if (M == 0 || N == 0) return;
     check_ptr(C, "C");
@@ -922,15 +990,16 @@ chfsi_status chfsi_zgemm(chfsi_ctx c, int32_t opA, int32_t opB, int64_t M, int64
     if (X) check_ld(ldx, M, "ldx");
     if (Z) check_ld(ldz, M, "ldz");
     c->ensure_small();
-    // split-K scratch for small outputs (large outputs never split)
-    const size_t need = (cdiv(M, 32) * cdiv(N, 32) < 256) ? (size_t)M * N * 16 : 0;
+    // split-K scratch: the requested split, or 16-way for small outputs
+    size_t need = (cdiv(M, 32) * cdiv(N, 32) < 256) ? (size_t)M * N * 16 : 0;
+    if (nsplit > 1) need = std::max(need, (size_t)M * N * nsplit);
     if (need && c->P_elems < need) {
       c->P.release();
       c->P.ensure(need * sizeof(zc));
       c->P_elems = need;
     }
     c->gemm(opA, opB, M, N, K, alpha, (const zc*)A, lda, (const zc*)B, ldb, (zc*)C, ldc, beta, (const zc*)X, ldx, gamma,
-            (const zc*)Z, ldz, flags, !(flags & GEMM_OUT_LOWER));
+            (const zc*)Z, ldz, structure, !(structure & GEMM_OUT_LOWER), false, cfg, nsplit);
     c->sync();
   });
 }

@@ -37,6 +37,8 @@ struct GemmOp {
   int batch = 1;            // strided batch count (s* are the strides)
   bool allow_splitk = true;
   bool filter_step = false;  // launch under the Chebyshev-step kernel symbol
+  int cfg = 0;              // tile configuration (0: chosen automatically)
+  int splitk = 0;           // K split (0: chosen automatically, 1: none)
 };
 
 // Scratch for split-K partial tiles.
@@ -61,5 +63,7 @@ struct ZGemmParams {
 };
 
 void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st);
+void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk);
+int zgemm_num_configs();
 
 }  // namespace chfsi

@@ -32,7 +32,7 @@ namespace chfsi {
 
 namespace {
 
-template <int OPA, int OPB, int BM, int BN, int BK>
+template <int BM, int BN, int BK>
 struct ZTile {
   static constexpr int NT = 256;
   static constexpr int PAD = 1;
@@ -40,18 +40,17 @@ struct ZTile {
   static constexpr int LDB_S = BN + PAD;
   static constexpr int EA = BM * BK / NT;  // A elements per thread per slab
   static constexpr int EB = BK * BN / NT;  // B elements per thread per slab
-  static constexpr int MI = BM / 32;       // 16-row fragments per wave
+  static constexpr int MI = BM / 32;       // 16-row fragments per wave (2x2 waves)
   static constexpr int NJ = BN / 32;       // 16-col fragments per wave
+  static constexpr int KS = BK / 4;        // MFMA depth steps per slab
   static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
   static_assert(BM * BK % NT == 0 && BK * BN % NT == 0, "tile/thread mismatch");
   static_assert(BK % 4 == 0, "BK multiple of the MFMA depth");
 };
 
-__device__ inline zc ld_z(const zc* p) { return *p; }
-
 template <int OPA, int OPB, int BM, int BN, int BK>
 __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
-  using T = ZTile<OPA, OPB, BM, BN, BK>;
+  using T = ZTile<BM, BN, BK>;
   __shared__ zc As[2][BK][T::LDA_S];
   __shared__ zc Bs[2][BK][T::LDB_S];
 
@@ -154,23 +153,45 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
     for (int64_t s = 0; s < nslab; s++) {
       const int buf = (int)(s & 1);
       if (s + 1 < nslab) load_slab(kbeg + (s + 1) * BK);
+      // fragments of depth step 0; the next step's are read while the
+      // current step's products run
+      zc a[2][T::MI], b[2][T::NJ];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        zc a[T::MI], b[T::NJ];
+      for (int i = 0; i < T::MI; i++) a[0][i] = As[buf][lk][wm0 + i * 16 + lr];
 #pragma unroll
-        for (int i = 0; i < T::MI; i++) a[i] = As[buf][kk + lk][wm0 + i * 16 + lr];
+      for (int j = 0; j < T::NJ; j++) b[0][j] = Bs[buf][lk][wn0 + j * 16 + lr];
 #pragma unroll
-        for (int j = 0; j < T::NJ; j++) b[j] = Bs[buf][kk + lk][wn0 + j * 16 + lr];
+      for (int ks = 0; ks < T::KS; ks++) {
+        const int c = ks & 1;
+        if (ks + 1 < T::KS) {
+#pragma unroll
+          for (int i = 0; i < T::MI; i++) a[c ^ 1][i] = As[buf][(ks + 1) * 4 + lk][wm0 + i * 16 + lr];
+#pragma unroll
+          for (int j = 0; j < T::NJ; j++) b[c ^ 1][j] = Bs[buf][(ks + 1) * 4 + lk][wn0 + j * 16 + lr];
+        }
+        // D[n][m] += B[k][n] A[m][k]  (transposed product: result lanes run
+        // down columns).  The four real products are issued type by type so
+        // that dependent accumulations are MI*NJ instructions apart.
 #pragma unroll
         for (int i = 0; i < T::MI; i++)
 #pragma unroll
-          for (int j = 0; j < T::NJ; j++) {
-            // D[n][m] += B[k][n] A[m][k]  (transposed product: result lanes run down columns)
-            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j].x, a[i].x, accR[i][j], 0, 0, 0);
-            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j].y, a[i].x, accI[i][j], 0, 0, 0);
-            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-b[j].y, a[i].y, accR[i][j], 0, 0, 0);
-            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j].x, a[i].y, accI[i][j], 0, 0, 0);
-          }
+          for (int j = 0; j < T::NJ; j++)
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[c][j].x, a[c][i].x, accR[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < T::MI; i++)
+#pragma unroll
+          for (int j = 0; j < T::NJ; j++)
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[c][j].y, a[c][i].x, accI[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < T::MI; i++)
+#pragma unroll
+          for (int j = 0; j < T::NJ; j++)
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-b[c][j].y, a[c][i].y, accR[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < T::MI; i++)
+#pragma unroll
+          for (int j = 0; j < T::NJ; j++)
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[c][j].x, a[c][i].y, accI[i][j], 0, 0, 0);
       }
       if (s + 1 < nslab) store_slab(buf ^ 1);
       __syncthreads();
@@ -214,20 +235,20 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
       }
 }
 
-template <int OPA, int OPB, int BM, int BN, int BK>
-__global__ void __launch_bounds__(256, 2) zgemm_kernel(ZGemmParams p) {
+template <int OPA, int OPB, int BM, int BN, int BK, int MINB>
+__global__ void __launch_bounds__(256, MINB) zgemm_kernel(ZGemmParams p) {
   zgemm_body<OPA, OPB, BM, BN, BK>(p);
 }
 
 // One degree step of the Chebyshev filter: the same body, launched under its
 // own symbol so that profiles separate the filter from the other products.
-template <int BM, int BN, int BK>
-__global__ void __launch_bounds__(256, 2) chebyshev_step_f64(ZGemmParams p) {
+template <int BM, int BN, int BK, int MINB>
+__global__ void __launch_bounds__(256, MINB) chebyshev_step_f64(ZGemmParams p) {
   zgemm_body<OP_N, OP_N, BM, BN, BK>(p);
 }
 
 // Combine split-K partial tiles and apply the epilogue.
-__global__ void zgemm_splitk_reduce(ZGemmParams p) {
+__device__ __forceinline__ void splitk_reduce_body(const ZGemmParams& p) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int batch = blockIdx.y;
   if (e >= p.M * p.N) return;
@@ -245,27 +266,131 @@ __global__ void zgemm_splitk_reduce(ZGemmParams p) {
   p.C[(int64_t)batch * p.sC + m + n * p.ldc] = v;
 }
 
-template <int OPA, int OPB, int BM, int BN, int BK>
-void launch_cfg(ZGemmParams& p, int batch, bool filter_step, hipStream_t st) {
+__global__ void zgemm_splitk_reduce(ZGemmParams p) { splitk_reduce_body(p); }
+
+// The filter step's split-K combination (its own symbol, like the step).
+__global__ void chebyshev_step_reduce_f64(ZGemmParams p) { splitk_reduce_body(p); }
+
+// Tile configurations.  All use 256 threads (2x2 waves).
+struct Cfg {
+  int bm, bn, bk, minb;
+  double eff;  // relative per-tile efficiency used by the chooser
+};
+constexpr Cfg CFGS[] = {
+    {0, 0, 0, 0, 0.0},        // 0: automatic
+    {64, 64, 16, 2, 1.0},     // 1
+    {32, 32, 16, 2, 0.55},    // 2
+    {64, 64, 8, 2, 1.0},      // 3
+    {128, 64, 8, 2, 1.05},    // 4
+    {64, 128, 8, 2, 1.05},    // 5
+    {128, 128, 8, 1, 1.1},    // 6
+    {64, 32, 16, 2, 0.8},     // 7
+};
+constexpr int NCFG = sizeof(CFGS) / sizeof(CFGS[0]);
+
+template <int OPA, int OPB, int BM, int BN, int BK, int MINB>
+void launch_one(ZGemmParams& p, int batch, bool filter_step, hipStream_t st) {
   p.tiles_m = (int)cdiv(p.M, BM);
   p.tiles_n = (int)cdiv(p.N, BN);
   dim3 grid((unsigned)((int64_t)p.tiles_m * p.tiles_n), (unsigned)(batch * p.splitk));
   if (OPA == OP_N && OPB == OP_N && filter_step)
-    hipLaunchKernelGGL((chebyshev_step_f64<BM, BN, BK>), grid, dim3(256), 0, st, p);
+    hipLaunchKernelGGL((chebyshev_step_f64<BM, BN, BK, MINB>), grid, dim3(256), 0, st, p);
   else
-    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, BM, BN, BK>), grid, dim3(256), 0, st, p);
+    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, BM, BN, BK, MINB>), grid, dim3(256), 0, st, p);
   CHFSI_CHECK_LAUNCH();
 }
 
-template <int BM, int BN, int BK>
-void launch_ops(int opA, int opB, ZGemmParams& p, int batch, bool filter_step, hipStream_t st) {
-  if (opA == OP_N && opB == OP_N) launch_cfg<OP_N, OP_N, BM, BN, BK>(p, batch, filter_step, st);
-  else if (opA == OP_N && opB == OP_C) launch_cfg<OP_N, OP_C, BM, BN, BK>(p, batch, filter_step, st);
-  else if (opA == OP_C && opB == OP_N) launch_cfg<OP_C, OP_N, BM, BN, BK>(p, batch, filter_step, st);
-  else launch_cfg<OP_C, OP_C, BM, BN, BK>(p, batch, filter_step, st);
+template <int OPA, int OPB>
+void launch_cfg(int cfg, ZGemmParams& p, int batch, bool filter_step, hipStream_t st) {
+  switch (cfg) {
+    case 1: launch_one<OPA, OPB, 64, 64, 16, 2>(p, batch, filter_step, st); break;
+    case 2: launch_one<OPA, OPB, 32, 32, 16, 2>(p, batch, filter_step, st); break;
+    case 7: launch_one<OPA, OPB, 64, 32, 16, 2>(p, batch, filter_step, st); break;
+    default:
+      if constexpr (OPA == OP_N && OPB == OP_N) {
+        switch (cfg) {
+          case 3: launch_one<OPA, OPB, 64, 64, 8, 2>(p, batch, filter_step, st); return;
+          case 4: launch_one<OPA, OPB, 128, 64, 8, 2>(p, batch, filter_step, st); return;
+          case 5: launch_one<OPA, OPB, 64, 128, 8, 2>(p, batch, filter_step, st); return;
+          case 6: launch_one<OPA, OPB, 128, 128, 8, 1>(p, batch, filter_step, st); return;
+          default: break;
+        }
+      }
+      throw Error(ST_EINVAL, "zgemm: tile configuration " + std::to_string(cfg) + " not available for these ops");
+  }
+}
+
+void launch_ops(int cfg, int opA, int opB, ZGemmParams& p, int batch, bool filter_step, hipStream_t st) {
+  if (opA == OP_N && opB == OP_N) launch_cfg<OP_N, OP_N>(cfg, p, batch, filter_step, st);
+  else if (opA == OP_N && opB == OP_C) launch_cfg<OP_N, OP_C>(cfg, p, batch, filter_step, st);
+  else if (opA == OP_C && opB == OP_N) launch_cfg<OP_C, OP_N>(cfg, p, batch, filter_step, st);
+  else launch_cfg<OP_C, OP_C>(cfg, p, batch, filter_step, st);
 }
 
 }  // namespace
+
+int zgemm_num_configs() { return NCFG; }
+
+// Choose the tile configuration and the K split: maximise the estimated
+// throughput = per-tile efficiency x occupancy of the chip's workgroup slots
+// (256 CUs x workgroups per CU), charging split-K for its partial-tile traffic.
+void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
+  const int batch = g.batch > 0 ? g.batch : 1;
+  const bool nn = g.opA == OP_N && g.opB == OP_N;
+  // Tall, deep products (the filter's A Y_i and the Rayleigh-Ritz A Q): rules
+  // read off a sweep of every configuration and split on MI355X (n = 4000 and
+  // 10000, k_a from 16 to 660).  The best choices keep each workgroup's K
+  // range near 1000 (the A panels of the workgroups resident on one XCD then
+  // fit its 4 MB L2) and use the widest tile that still gives >= ~500
+  // workgroups.
+  if (nn && batch == 1 && g.M >= 1024 && g.K >= 1024 && !(g.flags & GEMM_OUT_LOWER)) {
+    int c;
+    if (g.N >= 384) c = 3;        // 64 x 64 x 8
+    else if (g.N >= 160) c = 4;   // 128 x 64 x 8
+    else if (g.N >= 96) c = 5;    // 64 x 128 x 8
+    else c = 7;                   // 64 x 32 x 16
+    int sk = (int)std::min<int64_t>(8, std::max<int64_t>(1, (g.K + 500) / 1000));
+    if (g.N < 96) sk = 8;
+    while (sk > 1 && (!g.allow_splitk || !P_elems || (size_t)sk * g.M * g.N > (size_t)P_elems ||
+                      g.K < (int64_t)sk * 4 * CFGS[c].bk))
+      sk /= 2;
+    cfg = c;
+    splitk = sk;
+    return;
+  }
+  double best = -1.0;
+  cfg = 1;
+  splitk = 1;
+  const int cands_nn[] = {1, 2, 4, 5, 7};
+  const int cands_other[] = {1, 2, 7};
+  const int* cands = nn ? cands_nn : cands_other;
+  const int ncand = nn ? 5 : 3;
+  for (int ci = 0; ci < ncand; ci++) {
+    const Cfg& c = CFGS[cands[ci]];
+    const int64_t tiles = cdiv(g.M, c.bm) * cdiv(g.N, c.bn) * batch;
+    const int64_t slots = 256LL * c.minb;
+    // useful fraction of the tile (ragged edges)
+    const double fill = (double)(g.M * g.N) / (double)(cdiv(g.M, c.bm) * c.bm * cdiv(g.N, c.bn) * c.bn);
+    for (int sk = 1; sk <= 16; sk *= 2) {
+      if (sk > 1) {
+        if (!g.allow_splitk || (g.flags & GEMM_OUT_LOWER) || !P_elems) break;
+        if (g.K < (int64_t)sk * 4 * c.bk) break;
+        if ((size_t)sk * g.M * g.N * batch > (size_t)P_elems) break;
+      }
+      const int64_t work = tiles * sk;
+      const double waves = std::ceil((double)work / (double)slots);
+      const double occ = (double)work / (waves * (double)slots);
+      // split-K traffic relative to the product's own reads
+      const double extra = sk > 1 ? (double)sk * 2.0 * g.M * g.N / (double)(g.M * g.K + g.K * g.N + 1) : 0.0;
+      const double score = c.eff * fill * occ / (1.0 + 0.5 * extra);
+      if (score > best * 1.02) {
+        best = score;
+        cfg = cands[ci];
+        splitk = sk;
+      }
+    }
+  }
+}
 
 void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return;
@@ -278,34 +403,33 @@ void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st) {
   p.Z = g.Z; p.ldz = g.ldz; p.sZ = g.sZ;
   p.alpha = g.alpha; p.beta = g.beta; p.gamma = g.gamma;
   p.flags = g.flags;
-  p.splitk = 1;
-  p.kchunk = g.K;
-  p.P = nullptr;
   const int batch = g.batch > 0 ? g.batch : 1;
 
-  // tile shape: 64x64 when there are enough tiles to fill the chip
-  const bool big = cdiv(g.M, 64) * cdiv(g.N, 64) * batch >= 192;
-  const int bm = big ? 64 : 32, bn = big ? 64 : 32, bk = 16;
-  int64_t tiles = cdiv(g.M, bm) * cdiv(g.N, bn) * batch;
-
-  // split K for small, deep products (tiles < 1 per CU)
-  if (g.allow_splitk && !(g.flags & GEMM_OUT_LOWER) && tiles < 256 && g.K >= 8 * bk && w.P) {
-    int64_t want = cdiv(512, tiles);
-    int64_t maxsplit = g.K / (4 * bk);  // at least 4 slabs per split
-    int64_t cap = (int64_t)(w.P_elems / ((size_t)g.M * (size_t)g.N * (size_t)batch));
-    int64_t sk = std::min(std::min(want, maxsplit), std::min(cap, (int64_t)64));
-    if (sk >= 2) {
-      p.splitk = (int)sk;
-      p.kchunk = cdiv(cdiv(g.K, sk), bk) * bk;
-      p.splitk = (int)cdiv(g.K, p.kchunk);
-      p.P = w.P;
-    }
+  int cfg = g.cfg, sk = g.splitk;
+  if (cfg < 0 || cfg >= NCFG || sk < 0) throw Error(ST_EINVAL, "zgemm: bad tile configuration or split");
+  if (cfg == 0 || sk == 0) {
+    int c2, s2;
+    zgemm_choose(g, w.P ? (int64_t)w.P_elems : 0, c2, s2);
+    if (cfg == 0) cfg = c2;
+    if (sk == 0) sk = (g.cfg == 0) ? s2 : 1;
   }
-  if (big) launch_ops<64, 64, 16>(g.opA, g.opB, p, batch, g.filter_step, st);
-  else launch_ops<32, 32, 16>(g.opA, g.opB, p, batch, g.filter_step, st);
+  if (sk > 1) {
+    if (!w.P || (size_t)sk * g.M * g.N * batch > w.P_elems || (g.flags & GEMM_OUT_LOWER))
+      throw Error(ST_EINVAL, "zgemm: split-K scratch too small or not allowed");
+    const int bk = CFGS[cfg].bk;
+    p.kchunk = cdiv(cdiv(g.K, sk), bk) * bk;
+    p.splitk = (int)std::max<int64_t>(1, cdiv(g.K, p.kchunk));
+    p.P = w.P;
+  } else {
+    p.splitk = 1;
+    p.kchunk = g.K;
+    p.P = nullptr;
+  }
+  launch_ops(cfg, g.opA, g.opB, p, batch, g.filter_step, st);
   if (p.splitk > 1) {
     dim3 grid((unsigned)cdiv(g.M * g.N, 256), (unsigned)batch);
-    hipLaunchKernelGGL(zgemm_splitk_reduce, grid, dim3(256), 0, st, p);
+    if (g.filter_step) hipLaunchKernelGGL(chebyshev_step_reduce_f64, grid, dim3(256), 0, st, p);
+    else hipLaunchKernelGGL(zgemm_splitk_reduce, grid, dim3(256), 0, st, p);
     CHFSI_CHECK_LAUNCH();
   }
 }

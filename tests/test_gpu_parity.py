@@ -181,6 +181,42 @@ def test_qr_matches_oracle(lib, n, k):
     assert _rel(Q, Qr) <= 1e-12
 
 
+@pytest.mark.parametrize("n,k", [(300, 70), (1000, 130), (64, 64), (257, 1)])
+def test_orthonormalize_spans_the_oracle_basis(lib, n, k):
+    """The solver's re-orthonormalization (CholeskyQR2) spans the same space
+    as the oracle's Householder Q, to working precision."""
+    rng = _rng(n + 3 * k)
+    Y = _cg(rng, (n, k))
+    Qr, _ = oracle.householder_qr(Y)
+    ctx = lib.create(n)
+    Yt = _t(Y)
+    used_hh = lib.orthonormalize(ctx, Yt)
+    Q = _np(Yt)
+    assert not used_hh
+    assert np.abs(Q.conj().T @ Q - np.eye(k)).max() <= 1e-13
+    assert np.linalg.norm(Q - Qr @ (Qr.conj().T @ Q), 2) <= 1e-12
+
+
+def test_orthonormalize_falls_back_on_ill_conditioned_block(lib):
+    """cond ~ 1e13: the Gram matrix is not numerically positive definite,
+    Householder takes over and the result is still orthonormal and spans the
+    dominant directions."""
+    rng = _rng(5)
+    n, k = 400, 30
+    U, _ = np.linalg.qr(_cg(rng, (n, k)))
+    V, _ = np.linalg.qr(_cg(rng, (k, k)))
+    Y = U @ np.diag(np.logspace(0, -13, k)) @ V
+    ctx = lib.create(n)
+    Yt = _t(Y)
+    used_hh = lib.orthonormalize(ctx, Yt)
+    Q = _np(Yt)
+    assert used_hh
+    assert np.abs(Q.conj().T @ Q - np.eye(k)).max() <= 1e-13
+    # the leading directions (singular values >= 1e-4) are captured
+    lead = U[:, :9]
+    assert np.linalg.norm(lead - Q @ (Q.conj().T @ lead), 2) <= 1e-9
+
+
 @pytest.mark.parametrize("k", [1, 2, 40, 96, 97, 130])
 def test_eigh_matches_oracle(lib, k):
     rng = _rng(k)
@@ -307,6 +343,16 @@ def test_solve_config0_matches_oracle(lib):
     assert info["filter_flops"] > 0 and info["iterations"] > 1
 
 
+def test_solve_config0_householder_mode_matches_oracle(lib):
+    p = workloads.make_problem(512, 0)
+    ref = oracle.solve(p.H, p.S, 51, 13, tol=1e-10, degree=10, seed=0)
+    ctx = lib.create(512, degree=10, seed=0, qr_mode=1)
+    ev, X, info, st = lib.solve(ctx, _t(p.H), _t(p.S), 51, 13, tol=1e-10)
+    assert st == 0 and info["qr_householder"] == info["iterations"] + 1
+    assert np.abs(ev - ref["evals"]).max() <= 1e-12 * 100
+    _check_solution(p, ev, _np(X), 51)
+
+
 def test_solve_ragged_sizes_against_brute_force(lib):
     n, nev, nex = 333, 17, 6
     p = workloads.make_problem(n, 41)
@@ -396,3 +442,58 @@ def test_row_major_input_is_not_transposed(lib):
     Xn = _np(X)
     r = _checks.gen_residuals(p.H, p.S, Xn, ev)
     assert r.max() <= 1e-10 * _checks.spectral_norm(p.H)
+
+
+# --------------------------------------------------------------------------
+# full sizes of the benchmark (sampled outputs / properties)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,k,m", [(4000, 440, 20), (4000, 37, 20), (10000, 660, 20)])
+def test_filter_full_size_sampled_columns(lib, n, k, m):
+    """The filter at benchmark sizes (automatic tile / split choice, as the
+    solver launches it); the oracle recomputes a few sampled columns (the
+    filter acts on columns independently)."""
+    import torch
+    rng = _rng(n + k)
+    lam = np.sort(workloads.spectrum(n, rng))
+    G = torch.from_numpy(_cg(rng, (n, n))).cuda()
+    Q, _ = torch.linalg.qr(G)
+    del G
+    A = (Q * torch.from_numpy(lam).cuda().to(torch.complex128)[None, :]) @ Q.conj().T
+    A = (A + A.conj().T) / 2
+    del Q
+    A = A.mT.contiguous().mT
+    Y = _cg(rng, (n, k))
+    a, b, a0 = float(lam[min(k, n - 1)]), float(lam[-1] * 1.1), float(lam[0])
+    ctx = lib.create(n)
+    Yt = _t(Y)
+    lib.filter(ctx, A, Yt, m, a, b, a0)
+    cols = sorted(set([0, k // 2, k - 1]))
+    An = A.cpu().numpy()
+    ref = oracle.chebyshev_filter(An, Y[:, cols], m, a, b, a0)
+    got = _np(Yt)[:, cols]
+    assert _rel(got, ref) <= 1e-12
+
+
+def test_solve_full_size_first_problem_of_sequence(lib):
+    """n=4000, nev=400, nex=40, degree 20 (the benchmark's sequence, first
+    problem: spectrum known by construction)."""
+    import torch
+    p = workloads.make_problem_torch(4000, 1, device="cuda")
+    ctx = lib.create(4000, degree=20, seed=0)
+    ev, X, info, st = lib.solve(ctx, p["H"], p["S"], 400, 40, tol=1e-10)
+    assert st == 0
+    lam = np.sort(p["lam"])[:400]
+    H, S = p["H"], p["S"]
+    v = torch.ones(4000, dtype=torch.complex128, device="cuda")
+    for _ in range(50):
+        v = H @ v
+        v = v / torch.linalg.vector_norm(v)
+    hn = float(torch.linalg.vector_norm(H @ v))
+    ok, dmax = _checks.eig_ok(ev, lam, hn)
+    assert ok, dmax
+    lt = torch.from_numpy(ev).cuda().to(torch.complex128)
+    R = H @ X - (S @ X) * lt[None, :]
+    assert float(torch.linalg.vector_norm(R, dim=0).max()) <= 1e-10 * hn
+    G = X.conj().T @ (S @ X)
+    assert float((G - torch.eye(400, dtype=torch.complex128, device="cuda")).abs().max()) <= 1e-12
