@@ -71,6 +71,52 @@ def residual_check(p, evals, X):
     return float(torch.linalg.vector_norm(R, dim=0).max()) / hn
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "chebyshev_step_f64_seq4000_traffic.md")
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1305_5120_amd", "csrc", "zgemm.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per filter launch from the committed counter summary, or
+    None when the summary is absent, for another workload, or was taken on a
+    different version of the kernel source."""
+    import hashlib
+    if workload != "seq4000" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+CAL_N = 6000
+
+
+def calibrate_copy():
+    """Plain device copies of known size for scaling the memory counters of a
+    profiled run: the library's k_copy2d kernel moving contiguous
+    6000 x 6000 complex128 matrices (576,000,000 bytes read and written per
+    launch; the reduction copies S once and chfsi_copy_factors copies A, L
+    and L^{-1})."""
+    import torch
+    from paper_1305_5120_amd import chfsi
+    n = CAL_N
+    eye = torch.eye(n, dtype=torch.complex128, device="cuda").mT.contiguous().mT
+    ctx = chfsi.create(n)
+    chfsi.reduce(ctx, eye, eye)
+    chfsi.copy_factors(ctx)
+    torch.cuda.synchronize()
+    ctx.release()
+    log(f"[bench] copy calibration: k_copy2d launches with grid {n * n} moving {16 * n * n} bytes each way")
+
+
 def cpu_baseline(cfg, gpu_filter_flops_per_solve, target_seconds=12.0):
     """Time the CPU oracle's filter on a bounded sample of the same problem
     and scale it to solves/s of the filter work of one GPU solve."""
@@ -94,14 +140,16 @@ def cpu_baseline(cfg, gpu_filter_flops_per_solve, target_seconds=12.0):
     oracle.chebyshev_filter(A, Y, m, lo, hi, float(lam.min()))
     dt = time.perf_counter() - t0
     rate = 8.0 * n * n * k * m / dt
+    # scale the sample (columns first, then degree) to about target_seconds
     k2 = int(max(8, min(cfg["nev"] + cfg["nex"], rate * target_seconds / (8.0 * n * n * m))))
-    if k2 > k:
+    m2 = int(max(2, min(cfg["degree"], round(rate * target_seconds / (8.0 * n * n * k2)))))
+    if k2 > k or m2 > m:
         Y = oracle.gauss_block(1, 3, n, k2)
         t0 = time.perf_counter()
-        oracle.chebyshev_filter(A, Y, m, lo, hi, float(lam.min()))
+        oracle.chebyshev_filter(A, Y, m2, lo, hi, float(lam.min()))
         dt = time.perf_counter() - t0
-        rate = 8.0 * n * n * k2 * m / dt
-        k = k2
+        rate = 8.0 * n * n * k2 * m2 / dt
+        k, m = k2, m2
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     solve_s = gpu_filter_flops_per_solve / rate
     return {
@@ -124,6 +172,8 @@ def main():
     ap.add_argument("--workload", default="seq4000", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not time filter launches with events")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed region, run a device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs one problem sequence on one GPU; --gpus must be 1",
@@ -175,6 +225,10 @@ def main():
     launches = sum(i["filter_launches"] for i in infos)
     achieved = flops / fsec / 1e12 if fsec > 0 else None
     phase = {k: sum(i[k] for i in infos) for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid")}
+    # algorithmic bytes per launch: A once, Y_i and Y_{i-1} read, Y_{i+1}
+    # written; 8 n^2 k_a flops per launch give the mean k_a
+    mean_ka = (flops / launches) / (8.0 * n * n) if launches else 0.0
+    alg_bytes = 16.0 * n * n + 48.0 * n * mean_ka
     out = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -197,8 +251,13 @@ def main():
         "iterations": [i["iterations"] for i in infos],
         "phase_seconds": phase,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
-                     "frac": (achieved / PEAK_FP64_MFMA) if achieved else None, "traffic": None},
+                     "frac": (achieved / PEAK_FP64_MFMA) if achieved else None,
+                     "traffic": measured_traffic(args.workload),
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "algorithmic_flops_per_launch": flops / launches if launches else None},
     }
+    if args.calibrate_copy:
+        calibrate_copy()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(cfg, flops / len(infos))

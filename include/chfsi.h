@@ -58,7 +58,10 @@ typedef struct {
   int32_t degree;        /* Chebyshev filter degree m (default 20) */
   int32_t max_iter;      /* outer iterations before CHFSI_ENOCONV (default 1000) */
   int32_t lanczos_steps; /* Lanczos steps for the spectral bound (default 10, at most 96) */
-  int32_t precision;     /* 0: FP64 throughout (the only mode of this version) */
+  int32_t precision;     /* 0: FP64 throughout; 1: mixed - the Chebyshev filter in complex FP32
+                            (FP32 matrix cores, FP32 accumulation) while the leading unconverged
+                            residual is above 1e-5 h_H and falling, FP64 for everything else and
+                            for the final sweeps; accepted pairs meet the same FP64 tolerance */
   uint64_t seed;         /* Philox4x32-10 seed of the random start vectors (default 0) */
   int32_t profile;       /* 1: time every filter kernel launch with device events */
   int32_t qr_mode;       /* re-orthonormalization: 0 = CholeskyQR2, Householder when a Gram
@@ -83,6 +86,10 @@ typedef struct {
   double h_H;              /* Lanczos estimate of ||H||_2 (lower bound); scale of the lock test */
   double a0, a;            /* filter scale point and lower end of the damped interval at exit */
   double max_rel_residual; /* max_j ||H x_j - lambda_j S x_j||_2 / h_H over returned pairs */
+  int32_t iterations_fp32;      /* outer iterations whose filter ran in FP32 (precision = 1) */
+  int32_t filter_launches_fp32; /* of filter_launches, those in FP32 */
+  double filter_flops_fp32;     /* of filter_flops, the FP32 part */
+  double filter_kernel_seconds_fp32; /* of filter_kernel_seconds, the FP32 part */
 } chfsi_info;
 
 /* Fill *opts with the defaults listed above. */
@@ -139,7 +146,9 @@ chfsi_status chfsi_copy_factors(chfsi_ctx ctx, void* A, int64_t lda, void* L, in
 
 /* Chebyshev filter (eq. (3), scaled and shifted): Y (device n x k) is
  * overwritten with p(A) Y, p(t) = C_m((t - c)/e) / C_m((a0 - c)/e),
- * c = (a + b)/2, e = (b - a)/2.  Requires b > a, m >= 1. */
+ * c = (a + b)/2, e = (b - a)/2.  Requires b > a, m >= 1.  With the context's
+ * precision = 1 the recurrence runs in complex FP32 (A and Y rounded to FP32,
+ * the result widened back to FP64). */
 chfsi_status chfsi_filter(chfsi_ctx ctx, const void* A, int64_t lda, void* Y, int64_t ldy, int64_t k, int32_t m, double a,
                           double b, double a0);
 

@@ -46,7 +46,9 @@ class Info(ctypes.Structure):
                 ("filter_flops", c_dbl), ("filter_kernel_seconds", c_dbl),
                 ("t_reduce", c_dbl), ("t_lanczos", c_dbl), ("t_filter", c_dbl), ("t_qr", c_dbl), ("t_rr", c_dbl),
                 ("t_resid", c_dbl), ("t_total", c_dbl), ("b_upper", c_dbl), ("theta_min", c_dbl), ("h_H", c_dbl),
-                ("a0", c_dbl), ("a", c_dbl), ("max_rel_residual", c_dbl)]
+                ("a0", c_dbl), ("a", c_dbl), ("max_rel_residual", c_dbl),
+                ("iterations_fp32", c_i32), ("filter_launches_fp32", c_i32), ("filter_flops_fp32", c_dbl),
+                ("filter_kernel_seconds_fp32", c_dbl)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -58,8 +58,10 @@ struct chfsi_ctx_s {
   hipStream_t st = nullptr;
   std::string err;
 
-  // n x n: standard form, Cholesky factor, its inverse, work
-  DBuf A, L, Linv, W;
+  // n x n: standard form, Cholesky factor, its inverse, work; FP32 copy of A
+  DBuf A, L, Linv, W, A32;
+  // FP32 filter blocks (mixed precision)
+  DBuf Y32, Y32b;
   bool have_factors = false;
   // n x k blocks
   DBuf Y, Yb, F, Qb, Wk, Wz;
@@ -81,11 +83,19 @@ struct chfsi_ctx_s {
   int64_t warm_k = 0;
   double warm_a0 = 0, warm_a = 0;
 
-  // filter timing
+  // filter timing and work, per precision (0 FP64, 1 FP32)
   std::vector<EventPair> fev;
-  double filt_kernel_s = 0;
-  int filt_launches = 0;
-  double filt_flops = 0;
+  double filt_kernel_s[2] = {0, 0};
+  int filt_launches[2] = {0, 0};
+  double filt_flops[2] = {0, 0};
+  int last_filter_prec = 0;
+  void reset_filter_stats() {
+    for (int i = 0; i < 2; i++) {
+      filt_kernel_s[i] = 0;
+      filt_launches[i] = 0;
+      filt_flops[i] = 0;
+    }
+  }
 
   GemmWork gw() const { return GemmWork{P.z(), P_elems}; }
 
@@ -170,7 +180,7 @@ struct chfsi_ctx_s {
   void sync() { CHFSI_HIP(hipStreamSynchronize(st)); }
 
   void free_all() {
-    for (DBuf* b : {&A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
+    for (DBuf* b : {&A32, &Y32, &Y32b, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
                     &flags, &P, &hpart, &htop, &tau, &Tall, &gram, &Vp, &Wt, &W2, &LV, &Lw, &Lh, &Lab, &mvpart, &Tsm,
                     &Tz, &Tz2, &Tw, &npart})
       b->release();
@@ -384,6 +394,12 @@ struct chfsi_ctx_s {
   // ------------------------------------------------------------------------
   zc* filter(const zc* Ap, int64_t lda, zc* Yp, int64_t ldy, zc* Ybp, int64_t ldyb, int64_t ka, int m, double a, double b,
              double a0) {
+    return static_cast<zc*>(filter_any(PREC_F64, Ap, lda, Yp, ldy, Ybp, ldyb, ka, m, a, b, a0));
+  }
+
+  // The filter in either precision: element type zc (FP64) or cc (FP32).
+  void* filter_any(int prec, const void* Ap, int64_t lda, void* Yp, int64_t ldy, void* Ybp, int64_t ldyb, int64_t ka, int m,
+                   double a, double b, double a0) {
     const double e = (b - a) / 2.0, c = (b + a) / 2.0;
     const double sigma1 = e / (a0 - c);
     const double tau_ = 2.0 / sigma1;
@@ -396,17 +412,25 @@ struct chfsi_ctx_s {
         fev.push_back(ep);
       }
     }
-    auto step = [&](int i, const zc* cur, int64_t ldc, zc* out, int64_t ldo, double al, double be, double ga,
-                    const zc* prev, int64_t ldp) {
+    auto step = [&](int i, const void* cur, int64_t ldc, void* out, int64_t ldo, double al, double be, double ga,
+                    const void* prev, int64_t ldp) {
       if (prof) CHFSI_HIP(hipEventRecord(fev[i].a, st));
-      gemm(OP_N, OP_N, n, ka, n, al, Ap, lda, cur, ldc, out, ldo, be, cur, ldc, ga, prev, ldp, 0, true, true,
-           opts.filter_tile, opts.filter_splitk);
+      GemmOp g;
+      g.prec = prec;
+      g.M = n; g.N = ka; g.K = n;
+      g.A = Ap; g.lda = lda; g.B = cur; g.ldb = ldc; g.C = out; g.ldc = ldo;
+      g.X = cur; g.ldx = ldc; g.Z = prev; g.ldz = ldp;
+      g.alpha = al; g.beta = be; g.gamma = ga;
+      g.filter_step = true;
+      g.cfg = opts.filter_tile;
+      g.splitk = opts.filter_splitk;
+      zgemm(g, gw(), st);
       if (prof) CHFSI_HIP(hipEventRecord(fev[i].b, st));
     };
     // Y_1 = (sigma1/e)(A - cI) Y_0
     const double al1 = sigma1 / e;
     step(0, Yp, ldy, Ybp, ldyb, al1, -al1 * c, 0.0, nullptr, 0);
-    zc *cur = Ybp, *prev = Yp;
+    void *cur = Ybp, *prev = Yp;
     int64_t ldc = ldyb, ldp = ldy;
     double sigma = sigma1;
     for (int i = 2; i <= m; i++) {
@@ -418,8 +442,9 @@ struct chfsi_ctx_s {
       std::swap(ldc, ldp);
       sigma = sn;
     }
-    filt_launches += m;
-    filt_flops += 8.0 * (double)n * (double)n * (double)ka * (double)m;
+    filt_launches[prec] += m;
+    filt_flops[prec] += 8.0 * (double)n * (double)n * (double)ka * (double)m;
+    last_filter_prec = prec;
     return cur;
   }
 
@@ -428,7 +453,7 @@ struct chfsi_ctx_s {
     for (int i = 0; i < m && i < (int)fev.size(); i++) {
       float ms = 0.f;
       CHFSI_HIP(hipEventElapsedTime(&ms, fev[i].a, fev[i].b));
-      filt_kernel_s += ms * 1e-3;
+      filt_kernel_s[last_filter_prec] += ms * 1e-3;
     }
   }
 
@@ -565,9 +590,7 @@ void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds,
   auto secs = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
     return std::chrono::duration<double>(b - a).count();
   };
-  c->filt_kernel_s = 0;
-  c->filt_launches = 0;
-  c->filt_flops = 0;
+  c->reset_filter_stats();
 
   c->ensure_nn();
   c->ensure_small();
@@ -582,6 +605,13 @@ void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds,
 
   auto t0 = now();
   c->reduce(H, ldh, S, lds);
+  const bool mixed = o.precision == 1;
+  if (mixed) {
+    c->A32.ensure((size_t)n * n * sizeof(cc));
+    c->Y32.ensure((size_t)n * k * sizeof(cc));
+    c->Y32b.ensure((size_t)n * k * sizeof(cc));
+    to_f32(c->A.z(), n, (cc*)c->A32.p, n, n, n, st);
+  }
   c->sync();
   inf.t_reduce = secs(t0, now());
 
@@ -647,13 +677,39 @@ void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds,
       for (auto e : v) (void)hipEventDestroy(e);
     }
   } evg{ev};
+  // Mixed precision: the filter runs in complex FP32 while the first active
+  // column's generalized residual is above MIXED_SWITCH * h_H and still
+  // falling at least twofold per FP32 iteration; that column then gets FP64
+  // filtering until it locks.  Everything else stays FP64, and locking uses
+  // the FP64 residuals, so the accepted pairs meet the same tolerance.
+  const double MIXED_SWITCH = 1e-5;
+  int64_t fp64_col = -1, prev_col = -1;
+  double prev_rho = INFINITY;
+  bool prev32 = false;
   for (it = 1; it <= o.max_iter; it++) {
     const int64_t ka = k - cl;
+    bool use32 = false;
+    if (mixed) {
+      use32 = fp64_col != cl;
+      if (use32 && prev_col == cl && prev_rho <= MIXED_SWITCH * inf.h_H) {
+        use32 = false;
+        fp64_col = cl;
+      }
+    }
     CHFSI_HIP(hipEventRecord(ev[0], st));
-    zc* res = c->filter(c->A.z(), n, Y + cl * n, n, Yb + cl * n, n, ka, o.degree, a, b, a0);
+    if (use32) {
+      cc* y32 = (cc*)c->Y32.p;
+      cc* y32b = (cc*)c->Y32b.p;
+      to_f32(Y + cl * n, n, y32, n, n, ka, st);
+      void* r32 = c->filter_any(PREC_F32, c->A32.p, n, y32, n, y32b, n, ka, o.degree, a, b, a0);
+      to_f64((const cc*)r32, n, F + cl * n, n, n, ka, st);
+      inf.iterations_fp32++;
+    } else {
+      zc* res = c->filter(c->A.z(), n, Y + cl * n, n, Yb + cl * n, n, ka, o.degree, a, b, a0);
+      copy2d(res, n, F + cl * n, n, n, ka, st);
+    }
     CHFSI_HIP(hipEventRecord(ev[1], st));
     if (cl > 0) copy2d(Y, n, F, n, n, cl, st);
-    copy2d(res, n, F + cl * n, n, n, ka, st);
     inf.qr_householder += c->orthonormalize(F, k, Qb, n) ? 1 : 0;
     CHFSI_HIP(hipEventRecord(ev[2], st));
     c->rayleigh_ritz(c->A.z(), n, Qb + cl * n, n, ka, Y + cl * n, n, mu_d, Wk, Wz);
@@ -685,6 +741,13 @@ void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds,
       lam[cl + j] = mu[j];
       rho_lock[cl + j] = rho[j];
     }
+    if (mixed) {
+      // stall of an FP32 iteration on the same first column
+      if (prev32 && prev_col == cl && rho[0] > 0.5 * prev_rho) fp64_col = cl;
+      prev32 = use32;
+      prev_col = cl + nl;
+      prev_rho = nl < ka ? rho[nl] : INFINITY;
+    }
     cl += nl;
     a = mu[ka - 1];
     a0 = std::min(a0, mu[0]);
@@ -712,9 +775,12 @@ void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds,
   c->warm_k = k;
   c->warm_a0 = a0;
   c->warm_a = a;
-  inf.filter_flops = c->filt_flops;
-  inf.filter_launches = c->filt_launches;
-  inf.filter_kernel_seconds = c->filt_kernel_s;
+  inf.filter_flops = c->filt_flops[0] + c->filt_flops[1];
+  inf.filter_launches = c->filt_launches[0] + c->filt_launches[1];
+  inf.filter_kernel_seconds = c->filt_kernel_s[0] + c->filt_kernel_s[1];
+  inf.filter_flops_fp32 = c->filt_flops[1];
+  inf.filter_launches_fp32 = c->filt_launches[1];
+  inf.filter_kernel_seconds_fp32 = c->filt_kernel_s[1];
   inf.t_total = secs(t_start, now());
   if (info) *info = inf;
   if (!converged)
@@ -761,7 +827,7 @@ chfsi_status chfsi_create(chfsi_ctx* out, int64_t n, const chfsi_opts* opts, voi
   chfsi_opts o;
   chfsi_default_opts(&o);
   if (opts) o = *opts;
-  if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX || o.precision != 0 ||
+  if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX || (o.precision != 0 && o.precision != 1) ||
       (o.qr_mode != 0 && o.qr_mode != 1) || o.filter_tile < 0 || o.filter_tile >= zgemm_num_configs() ||
       o.filter_splitk < 0 || o.filter_splitk > 16)
     return CHFSI_EINVAL;
@@ -827,14 +893,26 @@ chfsi_status chfsi_filter(chfsi_ctx c, const void* A, int64_t lda, void* Y, int6
     if (k < 1 || k > c->n || m < 1 || !(b > a)) throw Error(ST_EINVAL, "filter: need 1 <= k <= n, m >= 1, b > a");
     c->ensure_small();
     c->ensure_k(k);
-    c->filt_kernel_s = 0;
+    c->reset_filter_stats();
     if (c->opts.filter_splitk > 1 && c->P_elems < (size_t)c->opts.filter_splitk * c->n * k) {
       c->P_elems = (size_t)c->opts.filter_splitk * c->n * k;
       c->P.release();
       c->P.ensure(c->P_elems * sizeof(zc));
     }
-    zc* res = c->filter((const zc*)A, lda, (zc*)Y, ldy, c->Yb.z(), c->n, k, m, a, b, a0);
-    if (res != (zc*)Y) copy2d(res, c->n, (zc*)Y, ldy, c->n, k, c->st);
+    const int64_t n = c->n;
+    if (c->opts.precision == 1) {
+      // mixed precision: the filter itself in complex FP32
+      c->A32.ensure((size_t)n * n * sizeof(cc));
+      c->Y32.ensure((size_t)n * k * sizeof(cc));
+      c->Y32b.ensure((size_t)n * k * sizeof(cc));
+      to_f32((const zc*)A, lda, (cc*)c->A32.p, n, n, n, c->st);
+      to_f32((const zc*)Y, ldy, (cc*)c->Y32.p, n, n, k, c->st);
+      void* r = c->filter_any(PREC_F32, c->A32.p, n, c->Y32.p, n, c->Y32b.p, n, k, m, a, b, a0);
+      to_f64((const cc*)r, n, (zc*)Y, ldy, n, k, c->st);
+    } else {
+      zc* res = c->filter((const zc*)A, lda, (zc*)Y, ldy, c->Yb.z(), n, k, m, a, b, a0);
+      if (res != (zc*)Y) copy2d(res, n, (zc*)Y, ldy, n, k, c->st);
+    }
     c->sync();
     c->collect_filter_events(m);
   });

@@ -21,17 +21,22 @@ enum {
   GEMM_OUT_LOWER = 16,
 };
 
+enum { PREC_F64 = 0, PREC_F32 = 1 };
+
 // out = alpha * op(A) op(B) + beta * X + gamma * Z, op(A) M x K, op(B) K x N.
 // X / Z may be null; out may alias X or Z (each element is read and written
-// by the same thread) but must not alias A or B.
+// by the same thread) but must not alias A or B.  Elements are complex FP64
+// (zc) or, with prec = PREC_F32 (op = N on both sides only), complex FP32
+// (cc) with FP32 accumulation.
 struct GemmOp {
+  int prec = PREC_F64;
   int opA = OP_N, opB = OP_N;
   int64_t M = 0, N = 0, K = 0;
-  const zc* A = nullptr; int64_t lda = 0, sA = 0;
-  const zc* B = nullptr; int64_t ldb = 0, sB = 0;
-  zc* C = nullptr; int64_t ldc = 0, sC = 0;
-  const zc* X = nullptr; int64_t ldx = 0, sX = 0;
-  const zc* Z = nullptr; int64_t ldz = 0, sZ = 0;
+  const void* A = nullptr; int64_t lda = 0, sA = 0;
+  const void* B = nullptr; int64_t ldb = 0, sB = 0;
+  void* C = nullptr; int64_t ldc = 0, sC = 0;
+  const void* X = nullptr; int64_t ldx = 0, sX = 0;
+  const void* Z = nullptr; int64_t ldz = 0, sZ = 0;
   double alpha = 1.0, beta = 0.0, gamma = 0.0;
   int flags = 0;
   int batch = 1;            // strided batch count (s* are the strides)
@@ -41,7 +46,8 @@ struct GemmOp {
   int splitk = 0;           // K split (0: chosen automatically, 1: none)
 };
 
-// Scratch for split-K partial tiles.
+// Scratch for split-K partial tiles (P_elems complex FP64 elements; an FP32
+// product uses the same bytes as twice as many complex FP32 elements).
 struct GemmWork {
   zc* P = nullptr;
   size_t P_elems = 0;
@@ -49,16 +55,16 @@ struct GemmWork {
 
 struct ZGemmParams {
   int64_t M, N, K;
-  const zc* A; int64_t lda, sA;
-  const zc* B; int64_t ldb, sB;
-  zc* C; int64_t ldc, sC;
-  const zc* X; int64_t ldx, sX;
-  const zc* Z; int64_t ldz, sZ;
+  const void* A; int64_t lda, sA;
+  const void* B; int64_t ldb, sB;
+  void* C; int64_t ldc, sC;
+  const void* X; int64_t ldx, sX;
+  const void* Z; int64_t ldz, sZ;
   double alpha, beta, gamma;
   int flags;
   int splitk;
   int64_t kchunk;
-  zc* P;
+  void* P;
   int tiles_m, tiles_n;
 };
 

@@ -66,6 +66,22 @@ __global__ void k_copy2d(const zc* src, int64_t lds, zc* dst, int64_t ldd, int64
   dst[i + j * ldd] = src[i + j * lds];
 }
 
+__global__ void k_z2c(const zc* src, int64_t lds, cc* dst, int64_t ldd, int64_t m, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  const int64_t i = e % m, j = e / m;
+  const zc v = src[i + j * lds];
+  dst[i + j * ldd] = make_float2((float)v.x, (float)v.y);
+}
+
+__global__ void k_c2z(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  const int64_t i = e % m, j = e / m;
+  const cc v = src[i + j * lds];
+  dst[i + j * ldd] = make_double2((double)v.x, (double)v.y);
+}
+
 __global__ void k_set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * n) return;
@@ -129,7 +145,7 @@ constexpr int CLD = CNB + 1;
 __global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi,
                                                     int64_t j0, int nb, int* info) {
   extern __shared__ zc smem[];
-  zc* Ls = smem;             // [CNB][CLD] row-major: Ls[i * CLD + c]
+  zc* Ls = smem;              // [CNB][CLD] row-major: Ls[i * CLD + c]
   zc* Xs = smem + CNB * CLD;  // inverse
   __shared__ int failed;
   const int tid = threadIdx.x;
@@ -139,17 +155,18 @@ __global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc*
     Ls[i * CLD + c] = (i >= c) ? W[(j0 + i) + (j0 + c) * ldw] : zmk(0.0, 0.0);
   }
   __syncthreads();
+  // right-looking factorization: per column, scale (every thread reads the
+  // pivot itself), barrier, rank-1 update of the trailing lower triangle
   for (int j = 0; j < nb; j++) {
-    if (tid == 0) {
-      const double d = Ls[j * CLD + j].x;
-      if (!(d > 0.0)) failed = j;
-      else Ls[j * CLD + j] = zmk(sqrt(d), 0.0);
+    const double d = Ls[j * CLD + j].x;
+    if (!(d > 0.0)) {
+      if (tid == 0) failed = j;
+      break;  // uniform: every thread read the same pivot
     }
-    __syncthreads();
-    if (failed >= 0) break;
-    const double inv = 1.0 / Ls[j * CLD + j].x;
+    const double ljj = sqrt(d), inv = 1.0 / ljj;
     for (int i = j + 1 + tid; i < nb; i += blockDim.x) Ls[i * CLD + j] = zscale(inv, Ls[i * CLD + j]);
     __syncthreads();
+    if (tid == 0) Ls[j * CLD + j] = zmk(ljj, 0.0);
     const int m = nb - j - 1;  // trailing size
     for (int e = tid; e < m * m; e += blockDim.x) {
       const int i = j + 1 + e % m, c = j + 1 + e / m;
@@ -157,30 +174,36 @@ __global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc*
     }
     __syncthreads();
   }
+  __syncthreads();
   if (failed >= 0) {
     if (tid == 0) atomicMin(info, (int)(j0 + failed + 1));
     return;
   }
-  // inverse: column c solved by thread c
-  if (tid < nb) {
-    const int c = tid;
-    for (int i = 0; i < nb; i++) {
-      zc x;
-      if (i < c) x = zmk(0.0, 0.0);
-      else if (i == c) x = zmk(1.0 / Ls[c * CLD + c].x, 0.0);
-      else {
-        zc s = zmk(0.0, 0.0);
-        for (int q = c; q < i; q++) s = zadd(s, zmul(Ls[i * CLD + q], Xs[q * CLD + c]));
-        x = zscale(-1.0 / Ls[i * CLD + i].x, s);
-      }
-      Xs[i * CLD + c] = x;
-    }
-  }
-  __syncthreads();
+  // inverse X = L^{-1} by forward substitution, one row at a time; row i of
+  // every column c <= i at once, each dot product split over 4 lanes
   for (int e = tid; e < nb * nb; e += blockDim.x) {
     const int i = e % nb, c = e / nb;
-    L[(j0 + i) + (j0 + c) * ldl] = (i >= c) ? Ls[i * CLD + c] : zmk(0.0, 0.0);
-    Linv[(j0 + i) + (j0 + c) * ldi] = (i >= c) ? Xs[i * CLD + c] : zmk(0.0, 0.0);
+    Xs[i * CLD + c] = zmk(0.0, 0.0);
+  }
+  __syncthreads();
+  const int c = tid >> 2, part = tid & 3;
+  for (int i = 0; i < nb; i++) {
+    const double dinv = 1.0 / Ls[i * CLD + i].x;
+    if (c < nb && c <= i) {
+      zc s = zmk(0.0, 0.0);
+      for (int q = c + part; q < i; q += 4) s = zadd(s, zmul(Ls[i * CLD + q], Xs[q * CLD + c]));
+      s.x += __shfl_xor(s.x, 1, 64);
+      s.y += __shfl_xor(s.y, 1, 64);
+      s.x += __shfl_xor(s.x, 2, 64);
+      s.y += __shfl_xor(s.y, 2, 64);
+      if (part == 0) Xs[i * CLD + c] = (i == c) ? zmk(dinv, 0.0) : zscale(-dinv, s);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nb * nb; e += blockDim.x) {
+    const int i = e % nb, cc_ = e / nb;
+    L[(j0 + i) + (j0 + cc_) * ldl] = (i >= cc_) ? Ls[i * CLD + cc_] : zmk(0.0, 0.0);
+    Linv[(j0 + i) + (j0 + cc_) * ldi] = (i >= cc_) ? Xs[i * CLD + cc_] : zmk(0.0, 0.0);
   }
 }
 
@@ -444,15 +467,19 @@ __device__ inline void rot_cols(const Rot& s, zc& zp, zc& zq) {
   zq = nq;
 }
 
+constexpr int JACOBI_ZLDS_MAX = 64;  // G and Z both in LDS up to this size
+
 __global__ void __launch_bounds__(1024) k_jacobi_small(const zc* G, int64_t ldg, int k, double* w, zc* Zout, int64_t ldz,
-                                                      zc* Z, int* sweeps_out) {
-  extern __shared__ zc Gs[];  // k x k, column-major ld k
+                                                      zc* Zg, int* sweeps_out) {
+  extern __shared__ zc Gs[];  // k x k, column-major ld k; then Z when k <= JACOBI_ZLDS_MAX
   __shared__ double red[16];
   __shared__ Rot prm[JACOBI_LDS_MAX / 2 + 1];
   __shared__ int pidx[JACOBI_LDS_MAX / 2 + 1], qidx[JACOBI_LDS_MAX / 2 + 1];
   __shared__ int rotated;
+  zc* Z = (k <= JACOBI_ZLDS_MAX) ? Gs + k * k : Zg;
   const int tid = threadIdx.x;
   const int K2 = k + (k & 1), half = K2 / 2;
+  const int nblk = half * (half + 1) / 2;
   double f = 0.0;
   for (int e = tid; e < k * k; e += blockDim.x) {
     const int i = e % k, j = e / k;
@@ -489,8 +516,12 @@ __global__ void __launch_bounds__(1024) k_jacobi_small(const zc* G, int64_t ldg,
         prm[tid] = R;
       }
       __syncthreads();
-      for (int e = tid; e < half * half; e += blockDim.x) {
-        const int rt = e % half, st = e / half;
+      // 2x2 blocks of pair rows rt >= pair columns st, mirrored (G Hermitian)
+      for (int e = tid; e < nblk; e += blockDim.x) {
+        int rt = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+        while (rt * (rt + 1) / 2 > e) rt--;
+        while ((rt + 1) * (rt + 2) / 2 <= e) rt++;
+        const int st = e - rt * (rt + 1) / 2;
         const Rot& Rr = prm[rt];
         const Rot& Rs = prm[st];
         if (!Rr.active && !Rs.active) continue;
@@ -513,6 +544,12 @@ __global__ void __launch_bounds__(1024) k_jacobi_small(const zc* G, int64_t ldg,
         if (qsv) Gs[pr + qs * k] = b01;
         if (qrv) Gs[qr + ps * k] = b10;
         if (qrv && qsv) Gs[qr + qs * k] = b11;
+        if (rt != st) {
+          Gs[ps + pr * k] = zconj(b00);
+          if (qsv) Gs[qs + pr * k] = zconj(b01);
+          if (qrv) Gs[ps + qr * k] = zconj(b10);
+          if (qrv && qsv) Gs[qs + qr * k] = zconj(b11);
+        }
       }
       for (int e = tid; e < k * half; e += blockDim.x) {
         const int i = e % k, st = e / k;
@@ -554,7 +591,11 @@ __global__ void k_jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z
 
 __global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
                                int* rotated) {
+  // G is Hermitian: thread e < half (half + 1)/2 owns the 2x2 block of pair
+  // rows rt >= pair columns st and writes it and its mirror; the remaining
+  // threads update Z's columns.
   const int64_t K2 = k + (k & 1), half = K2 / 2;
+  const int64_t nblk = half * (half + 1) / 2;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double skip2 = 1e-36 * fro2[0];
   auto rot_of = [&](int64_t t, int64_t& p, int64_t& q) -> Rot {
@@ -566,8 +607,12 @@ __global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout,
     }
     return make_rot(Gin[p + p * k], Gin[q + q * k], Gin[p + q * k], skip2);
   };
-  if (e < half * half) {
-    const int64_t rt = e % half, st = e / half;
+  if (e < nblk) {
+    // e -> (rt, st), rt >= st, e = rt (rt + 1)/2 + st
+    int64_t rt = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+    while (rt * (rt + 1) / 2 > e) rt--;
+    while ((rt + 1) * (rt + 2) / 2 <= e) rt++;
+    const int64_t st = e - rt * (rt + 1) / 2;
     int64_t pr, qr, ps, qs;
     const Rot Rr = rot_of(rt, pr, qr);
     const Rot Rs = rot_of(st, ps, qs);
@@ -592,9 +637,15 @@ __global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout,
     if (qsv) Gout[pr + qs * k] = b01;
     if (qrv) Gout[qr + ps * k] = b10;
     if (qrv && qsv) Gout[qr + qs * k] = b11;
+    if (rt != st) {
+      Gout[ps + pr * k] = zconj(b00);
+      if (qsv) Gout[qs + pr * k] = zconj(b01);
+      if (qrv) Gout[ps + qr * k] = zconj(b10);
+      if (qrv && qsv) Gout[qs + qr * k] = zconj(b11);
+    }
     return;
   }
-  const int64_t e2 = e - half * half;
+  const int64_t e2 = e - nblk;
   if (e2 >= k * half) return;
   const int64_t i = e2 % k, st = e2 / k;
   int64_t ps, qs;
@@ -757,6 +808,16 @@ void copy2d(const zc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t
   LAUNCH(k_copy2d, grid1(m * n), dim3(NT), 0, st, src, lds, dst, ldd, m, n);
 }
 
+void to_f32(const zc* src, int64_t lds, cc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st) {
+  if (m * n == 0) return;
+  LAUNCH(k_z2c, grid1(m * n), dim3(NT), 0, st, src, lds, dst, ldd, m, n);
+}
+
+void to_f64(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st) {
+  if (m * n == 0) return;
+  LAUNCH(k_c2z, grid1(m * n), dim3(NT), 0, st, src, lds, dst, ldd, m, n);
+}
+
 void set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st) {
   if (m * n == 0) return;
   LAUNCH(k_set_identity, grid1(m * n), dim3(NT), 0, st, Y, ldy, m, n);
@@ -834,7 +895,8 @@ void jacobi_small(const zc* G, int64_t ldg, int64_t k, double* w, zc* Z, int64_t
     CHFSI_HIP(hipFuncSetAttribute((const void*)k_jacobi_small, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     attr = true;
   }
-  LAUNCH(k_jacobi_small, dim3(1), dim3(1024), (size_t)k * k * sizeof(zc), st, G, ldg, (int)k, w, Z, ldz, Ztmp, sweeps_out);
+  const size_t dyn = (size_t)k * k * sizeof(zc) * (k <= JACOBI_ZLDS_MAX ? 2 : 1);
+  LAUNCH(k_jacobi_small, dim3(1), dim3(1024), dyn, st, G, ldg, (int)k, w, Z, ldz, Ztmp, sweeps_out);
 }
 
 void jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0, hipStream_t st) {
@@ -844,7 +906,8 @@ void jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0, hipStream_
 void jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
                   int* rotated, hipStream_t st) {
   const int64_t half = (k + (k & 1)) / 2;
-  LAUNCH(k_jacobi_round, grid1(half * half + k * half), dim3(NT), 0, st, Gin, Gout, Zin, Zout, k, round, fro2, rotated);
+  LAUNCH(k_jacobi_round, grid1(half * (half + 1) / 2 + k * half), dim3(NT), 0, st, Gin, Gout, Zin, Zout, k, round, fro2,
+         rotated);
 }
 
 void jacobi_norms(const zc* G, int64_t k, double* part, double* out, hipStream_t st) {

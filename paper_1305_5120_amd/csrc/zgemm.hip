@@ -32,6 +32,30 @@ namespace chfsi {
 
 namespace {
 
+// Precision traits: element type, real type, accumulator and the matrix-core
+// instruction.  Result lane layouts of the 16x16x4 instructions (lane l,
+// value r): FP64 holds D[l/16 + 4r][l%16], FP32 holds D[4(l/16) + r][l%16].
+struct PF64 {
+  using E = zc;
+  using R = double;
+  using Acc = d4v;
+  static __device__ __forceinline__ Acc mfma(R a, R b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lk, int r) { return lk + 4 * r; }
+  static __device__ __forceinline__ E mk(R x, R y) { return make_double2(x, y); }
+};
+struct PF32 {
+  using E = cc;
+  using R = float;
+  using Acc = f4v;
+  static __device__ __forceinline__ Acc mfma(R a, R b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lk, int r) { return 4 * lk + r; }
+  static __device__ __forceinline__ E mk(R x, R y) { return make_float2(x, y); }
+};
+
 template <int BM, int BN, int BK>
 struct ZTile {
   static constexpr int NT = 256;
@@ -48,11 +72,14 @@ struct ZTile {
   static_assert(BK % 4 == 0, "BK multiple of the MFMA depth");
 };
 
-template <int OPA, int OPB, int BM, int BN, int BK>
+template <class PT, int OPA, int OPB, int BM, int BN, int BK>
 __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
   using T = ZTile<BM, BN, BK>;
-  __shared__ zc As[2][BK][T::LDA_S];
-  __shared__ zc Bs[2][BK][T::LDB_S];
+  using E = typename PT::E;
+  using R = typename PT::R;
+  using Acc = typename PT::Acc;
+  __shared__ E As[2][BK][T::LDA_S];
+  __shared__ E Bs[2][BK][T::LDB_S];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -72,8 +99,8 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
 
   const int bz = blockIdx.y;
   const int batch = bz / p.splitk, split = bz % p.splitk;
-  const zc* __restrict__ A = p.A + (int64_t)batch * p.sA;
-  const zc* __restrict__ B = p.B + (int64_t)batch * p.sB;
+  const E* __restrict__ A = static_cast<const E*>(p.A) + (int64_t)batch * p.sA;
+  const E* __restrict__ B = static_cast<const E*>(p.B) + (int64_t)batch * p.sB;
 
   int64_t kbeg = 0, kend = p.K;
   if (p.flags & GEMM_TRI_A_LOWER) kend = min(kend, m0 + BM);
@@ -86,16 +113,16 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
   }
   const int64_t nslab = kend > kbeg ? cdiv(kend - kbeg, (int64_t)BK) : 0;
 
-  d4v accR[T::MI][T::NJ], accI[T::MI][T::NJ];
+  Acc accR[T::MI][T::NJ], accI[T::MI][T::NJ];
 #pragma unroll
   for (int i = 0; i < T::MI; i++)
 #pragma unroll
     for (int j = 0; j < T::NJ; j++) {
-      accR[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
-      accI[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+      accR[i][j] = Acc{0, 0, 0, 0};
+      accI[i][j] = Acc{0, 0, 0, 0};
     }
 
-  zc ra[T::EA], rb[T::EB];
+  E ra[T::EA], rb[T::EB];
 
   auto load_slab = [&](int64_t k0) {
 #pragma unroll
@@ -105,10 +132,13 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
       if (OPA == OP_N) { mm = e % BM; kk = e / BM; }
       else { kk = e % BK; mm = e / BK; }
       const int64_t gm = m0 + mm, gk = k0 + kk;
-      zc v = zmk(0.0, 0.0);
+      E v = PT::mk(0, 0);
       if (gm < p.M && gk < kend) {
         if (OPA == OP_N) v = A[gm + gk * p.lda];
-        else v = zconj(A[gk + gm * p.lda]);
+        else {
+          v = A[gk + gm * p.lda];
+          v.y = -v.y;
+        }
       }
       ra[q] = v;
     }
@@ -119,10 +149,13 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
       if (OPB == OP_N) { kk = e % BK; nn = e / BK; }
       else { nn = e % BN; kk = e / BN; }
       const int64_t gn = n0 + nn, gk = k0 + kk;
-      zc v = zmk(0.0, 0.0);
+      E v = PT::mk(0, 0);
       if (gn < p.N && gk < kend) {
         if (OPB == OP_N) v = B[gk + gn * p.ldb];
-        else v = zconj(B[gn + gk * p.ldb]);
+        else {
+          v = B[gn + gk * p.ldb];
+          v.y = -v.y;
+        }
       }
       rb[q] = v;
     }
@@ -155,7 +188,7 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
       if (s + 1 < nslab) load_slab(kbeg + (s + 1) * BK);
       // fragments of depth step 0; the next step's are read while the
       // current step's products run
-      zc a[2][T::MI], b[2][T::NJ];
+      E a[2][T::MI], b[2][T::NJ];
 #pragma unroll
       for (int i = 0; i < T::MI; i++) a[0][i] = As[buf][lk][wm0 + i * 16 + lr];
 #pragma unroll
@@ -176,33 +209,31 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
         for (int i = 0; i < T::MI; i++)
 #pragma unroll
           for (int j = 0; j < T::NJ; j++)
-            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[c][j].x, a[c][i].x, accR[i][j], 0, 0, 0);
+            accR[i][j] = PT::mfma(b[c][j].x, a[c][i].x, accR[i][j]);
 #pragma unroll
         for (int i = 0; i < T::MI; i++)
 #pragma unroll
           for (int j = 0; j < T::NJ; j++)
-            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[c][j].y, a[c][i].x, accI[i][j], 0, 0, 0);
+            accI[i][j] = PT::mfma(b[c][j].y, a[c][i].x, accI[i][j]);
 #pragma unroll
         for (int i = 0; i < T::MI; i++)
 #pragma unroll
           for (int j = 0; j < T::NJ; j++)
-            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-b[c][j].y, a[c][i].y, accR[i][j], 0, 0, 0);
+            accR[i][j] = PT::mfma(-b[c][j].y, a[c][i].y, accR[i][j]);
 #pragma unroll
         for (int i = 0; i < T::MI; i++)
 #pragma unroll
           for (int j = 0; j < T::NJ; j++)
-            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[c][j].x, a[c][i].y, accI[i][j], 0, 0, 0);
+            accI[i][j] = PT::mfma(b[c][j].x, a[c][i].y, accI[i][j]);
       }
       if (s + 1 < nslab) store_slab(buf ^ 1);
       __syncthreads();
     }
   }
 
-  // Epilogue.  Result lane layout of v_mfma_f64_16x16x4f64: lane l, value r
-  // holds D[l/16 + 4r][l%16]; here D's row is the output column n and its
-  // column the output row m.
+  // Epilogue.  D's row is the output column n, its column the output row m.
   if (p.splitk > 1) {
-    zc* P = p.P + ((int64_t)batch * p.splitk + split) * p.M * p.N;
+    E* P = static_cast<E*>(p.P) + ((int64_t)batch * p.splitk + split) * p.M * p.N;
 #pragma unroll
     for (int i = 0; i < T::MI; i++)
 #pragma unroll
@@ -210,14 +241,15 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
 #pragma unroll
         for (int r = 0; r < 4; r++) {
           const int64_t m = m0 + wm0 + i * 16 + lr;
-          const int64_t n = n0 + wn0 + j * 16 + lk + 4 * r;
-          if (m < p.M && n < p.N) P[m + n * p.M] = zmk(accR[i][j][r], accI[i][j][r]);
+          const int64_t n = n0 + wn0 + j * 16 + PT::out_row(lk, r);
+          if (m < p.M && n < p.N) P[m + n * p.M] = PT::mk(accR[i][j][r], accI[i][j][r]);
         }
     return;
   }
-  zc* C = p.C + (int64_t)batch * p.sC;
-  const zc* X = p.X ? p.X + (int64_t)batch * p.sX : nullptr;
-  const zc* Z = p.Z ? p.Z + (int64_t)batch * p.sZ : nullptr;
+  E* C = static_cast<E*>(p.C) + (int64_t)batch * p.sC;
+  const E* X = p.X ? static_cast<const E*>(p.X) + (int64_t)batch * p.sX : nullptr;
+  const E* Z = p.Z ? static_cast<const E*>(p.Z) + (int64_t)batch * p.sZ : nullptr;
+  const R al = (R)p.alpha, be = (R)p.beta, ga = (R)p.gamma;
 #pragma unroll
   for (int i = 0; i < T::MI; i++)
 #pragma unroll
@@ -225,51 +257,78 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int64_t m = m0 + wm0 + i * 16 + lr;
-        const int64_t n = n0 + wn0 + j * 16 + lk + 4 * r;
+        const int64_t n = n0 + wn0 + j * 16 + PT::out_row(lk, r);
         if (m < p.M && n < p.N) {
-          zc v = zmk(p.alpha * accR[i][j][r], p.alpha * accI[i][j][r]);
-          if (X) v = zadd(v, zscale(p.beta, X[m + n * p.ldx]));
-          if (Z) v = zadd(v, zscale(p.gamma, Z[m + n * p.ldz]));
-          C[m + n * p.ldc] = v;
+          R vx = al * accR[i][j][r], vy = al * accI[i][j][r];
+          if (X) {
+            const E x = X[m + n * p.ldx];
+            vx += be * x.x;
+            vy += be * x.y;
+          }
+          if (Z) {
+            const E z = Z[m + n * p.ldz];
+            vx += ga * z.x;
+            vy += ga * z.y;
+          }
+          C[m + n * p.ldc] = PT::mk(vx, vy);
         }
       }
 }
 
 template <int OPA, int OPB, int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) zgemm_kernel(ZGemmParams p) {
-  zgemm_body<OPA, OPB, BM, BN, BK>(p);
+  zgemm_body<PF64, OPA, OPB, BM, BN, BK>(p);
 }
 
 // One degree step of the Chebyshev filter: the same body, launched under its
 // own symbol so that profiles separate the filter from the other products.
 template <int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) chebyshev_step_f64(ZGemmParams p) {
-  zgemm_body<OP_N, OP_N, BM, BN, BK>(p);
+  zgemm_body<PF64, OP_N, OP_N, BM, BN, BK>(p);
+}
+
+// The mixed-precision filter step: complex FP32 operands on the FP32 matrix
+// cores with FP32 accumulation.
+template <int BM, int BN, int BK, int MINB>
+__global__ void __launch_bounds__(256, MINB) chebyshev_step_f32(ZGemmParams p) {
+  zgemm_body<PF32, OP_N, OP_N, BM, BN, BK>(p);
 }
 
 // Combine split-K partial tiles and apply the epilogue.
+template <class PT>
 __device__ __forceinline__ void splitk_reduce_body(const ZGemmParams& p) {
+  using E = typename PT::E;
+  using R = typename PT::R;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int batch = blockIdx.y;
   if (e >= p.M * p.N) return;
   const int64_t m = e % p.M, n = e / p.M;
-  const zc* P = p.P + (int64_t)batch * p.splitk * p.M * p.N;
-  double re = 0.0, im = 0.0;
+  const E* P = static_cast<const E*>(p.P) + (int64_t)batch * p.splitk * p.M * p.N;
+  R re = 0, im = 0;
   for (int s = 0; s < p.splitk; s++) {
-    const zc v = P[(int64_t)s * p.M * p.N + e];
+    const E v = P[(int64_t)s * p.M * p.N + e];
     re += v.x;
     im += v.y;
   }
-  zc v = zmk(p.alpha * re, p.alpha * im);
-  if (p.X) v = zadd(v, zscale(p.beta, p.X[(int64_t)batch * p.sX + m + n * p.ldx]));
-  if (p.Z) v = zadd(v, zscale(p.gamma, p.Z[(int64_t)batch * p.sZ + m + n * p.ldz]));
-  p.C[(int64_t)batch * p.sC + m + n * p.ldc] = v;
+  R vx = (R)p.alpha * re, vy = (R)p.alpha * im;
+  if (p.X) {
+    const E x = static_cast<const E*>(p.X)[(int64_t)batch * p.sX + m + n * p.ldx];
+    vx += (R)p.beta * x.x;
+    vy += (R)p.beta * x.y;
+  }
+  if (p.Z) {
+    const E z = static_cast<const E*>(p.Z)[(int64_t)batch * p.sZ + m + n * p.ldz];
+    vx += (R)p.gamma * z.x;
+    vy += (R)p.gamma * z.y;
+  }
+  static_cast<E*>(p.C)[(int64_t)batch * p.sC + m + n * p.ldc] = PT::mk(vx, vy);
 }
 
-__global__ void zgemm_splitk_reduce(ZGemmParams p) { splitk_reduce_body(p); }
+__global__ void zgemm_splitk_reduce(ZGemmParams p) { splitk_reduce_body<PF64>(p); }
 
-// The filter step's split-K combination (its own symbol, like the step).
-__global__ void chebyshev_step_reduce_f64(ZGemmParams p) { splitk_reduce_body(p); }
+// The filter steps' split-K combinations (own symbols, like the steps).
+__global__ void chebyshev_step_reduce_f64(ZGemmParams p) { splitk_reduce_body<PF64>(p); }
+__global__ void chebyshev_step_reduce_f32(ZGemmParams p) { splitk_reduce_body<PF32>(p); }
 
 // Tile configurations.  All use 256 threads (2x2 waves).
 struct Cfg {
@@ -298,6 +357,28 @@ void launch_one(ZGemmParams& p, int batch, bool filter_step, hipStream_t st) {
   else
     hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, BM, BN, BK, MINB>), grid, dim3(256), 0, st, p);
   CHFSI_CHECK_LAUNCH();
+}
+
+template <int BM, int BN, int BK, int MINB>
+void launch_one_f32(ZGemmParams& p, int batch, hipStream_t st) {
+  p.tiles_m = (int)cdiv(p.M, BM);
+  p.tiles_n = (int)cdiv(p.N, BN);
+  dim3 grid((unsigned)((int64_t)p.tiles_m * p.tiles_n), (unsigned)(batch * p.splitk));
+  hipLaunchKernelGGL((chebyshev_step_f32<BM, BN, BK, MINB>), grid, dim3(256), 0, st, p);
+  CHFSI_CHECK_LAUNCH();
+}
+
+void launch_f32(int cfg, ZGemmParams& p, int batch, hipStream_t st) {
+  switch (cfg) {
+    case 1: launch_one_f32<64, 64, 16, 2>(p, batch, st); break;
+    case 2: launch_one_f32<32, 32, 16, 2>(p, batch, st); break;
+    case 3: launch_one_f32<64, 64, 8, 2>(p, batch, st); break;
+    case 4: launch_one_f32<128, 64, 8, 2>(p, batch, st); break;
+    case 5: launch_one_f32<64, 128, 8, 2>(p, batch, st); break;
+    case 6: launch_one_f32<128, 128, 8, 1>(p, batch, st); break;
+    case 7: launch_one_f32<64, 32, 16, 2>(p, batch, st); break;
+    default: throw Error(ST_EINVAL, "cgemm: bad tile configuration");
+  }
 }
 
 template <int OPA, int OPB>
@@ -351,7 +432,8 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
     else c = 7;                   // 64 x 32 x 16
     int sk = (int)std::min<int64_t>(8, std::max<int64_t>(1, (g.K + 500) / 1000));
     if (g.N < 96) sk = 8;
-    while (sk > 1 && (!g.allow_splitk || !P_elems || (size_t)sk * g.M * g.N > (size_t)P_elems ||
+    const size_t cap = (size_t)P_elems * (g.prec == PREC_F32 ? 2 : 1);
+    while (sk > 1 && (!g.allow_splitk || !P_elems || (size_t)sk * g.M * g.N > cap ||
                       g.K < (int64_t)sk * 4 * CFGS[c].bk))
       sk /= 2;
     cfg = c;
@@ -413,8 +495,12 @@ void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st) {
     if (cfg == 0) cfg = c2;
     if (sk == 0) sk = (g.cfg == 0) ? s2 : 1;
   }
+  const bool f32 = g.prec == PREC_F32;
+  if (f32 && (g.opA != OP_N || g.opB != OP_N || g.flags))
+    throw Error(ST_EINVAL, "zgemm: FP32 products support op = N and no structure flags only");
   if (sk > 1) {
-    if (!w.P || (size_t)sk * g.M * g.N * batch > w.P_elems || (g.flags & GEMM_OUT_LOWER))
+    const size_t cap = f32 ? 2 * w.P_elems : w.P_elems;
+    if (!w.P || (size_t)sk * g.M * g.N * batch > cap || (g.flags & GEMM_OUT_LOWER))
       throw Error(ST_EINVAL, "zgemm: split-K scratch too small or not allowed");
     const int bk = CFGS[cfg].bk;
     p.kchunk = cdiv(cdiv(g.K, sk), bk) * bk;
@@ -425,10 +511,12 @@ void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st) {
     p.kchunk = g.K;
     p.P = nullptr;
   }
-  launch_ops(cfg, g.opA, g.opB, p, batch, g.filter_step, st);
+  if (f32) launch_f32(cfg, p, batch, st);
+  else launch_ops(cfg, g.opA, g.opB, p, batch, g.filter_step, st);
   if (p.splitk > 1) {
     dim3 grid((unsigned)cdiv(g.M * g.N, 256), (unsigned)batch);
-    if (g.filter_step) hipLaunchKernelGGL(chebyshev_step_reduce_f64, grid, dim3(256), 0, st, p);
+    if (f32) hipLaunchKernelGGL(chebyshev_step_reduce_f32, grid, dim3(256), 0, st, p);
+    else if (g.filter_step) hipLaunchKernelGGL(chebyshev_step_reduce_f64, grid, dim3(256), 0, st, p);
     else hipLaunchKernelGGL(zgemm_splitk_reduce, grid, dim3(256), 0, st, p);
     CHFSI_CHECK_LAUNCH();
   }

@@ -149,6 +149,25 @@ def test_filter_matches_oracle(lib, n, k, m):
     assert _rel(_np(Yt), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("n,k,m", [(300, 37, 7), (1000, 130, 20)])
+def test_filter_fp32_against_oracle(lib, n, k, m):
+    """Mixed precision: the recurrence in complex FP32 with FP32 accumulation
+    agrees with the FP64 oracle to FP32 accuracy (the scaled recurrence keeps
+    the iterates O(1), so errors stay near m * eps32)."""
+    p = workloads.make_problem(n, 90 + n)
+    rng = _rng(n + 1)
+    Y = _cg(rng, (n, k))
+    lam = np.sort(p.lam)
+    a, b, a0 = float(lam[k]), float(lam[-1] * 1.05), float(lam[0])
+    ref = oracle.chebyshev_filter(p.A, Y, m, a, b, a0)
+    ctx = lib.create(n, precision=1)
+    Yt = _t(Y)
+    lib.filter(ctx, _t(p.A), Yt, m, a, b, a0)
+    err = _rel(_np(Yt), ref)
+    assert err <= 2e-5, err
+    assert err >= 1e-9  # really computed in FP32
+
+
 def test_filter_closed_form_on_diagonal(lib):
     n, k, m = 100, 6, 9
     t = np.linspace(-1.0, 3.0, n)
@@ -353,6 +372,18 @@ def test_solve_config0_householder_mode_matches_oracle(lib):
     _check_solution(p, ev, _np(X), 51)
 
 
+def test_solve_config0_mixed_precision_matches_oracle(lib):
+    """FP32 filter + FP64 everything else reaches the same FP64 tolerance."""
+    p = workloads.make_problem(512, 0)
+    ref = oracle.solve(p.H, p.S, 51, 13, tol=1e-10, degree=10, seed=0)
+    ctx = lib.create(512, degree=10, seed=0, precision=1)
+    ev, X, info, st = lib.solve(ctx, _t(p.H), _t(p.S), 51, 13, tol=1e-10)
+    assert st == 0
+    assert info["iterations_fp32"] > 0 and info["filter_launches_fp32"] > 0
+    assert np.abs(ev - ref["evals"]).max() <= 1e-12 * 100
+    _check_solution(p, ev, _np(X), 51)
+
+
 def test_solve_ragged_sizes_against_brute_force(lib):
     n, nev, nex = 333, 17, 6
     p = workloads.make_problem(n, 41)
@@ -475,13 +506,15 @@ def test_filter_full_size_sampled_columns(lib, n, k, m):
     assert _rel(got, ref) <= 1e-12
 
 
-def test_solve_full_size_first_problem_of_sequence(lib):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_full_size_first_problem_of_sequence(lib, precision):
     """n=4000, nev=400, nex=40, degree 20 (the benchmark's sequence, first
     problem: spectrum known by construction)."""
     import torch
     p = workloads.make_problem_torch(4000, 1, device="cuda")
-    ctx = lib.create(4000, degree=20, seed=0)
+    ctx = lib.create(4000, degree=20, seed=0, precision=precision)
     ev, X, info, st = lib.solve(ctx, p["H"], p["S"], 400, 40, tol=1e-10)
+    assert (info["iterations_fp32"] > 0) == (precision == 1)
     assert st == 0
     lam = np.sort(p["lam"])[:400]
     H, S = p["H"], p["S"]
