@@ -205,6 +205,124 @@ chfsi_status chfsi_zgemm(chfsi_ctx ctx, int32_t opA, int32_t opB, int64_t M, int
                          const void* A, int64_t lda, const void* B, int64_t ldb, double beta, const void* X, int64_t ldx,
                          double gamma, const void* Z, int64_t ldz, void* C, int64_t ldc, int32_t flags);
 
+/* ---- Batching -----------------------------------------------------------------
+ * One solver per k-point for a fixed set of independent sequences (Section 2:
+ * one sequence of eigenproblems per k-point, all of one SCF step solved
+ * together).  A batch solve runs Algorithm 1 for every member in lockstep:
+ * each outer iteration launches the degree steps of all members' Chebyshev
+ * filters (eq. (3)) as one persistent grouped launch per step and precision,
+ * then orthonormalizes, projects and locks each member on its own stream.
+ * The grouped step's tile shape is chosen online: the first outer iterations
+ * of each precision try the candidate shapes on the real work and the one
+ * with the highest measured rate is kept for the rest of the batch's life
+ * (the block-size study of Section 4, made automatic).  With use_graph = 1
+ * the degree steps of an iteration replay as one captured HIP graph whose
+ * kernels read the members' widths, pointers and alpha / beta / gamma
+ * (eq. (3)) from device memory, so the same graph serves every iteration
+ * while columns lock.  Each member keeps its block and bounds between calls
+ * and warm-starts from them, as chfsi_solve does. */
+typedef struct chfsi_batch_s* chfsi_batch;
+
+typedef struct {
+  int32_t tile_config;        /* grouped step tile configuration in use (FP64) */
+  int32_t tile_config_fp32;   /* same for the FP32 steps (0: none ran yet) */
+  int32_t graph;              /* 1 if the degree steps ran as captured graphs */
+  int32_t outer_iterations;   /* lockstep iterations of this call */
+  int32_t grouped_launches;   /* grouped step launches of this call */
+  int32_t converged_members;  /* members that returned CHFSI_OK */
+  double filter_flops;        /* algorithmic filter flops of this call, 8 n^2 k_a per member and step */
+  double filter_seconds;      /* device time of the grouped steps (events around each iteration's steps) */
+  double seconds;             /* wall time of the call */
+  double tile_rate[8];        /* measured filter TFLOP/s per tile configuration (0: not tried; FP64) */
+} chfsi_batch_report;
+
+/* Create `count` (1..1024) member solvers of sizes n[0..count-1] on the
+ * current device, each with the options *opts (NULL: defaults; filter_tile
+ * != 0 pins the grouped tile shape instead of choosing it online; profile is
+ * ignored).  Streams are created and owned by the batch.  CHFSI_EINVAL on bad
+ * sizes or options. */
+chfsi_status chfsi_batch_create(chfsi_batch* out, int32_t count, const int64_t* n, const chfsi_opts* opts,
+                                int32_t use_graph);
+
+/* Solve one problem per member: H[i], S[i] device n_i x n_i column-major
+ * (S[i] NULL keeps member i's previous factor, as in chfsi_solve); nev[i],
+ * nex[i] as in chfsi_solve; evals[i] host, nev[i] doubles; X[i] device
+ * n_i x nev[i] or NULL.  infos (count entries) and statuses (count entries)
+ * receive each member's chfsi_info and status; report (may be NULL) the
+ * batch-level figures.  Returns CHFSI_OK when every member converged, else
+ * the first failing member's status; argument errors return CHFSI_EINVAL
+ * before any device work.  Input buffers must be ready on the device (the
+ * call synchronizes the device before starting); outputs are complete on
+ * return. */
+chfsi_status chfsi_batch_solve(chfsi_batch b, const void* const* H, const int64_t* ldh, const void* const* S,
+                               const int64_t* lds, const int64_t* nev, const int64_t* nex, double tol,
+                               double* const* evals, void* const* X, const int64_t* ldx, chfsi_info* infos,
+                               int32_t* statuses, chfsi_batch_report* report);
+
+/* Forget every member's warm state (the next solve starts cold). */
+chfsi_status chfsi_batch_reset(chfsi_batch b);
+
+/* Message of the last error (first failing member's, for a solve). */
+const char* chfsi_batch_last_error(chfsi_batch b);
+
+/* Free the members, streams and graphs.  NULL-safe. */
+void chfsi_batch_release(chfsi_batch b);
+
+/* ---- Serving ------------------------------------------------------------------
+ * A request loop over many sequences of problems (one sequence per k-point,
+ * Section 2).  Worker threads each own a HIP stream and a solver context, so
+ * admitted requests run concurrently on the device.  Each sequence keeps its
+ * last block of k vectors (generalized space) and its filter bounds in device
+ * memory and warm-starts its next problem from them.  A request is admitted
+ * when the device memory it needs (a solver context for its size plus its
+ * sequence's state) fits the budget; idle workers' contexts are released to
+ * make room.  Problems of one sequence run in submission order, one at a time.
+ * Results do not depend on what else runs: every solve uses its own context,
+ * stream and deterministic kernels. */
+typedef struct chfsi_server_s* chfsi_server;
+
+typedef struct {
+  int32_t workers;          /* concurrent solves (1..64) */
+  int32_t reserved;
+  int64_t hbm_budget_bytes; /* device memory for contexts + resident sequence state */
+  chfsi_opts opts;          /* solver options of every request */
+} chfsi_server_config;
+
+typedef struct {
+  int64_t submitted, completed, failed, queued, running;
+  int64_t bytes_in_use, peak_bytes, budget_bytes;
+  double solves_per_second; /* completed / (last completion - first submission) */
+  double p50_latency, p99_latency, mean_latency; /* seconds, submission to completion */
+} chfsi_server_statistics;
+
+/* Start a server on the current HIP device.  CHFSI_EINVAL on bad config. */
+chfsi_status chfsi_server_create(chfsi_server* out, const chfsi_server_config* cfg);
+
+/* Queue one problem of sequence `seq`.  H, S: device n x n (S required);
+ * evals: host, nev doubles; X: device n x nev (may be NULL).  All four must
+ * stay valid until chfsi_server_wait returns for the ticket.  The problem is
+ * solved as by chfsi_solve, warm-started from the sequence's previous problem
+ * when its size and block width match. */
+chfsi_status chfsi_server_submit(chfsi_server s, int64_t seq, int64_t n, const void* H, int64_t ldh, const void* S,
+                                 int64_t lds, int64_t nev, int64_t nex, double tol, double* evals, void* X, int64_t ldx,
+                                 int64_t* ticket);
+
+/* Block until the ticket's request has finished; returns its status
+ * (CHFSI_ENOMEM when it can never fit the budget).  The ticket is consumed. */
+chfsi_status chfsi_server_wait(chfsi_server s, int64_t ticket, chfsi_info* info, double* latency_seconds);
+
+/* Throughput, latency percentiles and memory of the requests so far. */
+chfsi_status chfsi_server_stats(chfsi_server s, chfsi_server_statistics* out);
+
+/* Drop a sequence's resident state (CHFSI_EINVAL while it has work queued). */
+chfsi_status chfsi_server_release_sequence(chfsi_server s, int64_t seq);
+
+/* Message of the last failed request. */
+const char* chfsi_server_last_error(chfsi_server s);
+
+/* Finish running requests, fail queued ones, free everything.  NULL-safe. */
+void chfsi_server_destroy(chfsi_server s);
+
 #ifdef __cplusplus
 }
 #endif

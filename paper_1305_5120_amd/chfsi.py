@@ -361,3 +361,107 @@ def zgemm(ctx, opA, opB, A, B, alpha=1.0, beta=0.0, X=None, gamma=0.0, Z=None, C
     if Cc.data_ptr() != C.data_ptr():
         C.copy_(Cc)
     return C
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("workers", c_i32), ("reserved", c_i32), ("hbm_budget_bytes", c_i64), ("opts", Opts)]
+
+
+class ServerStatistics(ctypes.Structure):
+    _fields_ = [("submitted", c_i64), ("completed", c_i64), ("failed", c_i64), ("queued", c_i64), ("running", c_i64),
+                ("bytes_in_use", c_i64), ("peak_bytes", c_i64), ("budget_bytes", c_i64),
+                ("solves_per_second", c_dbl), ("p50_latency", c_dbl), ("p99_latency", c_dbl), ("mean_latency", c_dbl)]
+
+
+def _load_server(L):
+    if getattr(L, "_server_ready", False):
+        return
+    L.chfsi_server_create.argtypes = [ctypes.POINTER(c_vp), ctypes.POINTER(ServerConfig)]
+    L.chfsi_server_create.restype = ctypes.c_int
+    L.chfsi_server_submit.argtypes = [c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_dbl, c_vp, c_vp,
+                                      c_i64, ctypes.POINTER(c_i64)]
+    L.chfsi_server_submit.restype = ctypes.c_int
+    L.chfsi_server_wait.argtypes = [c_vp, c_i64, ctypes.POINTER(Info), ctypes.POINTER(c_dbl)]
+    L.chfsi_server_wait.restype = ctypes.c_int
+    L.chfsi_server_stats.argtypes = [c_vp, ctypes.POINTER(ServerStatistics)]
+    L.chfsi_server_stats.restype = ctypes.c_int
+    L.chfsi_server_release_sequence.argtypes = [c_vp, c_i64]
+    L.chfsi_server_release_sequence.restype = ctypes.c_int
+    L.chfsi_server_last_error.argtypes = [c_vp]
+    L.chfsi_server_last_error.restype = ctypes.c_char_p
+    L.chfsi_server_destroy.argtypes = [c_vp]
+    L._server_ready = True
+
+
+class Server:
+    """Request loop over many sequences (chfsi_server_*).  Inputs stay
+    referenced until their ticket is waited for."""
+
+    def __init__(self, workers=4, hbm_budget_bytes=200 << 30, **opts):
+        self.lib = load()
+        _load_server(self.lib)
+        cfg = ServerConfig()
+        cfg.workers = workers
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.opts = default_opts(**opts)
+        h = c_vp()
+        st = self.lib.chfsi_server_create(ctypes.byref(h), ctypes.byref(cfg))
+        if st != 0:
+            raise ChfsiError(st, "chfsi_server_create failed")
+        self.h = h
+        self._live = {}
+
+    def submit(self, seq, H, S, nev, nex, tol=1e-10, want_vectors=True):
+        import torch
+        _check_dev(H, "H")
+        _check_dev(S, "S")
+        Hc, ldh = colmajor(H)
+        Sc, lds = colmajor(S)
+        n = H.shape[0]
+        evals = np.zeros(nev)
+        X = empty_colmajor(n, nev, H.device) if want_vectors else None
+        # the workers run on their own streams: inputs must be complete first
+        torch.cuda.current_stream().synchronize()
+        t = c_i64()
+        st = self.lib.chfsi_server_submit(self.h, int(seq), n, Hc.data_ptr(), ldh, Sc.data_ptr(), lds, int(nev), int(nex),
+                                          float(tol), evals.ctypes.data_as(c_vp),
+                                          X.data_ptr() if X is not None else None, n, ctypes.byref(t))
+        if st != 0:
+            raise ChfsiError(st, "chfsi_server_submit rejected the request")
+        self._live[t.value] = (Hc, Sc, evals, X)
+        return t.value
+
+    def wait(self, ticket, raise_on_error=True):
+        info = Info()
+        lat = c_dbl()
+        st = self.lib.chfsi_server_wait(self.h, int(ticket), ctypes.byref(info), ctypes.byref(lat))
+        Hc, Sc, evals, X = self._live.pop(ticket)
+        if st != 0 and raise_on_error:
+            msg = self.lib.chfsi_server_last_error(self.h)
+            raise ChfsiError(st, msg.decode() if msg else "")
+        return evals, X, info.as_dict(), lat.value, st
+
+    def stats(self):
+        s = ServerStatistics()
+        self.lib.chfsi_server_stats(self.h, ctypes.byref(s))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def release_sequence(self, seq):
+        st = self.lib.chfsi_server_release_sequence(self.h, int(seq))
+        if st != 0:
+            raise ChfsiError(st, "sequence busy")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.chfsi_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

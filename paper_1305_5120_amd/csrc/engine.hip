@@ -5,10 +5,18 @@
 // context's stream; the host only sequences launches, reads back the k_a Ritz
 // values and residual norms once per outer iteration and takes the locking
 // decision.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/chfsi.h"
@@ -50,6 +58,30 @@ struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
+// Coefficients of the m degree steps of the scaled Chebyshev filter
+// (eq. (3) on (A - cI)/e, normalized at a0): step i computes
+//   Y_{i+1} = alpha_i A Y_i + beta_i Y_i + gamma_i Y_{i-1}   (gamma_0 = 0).
+struct ChebStep {
+  double alpha, beta, gamma;
+};
+
+std::vector<ChebStep> cheb_schedule(int m, double a, double b, double a0) {
+  std::vector<ChebStep> out(m);
+  const double e = (b - a) / 2.0, c = (b + a) / 2.0;
+  const double sigma1 = e / (a0 - c);
+  const double tau = 2.0 / sigma1;
+  const double al1 = sigma1 / e;
+  out[0] = {al1, -al1 * c, 0.0};
+  double sigma = sigma1;
+  for (int i = 1; i < m; i++) {
+    const double sn = 1.0 / (tau - sigma);
+    const double al = 2.0 * sn / e;
+    out[i] = {al, -al * c, -sigma * sn};
+    sigma = sn;
+  }
+  return out;
+}
+
 }  // namespace
 
 struct chfsi_ctx_s {
@@ -74,6 +106,8 @@ struct chfsi_ctx_s {
   DBuf hpart, htop, tau, Tall, gram, Vp, Wt, W2;
   // Lanczos
   DBuf LV, Lw, Lh, Lab, mvpart, Tsm, Tz, Tz2, Tw, npart;
+  // sparse Jacobi schedules
+  DBuf jint, jrot;
   // host staging (pinned)
   double* hbuf = nullptr;
   size_t hbuf_elems = 0;
@@ -101,7 +135,10 @@ struct chfsi_ctx_s {
 
   void ensure_host(size_t elems) {
     if (hbuf_elems >= elems) return;
-    if (hbuf) (void)hipHostFree(hbuf);
+    if (hbuf) {
+      CHFSI_HIP(hipStreamSynchronize(st));  // no copy may still target the old buffer
+      (void)hipHostFree(hbuf);
+    }
     hbuf = nullptr;
     hbuf_elems = 0;
     CHFSI_HIP(hipHostMalloc((void**)&hbuf, elems * sizeof(double), hipHostMallocDefault));
@@ -182,7 +219,7 @@ struct chfsi_ctx_s {
   void free_all() {
     for (DBuf* b : {&A32, &Y32, &Y32b, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
                     &flags, &P, &hpart, &htop, &tau, &Tall, &gram, &Vp, &Wt, &W2, &LV, &Lw, &Lh, &Lab, &mvpart, &Tsm,
-                    &Tz, &Tz2, &Tw, &npart})
+                    &Tz, &Tz2, &Tw, &npart, &jint, &jrot})
       b->release();
     if (hbuf) (void)hipHostFree(hbuf);
     hbuf = nullptr;
@@ -284,37 +321,111 @@ struct chfsi_ctx_s {
   // ------------------------------------------------------------------------
   // Hermitian eigensolver (Jacobi) into w (device, ascending), Zo (device)
   // ------------------------------------------------------------------------
-  void eigh(const zc* Gp, int64_t ldg, int64_t k, double* w, zc* Zo, int64_t ldz) {
+  // tau > 0: couplings |G(p,q)| <= tau count as converged (the solver passes
+  // a value far below its lock scale: such couplings change Ritz vectors by
+  // less than their residual tolerance); tau = 0 iterates to working accuracy.
+  void eigh(const zc* Gp, int64_t ldg, int64_t k, double* w, zc* Zo, int64_t ldz, double tau = 0.0) {
     if (k <= JACOBI_LDS_MAX) {
-      jacobi_small(Gp, ldg, k, w, Zo, ldz, Ztmp.z(), nullptr, st);
+      jacobi_small(Gp, ldg, k, w, Zo, ldz, Ztmp.z(), nullptr, st, tau);
       return;
     }
+    // Larger k: sweeps of the parallel (round-robin) ordering while the
+    // matrix is far from diagonal; once few couplings remain significant
+    // (|g|^2 > 1e-34 ||G||_F^2), sparse sweeps rotate only those pairs,
+    // grouped into disjoint rounds.
     zc *g0 = G2.z(), *z0 = Ztmp.z(), *g1 = Z2.z();
-    // Z2 and a second k x k buffer: reuse Wz's storage for the Z ping-pong
-    zc* z1 = Wz.z();
+    zc* z1 = Wz.z();  // Wz (n x k) doubles as the second Z buffer
     jacobi_init(Gp, ldg, k, g0, z0, st);
     double* nr = norms.d();
     jacobi_norms(g0, k, npart.d(), nr, st);  // nr[0] = off, nr[1] = all (fro2)
-    CHFSI_HIP(hipMemcpyAsync(hbuf, nr, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    sync();
-    const double fro2 = hbuf[1];
-    double off2 = hbuf[0];
     const int64_t K2 = k + (k & 1);
-    for (int sweep = 0; sweep < 100 && off2 > 1e-32 * fro2 && off2 != 0.0; sweep++) {
+    const double THR = 1e-34;
+    const int64_t max_sparse = 8 * k;
+    const int max_rounds = 64;
+    const size_t ints = (size_t)2 * k + 2 * max_sparse + (size_t)max_rounds * k + 2 * max_sparse;
+    jint.ensure(ints * sizeof(int));
+    jrot.ensure((size_t)(k / 2 + 1) * jacobi_rot_bytes());
+    ensure_host(ints / 2 + 16);
+    int* counts = jint.i();
+    int* offsets = counts + k;
+    int* pairs = offsets + k;
+    int* rounds_d = pairs + 2 * max_sparse;
+    for (int sweep = 0; sweep < 100; sweep++) {
+      jacobi_count(g0, k, nr + 1, THR, tau, counts, st);
+      CHFSI_HIP(hipMemcpyAsync(hbuf, counts, k * sizeof(int), hipMemcpyDeviceToHost, st));
+      sync();
+      const int* hc = reinterpret_cast<const int*>(hbuf);
+      int64_t total = 0;
+      std::vector<int> off(k);
+      for (int64_t j = 0; j < k; j++) {
+        off[j] = (int)total;
+        total += hc[j];
+      }
+      if (total == 0) break;
+      bool sparse = total > 0 && total <= max_sparse;
+      std::vector<std::vector<int>> rounds;
+      if (sparse) {
+        std::memcpy(hbuf, off.data(), k * sizeof(int));
+        CHFSI_HIP(hipMemcpyAsync(offsets, hbuf, k * sizeof(int), hipMemcpyHostToDevice, st));
+        jacobi_list(g0, k, nr + 1, THR, tau, offsets, pairs, st);
+        CHFSI_HIP(hipMemcpyAsync(hbuf, pairs, 2 * total * sizeof(int), hipMemcpyDeviceToHost, st));
+        sync();
+        const int* hp = reinterpret_cast<const int*>(hbuf);
+        // greedy assignment of each pair to the first round where both of its
+        // indices are free
+        std::vector<uint64_t> busy((size_t)k, 0);
+        for (int64_t t = 0; t < total && sparse; t++) {
+          const int p = hp[2 * t], q = hp[2 * t + 1];
+          const uint64_t free_mask = ~(busy[p] | busy[q]);
+          if (!free_mask) {
+            sparse = false;
+            break;
+          }
+          const int r = __builtin_ctzll(free_mask);
+          if (r >= max_rounds) {
+            sparse = false;
+            break;
+          }
+          if ((int)rounds.size() <= r) rounds.resize(r + 1);
+          rounds[r].push_back(p);
+          rounds[r].push_back(q);
+          busy[p] |= (1ull << r);
+          busy[q] |= (1ull << r);
+        }
+      }
+      if (sparse) {
+        // device layout per round: pairs (2 np ints), then pair index per row (k ints)
+        int* hr = reinterpret_cast<int*>(hbuf);
+        size_t pos = 0;
+        std::vector<size_t> start(rounds.size());
+        for (size_t r = 0; r < rounds.size(); r++) {
+          start[r] = pos;
+          std::memcpy(hr + pos, rounds[r].data(), rounds[r].size() * sizeof(int));
+          pos += rounds[r].size();
+          int* po = hr + pos;
+          for (int64_t i = 0; i < k; i++) po[i] = -1;
+          for (size_t a = 0; a < rounds[r].size() / 2; a++) {
+            po[rounds[r][2 * a]] = (int)a;
+            po[rounds[r][2 * a + 1]] = (int)a;
+          }
+          pos += k;
+        }
+        CHFSI_HIP(hipMemcpyAsync(rounds_d, hr, pos * sizeof(int), hipMemcpyHostToDevice, st));
+        fill_i32(flags.i() + 1, 1, 0, st);
+        for (size_t r = 0; r < rounds.size(); r++) {
+          const int np = (int)(rounds[r].size() / 2);
+          const int* pr = rounds_d + start[r];
+          jacobi_sparse_round(g0, z0, k, pr, np, pr + 2 * np, jrot.p, nr + 1, tau, flags.i() + 1, st);
+        }
+        continue;
+      }
+      // dense sweep
       fill_i32(flags.i() + 1, 1, 0, st);
       for (int64_t r = 0; r < K2 - 1; r++) {
-        jacobi_round(g0, g1, z0, z1, k, r, nr + 1, flags.i() + 1, st);
+        jacobi_round(g0, g1, z0, z1, k, r, nr + 1, flags.i() + 1, st, tau);
         std::swap(g0, g1);
         std::swap(z0, z1);
       }
-      jacobi_norms(g0, k, npart.d(), nr + 2, st);
-      CHFSI_HIP(hipMemcpyAsync(hbuf, nr + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      CHFSI_HIP(hipMemcpyAsync(hbuf + 2, flags.i() + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-      sync();
-      off2 = hbuf[0];
-      int rot;
-      std::memcpy(&rot, hbuf + 2, sizeof(int));
-      if (!rot) break;
     }
     jacobi_sort(g0, z0, k, w, rank.i(), Zo, ldz, st);
   }
@@ -400,9 +511,6 @@ struct chfsi_ctx_s {
   // The filter in either precision: element type zc (FP64) or cc (FP32).
   void* filter_any(int prec, const void* Ap, int64_t lda, void* Yp, int64_t ldy, void* Ybp, int64_t ldyb, int64_t ka, int m,
                    double a, double b, double a0) {
-    const double e = (b - a) / 2.0, c = (b + a) / 2.0;
-    const double sigma1 = e / (a0 - c);
-    const double tau_ = 2.0 / sigma1;
     const bool prof = opts.profile != 0;
     if (prof && (int)fev.size() < m) {
       for (int i = (int)fev.size(); i < m; i++) {
@@ -427,20 +535,16 @@ struct chfsi_ctx_s {
       zgemm(g, gw(), st);
       if (prof) CHFSI_HIP(hipEventRecord(fev[i].b, st));
     };
+    const std::vector<ChebStep> cs = cheb_schedule(m, a, b, a0);
     // Y_1 = (sigma1/e)(A - cI) Y_0
-    const double al1 = sigma1 / e;
-    step(0, Yp, ldy, Ybp, ldyb, al1, -al1 * c, 0.0, nullptr, 0);
+    step(0, Yp, ldy, Ybp, ldyb, cs[0].alpha, cs[0].beta, 0.0, nullptr, 0);
     void *cur = Ybp, *prev = Yp;
     int64_t ldc = ldyb, ldp = ldy;
-    double sigma = sigma1;
-    for (int i = 2; i <= m; i++) {
-      const double sn = 1.0 / (tau_ - sigma);
-      const double al = 2.0 * sn / e;
-      // Y_i = al (A - cI) Y_{i-1} - sigma sn Y_{i-2}, written over Y_{i-2}
-      step(i - 1, cur, ldc, prev, ldp, al, -al * c, -sigma * sn, prev, ldp);
+    for (int i = 1; i < m; i++) {
+      // Y_{i+1} = alpha (A - cI)-scaled product - sigma sigma' Y_{i-1}, over Y_{i-1}
+      step(i, cur, ldc, prev, ldp, cs[i].alpha, cs[i].beta, cs[i].gamma, prev, ldp);
       std::swap(cur, prev);
       std::swap(ldc, ldp);
-      sigma = sn;
     }
     filt_launches[prec] += m;
     filt_flops[prec] += 8.0 * (double)n * (double)n * (double)ka * (double)m;
@@ -462,11 +566,11 @@ struct chfsi_ctx_s {
   // WZo = A Yo (through W Z).
   // ------------------------------------------------------------------------
   void rayleigh_ritz(const zc* Ap, int64_t lda, const zc* Qa, int64_t ldq, int64_t ka, zc* Yo, int64_t ldyo, double* mu_d,
-                     zc* Wbuf, zc* WZo) {
+                     zc* Wbuf, zc* WZo, double tau = 0.0) {
     gemm(OP_N, OP_N, n, ka, n, 1.0, Ap, lda, Qa, ldq, Wbuf, n);
     gemm(OP_C, OP_N, ka, ka, n, 1.0, Qa, ldq, Wbuf, n, G.z(), ka);
     hermitize(G.z(), ka, ka, st);
-    eigh(G.z(), ka, ka, mu_d, Z.z(), ka);
+    eigh(G.z(), ka, ka, mu_d, Z.z(), ka, tau);
     gemm(OP_N, OP_N, n, ka, ka, 1.0, Qa, ldq, Z.z(), ka, Yo, ldyo);
     if (WZo) gemm(OP_N, OP_N, n, ka, ka, 1.0, Wbuf, n, Z.z(), ka, WZo, n);
   }
@@ -567,29 +671,71 @@ void check_ptr(const void* p, const char* name) {
   if (!p) throw Error(ST_EINVAL, std::string("null pointer: ") + name);
 }
 
-// Run the whole of Algorithm 1.
-void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds, int64_t nev, int64_t nex, const zc* Vw,
-                int64_t ldv, int64_t kw, double tol, double* evals, zc* X, int64_t ldx, chfsi_info* info) {
-  const int64_t n = c->n;
-  const int64_t k = nev + nex;
-  if (nev < 1 || nex < 0 || k > n) throw Error(ST_EINVAL, "need 1 <= nev and nev + nex <= n");
-  if (!(tol > 0.0)) throw Error(ST_EINVAL, "tol must be positive");
-  if (kw < 0 || kw > k) throw Error(ST_EINVAL, "kw out of range");
-  check_ptr(H, "H");
-  check_ld(ldh, n, "ldh");
-  if (S) check_ld(lds, n, "lds");
-  if (Vw && kw > 0) check_ld(ldv, n, "ldv");
-  if (X) check_ld(ldx, n, "ldx");
-  check_ptr(evals, "evals");
-  const chfsi_opts& o = c->opts;
-  hipStream_t st = c->st;
+// Algorithm 1 in phases, so that a batch of problems can run its filters in
+// shared launches: solve_begin (reduction, Lanczos, start block, bounds),
+// then per outer iteration solve_filter (the Chebyshev filter of the active
+// columns into F) and solve_post (QR, Rayleigh-Ritz, residuals, locking),
+// then solve_finish (outputs and warm state).
+struct SolveState {
+  const zc* H = nullptr;
+  int64_t ldh = 0;
+  const zc* S = nullptr;
+  int64_t lds = 0;
+  int64_t nev = 0, nex = 0, k = 0;
+  const zc* Vw = nullptr;
+  int64_t ldv = 0, kw = 0;
+  double tol = 0;
+  double* evals = nullptr;
+  zc* X = nullptr;
+  int64_t ldx = 0;
+  const double* bounds_in = nullptr;
 
   chfsi_info inf{};
-  auto t_start = std::chrono::steady_clock::now();
-  auto now = [&]() { return std::chrono::steady_clock::now(); };
-  auto secs = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
-    return std::chrono::duration<double>(b - a).count();
-  };
+  std::chrono::steady_clock::time_point t_start;
+  double a0 = 0, a = 0, b = 0, hs = 0;
+  int64_t cl = 0;
+  int it = 0;
+  bool converged = false, done = false, mixed = false;
+  std::vector<double> lam, rho_lock;
+  std::vector<hipEvent_t> ev;
+  // mixed-precision bookkeeping
+  int64_t fp64_col = -1, prev_col = -1;
+  double prev_rho = INFINITY;
+  bool prev32 = false, use32 = false;
+
+  ~SolveState() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+// Mixed precision: the filter runs in complex FP32 while the first active
+// column's generalized residual is above MIXED_SWITCH * h_H and still
+// falling at least twofold per FP32 iteration; that column then gets FP64
+// filtering until it locks.  Everything else stays FP64, and locking uses
+// the FP64 residuals, so the accepted pairs meet the same tolerance.
+constexpr double MIXED_SWITCH = 1e-5;
+
+double secs_since(std::chrono::steady_clock::time_point a) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+}
+
+void solve_begin(chfsi_ctx c, SolveState& s) {
+  const int64_t n = c->n;
+  s.k = s.nev + s.nex;
+  const int64_t k = s.k;
+  if (s.nev < 1 || s.nex < 0 || k > n) throw Error(ST_EINVAL, "need 1 <= nev and nev + nex <= n");
+  if (!(s.tol > 0.0)) throw Error(ST_EINVAL, "tol must be positive");
+  if (s.kw < 0 || s.kw > k) throw Error(ST_EINVAL, "kw out of range");
+  check_ptr(s.H, "H");
+  check_ld(s.ldh, n, "ldh");
+  if (s.S) check_ld(s.lds, n, "lds");
+  if (s.Vw && s.kw > 0) check_ld(s.ldv, n, "ldv");
+  if (s.X) check_ld(s.ldx, n, "ldx");
+  check_ptr(s.evals, "evals");
+  const chfsi_opts& o = c->opts;
+  hipStream_t st = c->st;
+  chfsi_info& inf = s.inf;
+  s.t_start = std::chrono::steady_clock::now();
   c->reset_filter_stats();
 
   c->ensure_nn();
@@ -598,194 +744,808 @@ void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds,
   c->ensure_k(k);
   // a warm block meant for a changed S goes through the generalized space:
   // X_old = L_old^{-H} Y (into F) before the new factor replaces L_old
-  const bool use_state = (Vw == nullptr || kw == 0) && state_ok;
-  if (use_state && S && c->have_factors)
+  const bool use_state = (s.Vw == nullptr || s.kw == 0) && state_ok;
+  if (use_state && s.S && c->have_factors)
     c->gemm(OP_C, OP_N, n, k, n, 1.0, c->Linv.z(), n, c->Y.z(), n, c->F.z(), n, 0.0, nullptr, 0, 0.0, nullptr, 0,
             GEMM_TRI_A_UPPER);
 
-  auto t0 = now();
-  c->reduce(H, ldh, S, lds);
-  const bool mixed = o.precision == 1;
-  if (mixed) {
+  auto t0 = std::chrono::steady_clock::now();
+  c->reduce(s.H, s.ldh, s.S, s.lds);
+  s.mixed = o.precision == 1;
+  if (s.mixed) {
     c->A32.ensure((size_t)n * n * sizeof(cc));
     c->Y32.ensure((size_t)n * k * sizeof(cc));
     c->Y32b.ensure((size_t)n * k * sizeof(cc));
     to_f32(c->A.z(), n, (cc*)c->A32.p, n, n, n, st);
   }
   c->sync();
-  inf.t_reduce = secs(t0, now());
+  inf.t_reduce = secs_since(t0);
 
-  t0 = now();
+  t0 = std::chrono::steady_clock::now();
   double lz[3];
   c->lanczos(c->A.z(), n, o.lanczos_steps, o.seed, 1u, lz);
   inf.theta_min = lz[0];
   inf.b_upper = lz[2];
-  c->lanczos(H, ldh, o.lanczos_steps, o.seed, 2u, lz);
+  c->lanczos(s.H, s.ldh, o.lanczos_steps, o.seed, 2u, lz);
   inf.h_H = std::max(std::fabs(lz[0]), std::fabs(lz[1]));
-  inf.t_lanczos = secs(t0, now());
+  inf.t_lanczos = secs_since(t0);
 
   zc* Y = c->Y.z();
-  zc* Yb = c->Yb.z();
   zc* F = c->F.z();
   zc* Qb = c->Qb.z();
-  zc* Wk = c->Wk.z();
-  zc* Wz = c->Wz.z();
-  double* mu_d = c->mu.d();
-  double* rho_d = c->rho.d();
-  double* hb = c->hbuf;
-
   // start block
   bool warm = false;
-  if (Vw && kw > 0) {
-    c->gemm(OP_C, OP_N, n, kw, n, 1.0, c->L.z(), n, Vw, ldv, Y, n, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_A_UPPER);
-    if (kw < k) random_block(o.seed, 3u, n, k - kw, kw, Y + kw * n, n, st);
+  if (s.Vw && s.kw > 0) {
+    c->gemm(OP_C, OP_N, n, s.kw, n, 1.0, c->L.z(), n, s.Vw, s.ldv, Y, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+            GEMM_TRI_A_UPPER);
+    if (s.kw < k) random_block(o.seed, 3u, n, k - s.kw, s.kw, Y + s.kw * n, n, st);
     warm = true;
   } else if (use_state) {
-    if (S) c->gemm(OP_C, OP_N, n, k, n, 1.0, c->L.z(), n, F, n, Y, n, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_A_UPPER);
+    if (s.S) c->gemm(OP_C, OP_N, n, k, n, 1.0, c->L.z(), n, F, n, Y, n, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_A_UPPER);
     warm = true;
   } else {
     random_block(o.seed, 3u, n, k, 0, Y, n, st);
   }
   copy2d(Y, n, F, n, n, k, st);
   inf.qr_householder += c->orthonormalize(F, k, Qb, n) ? 1 : 0;
-  double a0, a;
-  const double b = inf.b_upper;
-  if (warm && c->warm_valid && c->warm_k == k) {
+  s.b = inf.b_upper;
+  if (warm && s.bounds_in) {
     copy2d(Qb, n, Y, n, n, k, st);
-    a0 = c->warm_a0;
-    a = c->warm_a;
+    s.a0 = s.bounds_in[0];
+    s.a = s.bounds_in[1];
+  } else if (warm && c->warm_valid && c->warm_k == k) {
+    copy2d(Qb, n, Y, n, n, k, st);
+    s.a0 = c->warm_a0;
+    s.a = c->warm_a;
   } else {
-    c->rayleigh_ritz(c->A.z(), n, Qb, n, k, Y, n, mu_d, Wk, nullptr);
-    CHFSI_HIP(hipMemcpyAsync(hb, mu_d, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    c->rayleigh_ritz(c->A.z(), n, Qb, n, k, Y, n, c->mu.d(), c->Wk.z(), nullptr);
+    double* hb = c->hbuf;
+    CHFSI_HIP(hipMemcpyAsync(hb, c->mu.d(), k * sizeof(double), hipMemcpyDeviceToHost, st));
     c->sync();
-    a0 = std::min(inf.theta_min, hb[0]);
-    a = hb[k - 1];
+    s.a0 = std::min(inf.theta_min, hb[0]);
+    s.a = hb[k - 1];
   }
   inf.warm_start = warm ? 1 : 0;
   c->warm_valid = false;  // the block is being rewritten
+  s.lam.assign(k, NAN);
+  s.rho_lock.assign(k, 0.0);
+  s.cl = 0;
+  s.it = 0;
+  s.hs = s.tol * inf.h_H;
+  s.ev.resize(5);
+  for (auto& e : s.ev) CHFSI_HIP(hipEventCreate(&e));
+}
 
-  std::vector<double> lam(k, NAN), rho_lock(k, 0.0);
-  int64_t cl = 0;
-  int it = 0;
-  const double hs = tol * inf.h_H;
-  bool converged = false;
-  std::vector<hipEvent_t> ev(5);
-  for (auto& e : ev) CHFSI_HIP(hipEventCreate(&e));
-  struct EvGuard {
-    std::vector<hipEvent_t>& v;
-    ~EvGuard() {
-      for (auto e : v) (void)hipEventDestroy(e);
-    }
-  } evg{ev};
-  // Mixed precision: the filter runs in complex FP32 while the first active
-  // column's generalized residual is above MIXED_SWITCH * h_H and still
-  // falling at least twofold per FP32 iteration; that column then gets FP64
-  // filtering until it locks.  Everything else stays FP64, and locking uses
-  // the FP64 residuals, so the accepted pairs meet the same tolerance.
-  const double MIXED_SWITCH = 1e-5;
-  int64_t fp64_col = -1, prev_col = -1;
-  double prev_rho = INFINITY;
-  bool prev32 = false;
-  for (it = 1; it <= o.max_iter; it++) {
-    const int64_t ka = k - cl;
-    bool use32 = false;
-    if (mixed) {
-      use32 = fp64_col != cl;
-      if (use32 && prev_col == cl && prev_rho <= MIXED_SWITCH * inf.h_H) {
-        use32 = false;
-        fp64_col = cl;
-      }
-    }
-    CHFSI_HIP(hipEventRecord(ev[0], st));
-    if (use32) {
-      cc* y32 = (cc*)c->Y32.p;
-      cc* y32b = (cc*)c->Y32b.p;
-      to_f32(Y + cl * n, n, y32, n, n, ka, st);
-      void* r32 = c->filter_any(PREC_F32, c->A32.p, n, y32, n, y32b, n, ka, o.degree, a, b, a0);
-      to_f64((const cc*)r32, n, F + cl * n, n, n, ka, st);
-      inf.iterations_fp32++;
-    } else {
-      zc* res = c->filter(c->A.z(), n, Y + cl * n, n, Yb + cl * n, n, ka, o.degree, a, b, a0);
-      copy2d(res, n, F + cl * n, n, n, ka, st);
-    }
-    CHFSI_HIP(hipEventRecord(ev[1], st));
-    if (cl > 0) copy2d(Y, n, F, n, n, cl, st);
-    inf.qr_householder += c->orthonormalize(F, k, Qb, n) ? 1 : 0;
-    CHFSI_HIP(hipEventRecord(ev[2], st));
-    c->rayleigh_ritz(c->A.z(), n, Qb + cl * n, n, ka, Y + cl * n, n, mu_d, Wk, Wz);
-    CHFSI_HIP(hipEventRecord(ev[3], st));
-    c->residual_norms(c->L.z(), n, Wz, Y + cl * n, n, ka, mu_d, Wk, F, rho_d);
-    CHFSI_HIP(hipMemcpyAsync(hb, mu_d, ka * sizeof(double), hipMemcpyDeviceToHost, st));
-    CHFSI_HIP(hipMemcpyAsync(hb + ka, rho_d, ka * sizeof(double), hipMemcpyDeviceToHost, st));
-    CHFSI_HIP(hipEventRecord(ev[4], st));
-    c->sync();
-    float ms[4];
-    for (int i = 0; i < 4; i++) CHFSI_HIP(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
-    inf.t_filter += ms[0] * 1e-3;
-    inf.t_qr += ms[1] * 1e-3;
-    inf.t_rr += ms[2] * 1e-3;
-    inf.t_resid += ms[3] * 1e-3;
-    c->collect_filter_events(o.degree);
-    const double* mu = hb;
-    const double* rho = hb + ka;
-    for (int64_t j = 0; j < ka; j++)
-      if (!std::isfinite(mu[j]) || !std::isfinite(rho[j]))
-        throw Error(ST_ENAN, "non-finite Ritz value or residual at iteration " + std::to_string(it));
-    int64_t nl = 0;
-    while (cl + nl < nev && nl < ka && rho[nl] <= hs) {
-      lam[cl + nl] = mu[nl];
-      rho_lock[cl + nl] = rho[nl];
-      nl++;
-    }
-    for (int64_t j = nl; j < ka; j++) {
-      lam[cl + j] = mu[j];
-      rho_lock[cl + j] = rho[j];
-    }
-    if (mixed) {
-      // stall of an FP32 iteration on the same first column
-      if (prev32 && prev_col == cl && rho[0] > 0.5 * prev_rho) fp64_col = cl;
-      prev32 = use32;
-      prev_col = cl + nl;
-      prev_rho = nl < ka ? rho[nl] : INFINITY;
-    }
-    cl += nl;
-    a = mu[ka - 1];
-    a0 = std::min(a0, mu[0]);
-    inf.converged = (int32_t)cl;
-    if (cl >= nev) {
-      converged = true;
-      break;
-    }
+// Whether this iteration's filter runs in FP32 (mixed precision only).
+bool solve_wants_fp32(const SolveState& s) {
+  if (!s.mixed) return false;
+  if (s.fp64_col == s.cl) return false;
+  if (s.prev_col == s.cl && s.prev_rho <= MIXED_SWITCH * s.inf.h_H) return false;
+  return true;
+}
+
+// Host side of an outer iteration's start: count it and fix the precision
+// of its filter.
+void solve_filter_begin(SolveState& s) {
+  s.it++;
+  s.use32 = solve_wants_fp32(s);
+  if (s.mixed && !s.use32 && s.fp64_col != s.cl && s.prev_col == s.cl) s.fp64_col = s.cl;
+}
+
+// The filter of the active columns, result into F(:, cl:k).
+void solve_filter(chfsi_ctx c, SolveState& s) {
+  const int64_t n = c->n, ka = s.k - s.cl;
+  hipStream_t st = c->st;
+  solve_filter_begin(s);
+  CHFSI_HIP(hipEventRecord(s.ev[0], st));
+  zc* Y = c->Y.z();
+  zc* F = c->F.z();
+  if (s.use32) {
+    cc* y32 = (cc*)c->Y32.p;
+    cc* y32b = (cc*)c->Y32b.p;
+    to_f32(Y + s.cl * n, n, y32, n, n, ka, st);
+    void* r32 = c->filter_any(PREC_F32, c->A32.p, n, y32, n, y32b, n, ka, c->opts.degree, s.a, s.b, s.a0);
+    to_f64((const cc*)r32, n, F + s.cl * n, n, n, ka, st);
+    s.inf.iterations_fp32++;
+  } else {
+    zc* res = c->filter(c->A.z(), n, Y + s.cl * n, n, c->Yb.z() + s.cl * n, n, ka, c->opts.degree, s.a, s.b, s.a0);
+    copy2d(res, n, F + s.cl * n, n, n, ka, st);
   }
-  inf.iterations = std::min(it, o.max_iter);
-  inf.a0 = a0;
-  inf.a = a;
-  const int64_t nout = converged ? nev : cl;
+  CHFSI_HIP(hipEventRecord(s.ev[1], st));
+}
+
+// QR, Rayleigh-Ritz, residuals and locking after the filter.
+void solve_post(chfsi_ctx c, SolveState& s) {
+  const int64_t n = c->n, k = s.k, ka = k - s.cl, cl = s.cl;
+  hipStream_t st = c->st;
+  chfsi_info& inf = s.inf;
+  zc* Y = c->Y.z();
+  zc* F = c->F.z();
+  zc* Qb = c->Qb.z();
+  double* mu_d = c->mu.d();
+  double* rho_d = c->rho.d();
+  if (cl > 0) copy2d(Y, n, F, n, n, cl, st);
+  inf.qr_householder += c->orthonormalize(F, k, Qb, n) ? 1 : 0;
+  CHFSI_HIP(hipEventRecord(s.ev[2], st));
+  c->rayleigh_ritz(c->A.z(), n, Qb + cl * n, n, ka, Y + cl * n, n, mu_d, c->Wk.z(), c->Wz.z(), 1e-3 * s.hs);
+  CHFSI_HIP(hipEventRecord(s.ev[3], st));
+  c->residual_norms(c->L.z(), n, c->Wz.z(), Y + cl * n, n, ka, mu_d, c->Wk.z(), F, rho_d);
+  double* hb = c->hbuf;
+  CHFSI_HIP(hipMemcpyAsync(hb, mu_d, ka * sizeof(double), hipMemcpyDeviceToHost, st));
+  CHFSI_HIP(hipMemcpyAsync(hb + ka, rho_d, ka * sizeof(double), hipMemcpyDeviceToHost, st));
+  CHFSI_HIP(hipEventRecord(s.ev[4], st));
+  c->sync();
+  float ms[4];
+  for (int i = 0; i < 4; i++) CHFSI_HIP(hipEventElapsedTime(&ms[i], s.ev[i], s.ev[i + 1]));
+  inf.t_filter += ms[0] * 1e-3;
+  inf.t_qr += ms[1] * 1e-3;
+  inf.t_rr += ms[2] * 1e-3;
+  inf.t_resid += ms[3] * 1e-3;
+  c->collect_filter_events(c->opts.degree);
+  const double* mu = hb;
+  const double* rho = hb + ka;
+  for (int64_t j = 0; j < ka; j++)
+    if (!std::isfinite(mu[j]) || !std::isfinite(rho[j]))
+      throw Error(ST_ENAN, "non-finite Ritz value or residual at iteration " + std::to_string(s.it));
+  int64_t nl = 0;
+  while (cl + nl < s.nev && nl < ka && rho[nl] <= s.hs) {
+    s.lam[cl + nl] = mu[nl];
+    s.rho_lock[cl + nl] = rho[nl];
+    nl++;
+  }
+  for (int64_t j = nl; j < ka; j++) {
+    s.lam[cl + j] = mu[j];
+    s.rho_lock[cl + j] = rho[j];
+  }
+  if (s.mixed) {
+    // stall of an FP32 iteration on the same first column
+    if (s.prev32 && s.prev_col == cl && rho[0] > 0.5 * s.prev_rho) s.fp64_col = cl;
+    s.prev32 = s.use32;
+    s.prev_col = cl + nl;
+    s.prev_rho = nl < ka ? rho[nl] : INFINITY;
+  }
+  s.cl += nl;
+  s.a = mu[ka - 1];
+  s.a0 = std::min(s.a0, mu[0]);
+  inf.converged = (int32_t)s.cl;
+  if (s.cl >= s.nev) {
+    s.converged = true;
+    s.done = true;
+  } else if (s.it >= c->opts.max_iter) {
+    s.done = true;
+  }
+}
+
+void solve_finish(chfsi_ctx c, SolveState& s, chfsi_info* info) {
+  const int64_t n = c->n;
+  chfsi_info& inf = s.inf;
+  inf.iterations = s.it;
+  inf.a0 = s.a0;
+  inf.a = s.a;
+  const int64_t nout = s.converged ? s.nev : s.cl;
   double mx = 0.0;
-  for (int64_t j = 0; j < nev; j++) {
-    evals[j] = j < nout ? lam[j] : NAN;
-    if (j < nout) mx = std::max(mx, rho_lock[j] / inf.h_H);
+  for (int64_t j = 0; j < s.nev; j++) {
+    s.evals[j] = j < nout ? s.lam[j] : NAN;
+    if (j < nout) mx = std::max(mx, s.rho_lock[j] / inf.h_H);
   }
   inf.max_rel_residual = mx;
-  if (X && nev > 0)
-    c->gemm(OP_C, OP_N, n, nev, n, 1.0, c->Linv.z(), n, Y, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_A_UPPER);
+  if (s.X && s.nev > 0)
+    c->gemm(OP_C, OP_N, n, s.nev, n, 1.0, c->Linv.z(), n, c->Y.z(), n, s.X, s.ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
+            GEMM_TRI_A_UPPER);
   c->sync();
   // warm state for the next problem of the sequence
   c->warm_valid = true;
-  c->warm_k = k;
-  c->warm_a0 = a0;
-  c->warm_a = a;
+  c->warm_k = s.k;
+  c->warm_a0 = s.a0;
+  c->warm_a = s.a;
   inf.filter_flops = c->filt_flops[0] + c->filt_flops[1];
   inf.filter_launches = c->filt_launches[0] + c->filt_launches[1];
   inf.filter_kernel_seconds = c->filt_kernel_s[0] + c->filt_kernel_s[1];
   inf.filter_flops_fp32 = c->filt_flops[1];
   inf.filter_launches_fp32 = c->filt_launches[1];
   inf.filter_kernel_seconds_fp32 = c->filt_kernel_s[1];
-  inf.t_total = secs(t_start, now());
+  inf.t_total = secs_since(s.t_start);
   if (info) *info = inf;
-  if (!converged)
-    throw Error(ST_ENOCONV, "not converged after " + std::to_string(o.max_iter) + " iterations (" + std::to_string(cl) +
-                                " of " + std::to_string(nev) + " locked)");
+  if (!s.converged)
+    throw Error(ST_ENOCONV, "not converged after " + std::to_string(c->opts.max_iter) + " iterations (" +
+                                std::to_string(s.cl) + " of " + std::to_string(s.nev) + " locked)");
+}
+
+// Run the whole of Algorithm 1.
+void solve_impl(chfsi_ctx c, const zc* H, int64_t ldh, const zc* S, int64_t lds, int64_t nev, int64_t nex, const zc* Vw,
+                int64_t ldv, int64_t kw, double tol, double* evals, zc* X, int64_t ldx, chfsi_info* info,
+                const double* bounds_in = nullptr) {
+  SolveState s;
+  s.H = H; s.ldh = ldh; s.S = S; s.lds = lds; s.nev = nev; s.nex = nex; s.Vw = Vw; s.ldv = ldv; s.kw = kw;
+  s.tol = tol; s.evals = evals; s.X = X; s.ldx = ldx; s.bounds_in = bounds_in;
+  solve_begin(c, s);
+  while (!s.done) {
+    solve_filter(c, s);
+    solve_post(c, s);
+  }
+  solve_finish(c, s, info);
+}
+
+}  // namespace
+
+// ===========================================================================
+// Serving: a request loop over many k-point sequences (Section 2: one
+// sequence of correlated problems per k-point).  Worker threads each own a
+// HIP stream and a solver context, so admitted solves overlap on the device;
+// each sequence keeps its last block (generalized space) and filter bounds on
+// the device to warm-start its next problem; requests are admitted while the
+// device memory they need fits the budget.
+// ===========================================================================
+namespace {
+
+struct SeqState {
+  int64_t n = 0, k = 0;
+  DBuf X;  // n x k block of the last solve, generalized space
+  double a0 = 0, a = 0;
+  bool valid = false, busy = false;
+};
+
+struct Req {
+  int64_t ticket = 0, seq = 0, n = 0, nev = 0, nex = 0;
+  const zc* H = nullptr;
+  int64_t ldh = 0;
+  const zc* S = nullptr;
+  int64_t lds = 0;
+  double tol = 0;
+  double* evals = nullptr;
+  zc* X = nullptr;
+  int64_t ldx = 0;
+  std::chrono::steady_clock::time_point t_submit, t_end;
+  int status = 0;
+  bool done = false;
+  chfsi_info info{};
+  std::string err;
+};
+
+struct Worker {
+  std::thread th;
+  hipStream_t st = nullptr;
+  chfsi_ctx ctx = nullptr;
+  int64_t n = 0;
+  size_t bytes = 0;  // accounted footprint of ctx
+  bool busy = false;
+};
+
+// Device bytes of a solver context for problems of size n with block k.
+size_t ctx_footprint(int64_t n, int64_t k, int precision) {
+  size_t z = sizeof(zc);
+  size_t b = z * ((size_t)4 * n * n + (size_t)6 * n * k + (size_t)13 * k * k + (size_t)4 * n * k + (size_t)64 * n);
+  if (precision == 1) b += sizeof(cc) * ((size_t)n * n + (size_t)2 * n * k);
+  return b;
+}
+
+}  // namespace
+
+struct chfsi_server_s {
+  chfsi_server_config cfg{};
+  int device = 0;
+  std::mutex m;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Req*> queue;
+  std::unordered_map<int64_t, std::unique_ptr<Req>> reqs;
+  std::unordered_map<int64_t, std::unique_ptr<SeqState>> seqs;
+  std::vector<std::unique_ptr<Worker>> workers;
+  size_t used = 0, peak = 0;
+  bool stop = false;
+  int64_t next_ticket = 1, submitted = 0, completed = 0, failed = 0, running = 0;
+  std::vector<double> lat;
+  bool have_first = false;
+  std::chrono::steady_clock::time_point t_first, t_last;
+  std::string err;
+
+  size_t seq_need(const Req& r) const {
+    auto it = seqs.find(r.seq);
+    const int64_t k = r.nev + r.nex;
+    const size_t want = (size_t)r.n * k * sizeof(zc);
+    if (it == seqs.end()) return want;
+    return it->second->X.bytes >= want ? 0 : want - it->second->X.bytes;
+  }
+
+  // Choose the next admissible request for worker w (lock held).
+  Req* pick(Worker& w) {
+    for (auto it = queue.begin(); it != queue.end(); ++it) {
+      Req* r = *it;
+      auto sq = seqs.find(r->seq);
+      if (sq != seqs.end() && sq->second->busy) continue;  // one problem of a sequence at a time, in order
+      const int64_t k = r->nev + r->nex;
+      const size_t ctx_need = ctx_footprint(r->n, k, cfg.opts.precision);
+      const size_t ctx_delta = (w.n == r->n && w.bytes >= ctx_need) ? 0 : ctx_need;
+      const size_t ctx_freed = (ctx_delta && w.ctx) ? w.bytes : 0;
+      size_t need = ctx_delta + seq_need(*r);
+      if ((size_t)cfg.hbm_budget_bytes < ctx_need + (size_t)r->n * k * sizeof(zc)) {
+        // can never fit
+        r->status = CHFSI_ENOMEM;
+        r->err = "request needs more device memory than the server budget";
+        r->done = true;
+        failed++;
+        queue.erase(it);
+        cv_done.notify_all();
+        return pick(w);
+      }
+      if (used - ctx_freed + need > (size_t)cfg.hbm_budget_bytes) {
+        // release idle workers' contexts and retry
+        for (auto& o : workers)
+          if (o.get() != &w && !o->busy && o->ctx) {
+            chfsi_release(o->ctx);
+            o->ctx = nullptr;
+            used -= o->bytes;
+            o->bytes = 0;
+            o->n = 0;
+          }
+        if (used - ctx_freed + need > (size_t)cfg.hbm_budget_bytes) continue;
+      }
+      queue.erase(it);
+      used = used - ctx_freed + need;
+      peak = std::max(peak, used);
+      if (ctx_delta) {
+        w.bytes = ctx_need;
+        w.n = -r->n;  // context to be (re)created for n by the worker
+      }
+      auto& st = seqs[r->seq];
+      if (!st) st.reset(new SeqState());
+      st->busy = true;
+      w.busy = true;
+      running++;
+      return r;
+    }
+    return nullptr;
+  }
+
+  void run(Worker& w, Req& r, SeqState& q) {
+    const int64_t k = r.nev + r.nex;
+    try {
+      if (w.n < 0) {
+        if (w.ctx) chfsi_release(w.ctx);
+        w.ctx = nullptr;
+        int st = chfsi_create(&w.ctx, r.n, &cfg.opts, w.st);
+        if (st != CHFSI_OK) throw Error(st, "server: context creation failed");
+        w.n = r.n;
+      }
+      chfsi_ctx c = w.ctx;
+      c->warm_valid = false;
+      const bool warm = q.valid && q.n == r.n && q.k == k;
+      const double bounds[2] = {q.a0, q.a};
+      c->err.clear();
+      solve_impl(c, r.H, r.ldh, r.S, r.lds, r.nev, r.nex, warm ? q.X.z() : nullptr, r.n, warm ? k : 0, r.tol, r.evals,
+                 r.X, r.ldx, &r.info, warm ? bounds : nullptr);
+      r.status = CHFSI_OK;
+    } catch (const Error& e) {
+      r.status = e.code;
+      r.err = e.what();
+    } catch (const std::exception& e) {
+      r.status = CHFSI_EHIP;
+      r.err = e.what();
+    }
+    // keep the block for the sequence's next problem (also after ENOCONV)
+    if (r.status == CHFSI_OK || r.status == CHFSI_ENOCONV) {
+      try {
+        chfsi_ctx c = w.ctx;
+        const int64_t n = r.n;
+        q.X.ensure((size_t)n * k * sizeof(zc));
+        c->gemm(OP_C, OP_N, n, k, n, 1.0, c->Linv.z(), n, c->Y.z(), n, q.X.z(), n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                GEMM_TRI_A_UPPER);
+        c->sync();
+        q.n = n;
+        q.k = k;
+        q.a0 = c->warm_a0;
+        q.a = c->warm_a;
+        q.valid = true;
+      } catch (const Error& e) {
+        q.valid = false;
+        if (r.status == CHFSI_OK) {
+          r.status = e.code;
+          r.err = e.what();
+        }
+      }
+    } else {
+      q.valid = false;
+    }
+  }
+};
+
+namespace {
+
+void server_worker(chfsi_server s, Worker* w) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->m);
+  while (true) {
+    Req* r = nullptr;
+    s->cv_work.wait(lk, [&] { return s->stop || (r = s->pick(*w)) != nullptr; });
+    if (!r) break;  // stop requested and nothing admissible
+    SeqState* q = s->seqs[r->seq].get();
+    lk.unlock();
+    s->run(*w, *r, *q);
+    lk.lock();
+    r->t_end = std::chrono::steady_clock::now();
+    r->done = true;
+    q->busy = false;
+    w->busy = false;
+    s->running--;
+    if (r->status == CHFSI_OK) {
+      s->completed++;
+      s->lat.push_back(std::chrono::duration<double>(r->t_end - r->t_submit).count());
+      s->t_last = r->t_end;
+    } else {
+      s->failed++;
+      s->err = r->err;
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Batching: Algorithm 1 for many independent problems in lockstep.  Each
+// outer iteration runs the degree steps of every member's filter as grouped
+// launches (one per step and precision), then each member's QR, Rayleigh-Ritz,
+// residuals and locking on its own stream, issued from a few host threads.
+// ===========================================================================
+namespace {
+
+// fn(i) for i in [0, count) on up to `threads` host threads, each with the
+// device current; fn must not throw.
+template <class F>
+void for_members(int count, int threads, int device, F&& fn) {
+  threads = std::max(1, std::min(threads, count));
+  if (threads == 1) {
+    for (int i = 0; i < count; i++) fn(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  th.reserve(threads);
+  for (int t = 0; t < threads; t++)
+    th.emplace_back([&] {
+      (void)hipSetDevice(device);
+      for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) fn(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+// Tile configurations the online choice tries, in order.
+constexpr int BATCH_CANDIDATES[] = {3, 4, 5, 1, 7};
+constexpr int BATCH_NCAND = sizeof(BATCH_CANDIDATES) / sizeof(BATCH_CANDIDATES[0]);
+
+}  // namespace
+
+struct chfsi_batch_s {
+  int count = 0;
+  int device = 0;
+  int threads = 8;
+  bool use_graph = false;
+  chfsi_opts opts{};
+  std::vector<chfsi_ctx> mem;
+  std::vector<hipStream_t> mst;
+  std::vector<hipEvent_t> ready;
+  hipStream_t gst = nullptr;  // the grouped launches
+  hipEvent_t gdone = nullptr;
+  hipEvent_t gt[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  // per precision: step parameters (degree x count, step-major) and tile
+  // prefixes (count + 1) on the device, with pinned staging
+  DBuf gp[2], t0[2];
+  ZGemmParams* hgp[2] = {nullptr, nullptr};
+  int64_t* ht0[2] = {nullptr, nullptr};
+  // online tile choice: chosen configuration (0 while trying), next trial,
+  // measured rates
+  int cfg[2] = {0, 0};
+  int trial[2] = {0, 0};
+  double rate[2][8] = {};
+  int grid[2][8] = {};
+  // captured degree steps per precision, for configuration gexec_cfg
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gexec_cfg[2] = {0, 0};
+  std::string err;
+
+  void destroy() {
+    for (int p = 0; p < 2; p++) {
+      if (gexec[p]) (void)hipGraphExecDestroy(gexec[p]);
+      gexec[p] = nullptr;
+      if (hgp[p]) (void)hipHostFree(hgp[p]);
+      if (ht0[p]) (void)hipHostFree(ht0[p]);
+      hgp[p] = nullptr;
+      ht0[p] = nullptr;
+      gp[p].release();
+      t0[p].release();
+      for (int q = 0; q < 2; q++)
+        if (gt[p][q]) (void)hipEventDestroy(gt[p][q]);
+    }
+    for (auto c : mem) chfsi_release(c);
+    mem.clear();
+    for (auto e : ready) (void)hipEventDestroy(e);
+    ready.clear();
+    for (auto x : mst) (void)hipStreamDestroy(x);
+    mst.clear();
+    if (gdone) (void)hipEventDestroy(gdone);
+    if (gst) (void)hipStreamDestroy(gst);
+    gdone = nullptr;
+    gst = nullptr;
+  }
+
+  int grid_of(int prec, int c) {
+    if (!grid[prec][c]) grid[prec][c] = zgemm_grouped_grid(prec, c);
+    return grid[prec][c];
+  }
+
+  // Configuration for this iteration's steps in precision prec.
+  int config_for(int prec) const { return cfg[prec] ? cfg[prec] : BATCH_CANDIDATES[trial[prec]]; }
+
+  // The m grouped steps of precision prec on gst (parameters already on the device).
+  void launch_steps(int prec, int c, int m) {
+    const ZGemmParams* g = static_cast<const ZGemmParams*>(gp[prec].p);
+    const int64_t* t = static_cast<const int64_t*>(t0[prec].p);
+    for (int i = 0; i < m; i++) zgemm_grouped_filter_step(prec, c, g + (int64_t)i * count, t, count, grid_of(prec, c), gst);
+  }
+
+  void capture(int prec, int c, int m) {
+    if (gexec[prec]) (void)hipGraphExecDestroy(gexec[prec]);
+    gexec[prec] = nullptr;
+    hipGraph_t graph = nullptr;
+    CHFSI_HIP(hipStreamBeginCapture(gst, hipStreamCaptureModeThreadLocal));
+    try {
+      launch_steps(prec, c, m);
+    } catch (...) {
+      (void)hipStreamEndCapture(gst, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    CHFSI_HIP(hipStreamEndCapture(gst, &graph));
+    hipError_t e = hipGraphInstantiate(&gexec[prec], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      gexec[prec] = nullptr;
+      throw Error(ST_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+    }
+    gexec_cfg[prec] = c;
+  }
+};
+
+namespace {
+
+struct BatchMember {
+  SolveState s;
+  int status = CHFSI_OK;
+  std::string err;
+  bool active = false;     // taking part in the current iteration
+  double iter_flops = 0;   // its filter flops in the current iteration
+};
+
+void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, const void* const* S,
+                      const int64_t* lds, const int64_t* nev, const int64_t* nex, double tol, double* const* evals,
+                      void* const* X, const int64_t* ldx, chfsi_info* infos, int32_t* statuses,
+                      chfsi_batch_report* report) {
+  const int G = b->count;
+  check_ptr(H, "H");
+  check_ptr(ldh, "ldh");
+  check_ptr(nev, "nev");
+  check_ptr(nex, "nex");
+  check_ptr(evals, "evals");
+  check_ptr(infos, "infos");
+  check_ptr(statuses, "statuses");
+  if (S) check_ptr(lds, "lds");
+  if (X) check_ptr(ldx, "ldx");
+  if (!(tol > 0.0)) throw Error(ST_EINVAL, "tol must be positive");
+  for (int j = 0; j < G; j++) {
+    const int64_t n = b->mem[j]->n;
+    const std::string w = " (member " + std::to_string(j) + ")";
+    if (!H[j]) throw Error(ST_EINVAL, "null H" + w);
+    if (!evals[j]) throw Error(ST_EINVAL, "null evals" + w);
+    if (nev[j] < 1 || nex[j] < 0 || nev[j] + nex[j] > n) throw Error(ST_EINVAL, "need 1 <= nev and nev + nex <= n" + w);
+    if (ldh[j] < n) throw Error(ST_EINVAL, "ldh smaller than n" + w);
+    if (S && S[j] && lds[j] < n) throw Error(ST_EINVAL, "lds smaller than n" + w);
+    if (X && X[j] && ldx[j] < n) throw Error(ST_EINVAL, "ldx smaller than n" + w);
+  }
+  const auto t_start = std::chrono::steady_clock::now();
+  CHFSI_HIP(hipDeviceSynchronize());  // callers' inputs are complete
+
+  chfsi_batch_report rep{};
+  const int m = b->opts.degree;
+  std::vector<std::unique_ptr<BatchMember>> mb(G);
+  for (int j = 0; j < G; j++) {
+    mb[j].reset(new BatchMember());
+    SolveState& s = mb[j]->s;
+    s.H = static_cast<const zc*>(H[j]);
+    s.ldh = ldh[j];
+    s.S = S ? static_cast<const zc*>(S[j]) : nullptr;
+    s.lds = S ? lds[j] : 0;
+    s.nev = nev[j];
+    s.nex = nex[j];
+    s.tol = tol;
+    s.evals = evals[j];
+    s.X = X ? static_cast<zc*>(X[j]) : nullptr;
+    s.ldx = X ? ldx[j] : 0;
+  }
+  auto fail = [&](int j, const Error& e) {
+    mb[j]->status = e.code;
+    mb[j]->err = e.what();
+    mb[j]->s.done = true;
+    (void)hipGetLastError();
+  };
+  auto member_guard = [&](int j, auto&& f) {
+    try {
+      f();
+    } catch (const Error& e) {
+      fail(j, e);
+    } catch (const std::exception& e) {
+      fail(j, Error(ST_EHIP, e.what()));
+    }
+  };
+
+  // reduction, bounds and start blocks
+  for_members(G, b->threads, b->device, [&](int j) {
+    member_guard(j, [&] {
+      b->mem[j]->err.clear();
+      solve_begin(b->mem[j], mb[j]->s);
+    });
+  });
+
+  for (int it = 0;; it++) {
+    std::vector<int> act[2];
+    for (int j = 0; j < G; j++) {
+      mb[j]->active = !mb[j]->s.done;
+      if (!mb[j]->active) continue;
+      solve_filter_begin(mb[j]->s);
+      act[mb[j]->s.use32 ? 1 : 0].push_back(j);
+    }
+    if (act[0].empty() && act[1].empty()) break;
+    rep.outer_iterations++;
+
+    // members' blocks ready for the grouped steps
+    for (int p = 0; p < 2; p++)
+      for (int j : act[p]) {
+        chfsi_ctx c = b->mem[j];
+        SolveState& s = mb[j]->s;
+        const int64_t n = c->n, ka = s.k - s.cl;
+        CHFSI_HIP(hipEventRecord(s.ev[0], c->st));
+        if (p == 1) to_f32(c->Y.z() + s.cl * n, n, (cc*)c->Y32.p, n, n, ka, c->st);
+        CHFSI_HIP(hipEventRecord(b->ready[j], c->st));
+        CHFSI_HIP(hipStreamWaitEvent(b->gst, b->ready[j], 0));
+      }
+
+    double flops[2] = {0, 0};
+    int used_cfg[2] = {0, 0};
+    for (int p = 0; p < 2; p++) {
+      if (act[p].empty()) continue;
+      const int cf = b->config_for(p);
+      used_cfg[p] = cf;
+      int bm = 0, bn = 0;
+      zgemm_tile_shape(cf, &bm, &bn);
+      ZGemmParams* hp = b->hgp[p];
+      int64_t* ht = b->ht0[p];
+      std::vector<char> on(G, 0);
+      for (int j : act[p]) on[j] = 1;
+      ht[0] = 0;
+      for (int j = 0; j < G; j++) {
+        int64_t tiles = 0;
+        if (on[j]) {
+          chfsi_ctx c = b->mem[j];
+          const SolveState& s = mb[j]->s;
+          const int64_t n = c->n, ka = s.k - s.cl;
+          const int64_t tm = cdiv(n, (int64_t)bm), tn = cdiv(ka, (int64_t)bn);
+          tiles = tm * tn;
+          char* y0 = p ? (char*)c->Y32.p : (char*)(c->Y.z() + s.cl * n);
+          char* y1 = p ? (char*)c->Y32b.p : (char*)(c->Yb.z() + s.cl * n);
+          const std::vector<ChebStep> cs = cheb_schedule(m, s.a, s.b, s.a0);
+          void *cur = y0, *out = y1;
+          for (int i = 0; i < m; i++) {
+            ZGemmParams q{};
+            q.M = n; q.N = ka; q.K = n;
+            q.A = p ? c->A32.p : (const void*)c->A.z(); q.lda = n;
+            q.B = cur; q.ldb = n;
+            q.C = out; q.ldc = n;
+            q.X = cur; q.ldx = n;
+            q.Z = i ? out : nullptr; q.ldz = n;
+            q.alpha = cs[i].alpha; q.beta = cs[i].beta; q.gamma = cs[i].gamma;
+            q.flags = 0; q.splitk = 1; q.kchunk = n; q.P = nullptr;
+            q.tiles_m = (int)tm; q.tiles_n = (int)tn;
+            hp[(int64_t)i * G + j] = q;
+            std::swap(cur, out);
+          }
+          mb[j]->iter_flops = 8.0 * (double)n * (double)n * (double)ka * (double)m;
+          flops[p] += mb[j]->iter_flops;
+          c->filt_launches[p] += m;
+          c->filt_flops[p] += mb[j]->iter_flops;
+        } else {
+          for (int i = 0; i < m; i++) hp[(int64_t)i * G + j] = ZGemmParams{};
+        }
+        ht[j + 1] = ht[j] + tiles;
+      }
+      CHFSI_HIP(hipMemcpyAsync(b->gp[p].p, hp, (size_t)m * G * sizeof(ZGemmParams), hipMemcpyHostToDevice, b->gst));
+      CHFSI_HIP(hipMemcpyAsync(b->t0[p].p, ht, (size_t)(G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->gst));
+      CHFSI_HIP(hipEventRecord(b->gt[p][0], b->gst));
+      const bool graph = b->use_graph && b->cfg[p] != 0;
+      if (graph) {
+        if (!b->gexec[p] || b->gexec_cfg[p] != cf) b->capture(p, cf, m);
+        CHFSI_HIP(hipGraphLaunch(b->gexec[p], b->gst));
+        rep.graph = 1;
+      } else {
+        b->launch_steps(p, cf, m);
+      }
+      CHFSI_HIP(hipEventRecord(b->gt[p][1], b->gst));
+      rep.grouped_launches += m;
+    }
+    CHFSI_HIP(hipEventRecord(b->gdone, b->gst));
+
+    // results into F(:, cl:k), then each member's QR / Rayleigh-Ritz / locking
+    for (int p = 0; p < 2; p++)
+      for (int j : act[p]) {
+        chfsi_ctx c = b->mem[j];
+        SolveState& s = mb[j]->s;
+        const int64_t n = c->n, ka = s.k - s.cl;
+        CHFSI_HIP(hipStreamWaitEvent(c->st, b->gdone, 0));
+        zc* F = c->F.z() + s.cl * n;
+        if (p == 1) {
+          const cc* r = (const cc*)((m & 1) ? c->Y32b.p : c->Y32.p);
+          to_f64(r, n, F, n, n, ka, c->st);
+          s.inf.iterations_fp32++;
+        } else {
+          const zc* r = (m & 1) ? c->Yb.z() + s.cl * n : c->Y.z() + s.cl * n;
+          copy2d(r, n, F, n, n, ka, c->st);
+        }
+        CHFSI_HIP(hipEventRecord(s.ev[1], c->st));
+      }
+    std::vector<int> all(act[0]);
+    all.insert(all.end(), act[1].begin(), act[1].end());
+    for_members((int)all.size(), b->threads, b->device, [&](int q) {
+      const int j = all[q];
+      member_guard(j, [&] { solve_post(b->mem[j], mb[j]->s); });
+    });
+
+    // grouped step times (every member stream has passed gdone)
+    CHFSI_HIP(hipEventSynchronize(b->gdone));
+    for (int p = 0; p < 2; p++) {
+      if (act[p].empty()) continue;
+      float ms = 0.f;
+      CHFSI_HIP(hipEventElapsedTime(&ms, b->gt[p][0], b->gt[p][1]));
+      const double sec = ms * 1e-3;
+      rep.filter_seconds += sec;
+      rep.filter_flops += flops[p];
+      // members' share of the launch time, in proportion to their flops
+      for (int j : act[p])
+        if (flops[p] > 0) b->mem[j]->filt_kernel_s[p] += sec * mb[j]->iter_flops / flops[p];
+      if (!b->cfg[p]) {
+        const int cf = used_cfg[p];
+        if (sec > 0) b->rate[p][cf] = flops[p] / sec * 1e-12;
+        b->trial[p]++;
+        if (b->trial[p] >= BATCH_NCAND) {
+          int best = BATCH_CANDIDATES[0];
+          for (int q = 0; q < BATCH_NCAND; q++)
+            if (b->rate[p][BATCH_CANDIDATES[q]] > b->rate[p][best]) best = BATCH_CANDIDATES[q];
+          b->cfg[p] = best;
+        }
+      }
+    }
+  }
+
+  for_members(G, b->threads, b->device, [&](int j) {
+    if (mb[j]->status != CHFSI_OK) return;
+    member_guard(j, [&] { solve_finish(b->mem[j], mb[j]->s, &infos[j]); });
+  });
+  int first_bad = -1;
+  for (int j = 0; j < G; j++) {
+    statuses[j] = mb[j]->status;
+    if (mb[j]->status == CHFSI_OK) rep.converged_members++;
+    else if (first_bad < 0) first_bad = j;
+    if (mb[j]->status != CHFSI_OK && mb[j]->status != CHFSI_ENOCONV) {
+      infos[j] = mb[j]->s.inf;
+      b->mem[j]->warm_valid = false;
+    }
+  }
+  for (auto x : b->mst) CHFSI_HIP(hipStreamSynchronize(x));
+  CHFSI_HIP(hipStreamSynchronize(b->gst));
+  rep.tile_config = b->cfg[0] ? b->cfg[0] : 0;
+  rep.tile_config_fp32 = b->cfg[1] ? b->cfg[1] : 0;
+  for (int q = 0; q < 8; q++) rep.tile_rate[q] = b->rate[0][q];
+  rep.seconds = secs_since(t_start);
+  if (report) *report = rep;
+  if (first_bad >= 0)
+    throw Error(mb[first_bad]->status, "member " + std::to_string(first_bad) + ": " + mb[first_bad]->err);
 }
 
 }  // namespace
@@ -1080,6 +1840,248 @@ chfsi_status chfsi_zgemm(chfsi_ctx c, int32_t opA, int32_t opB, int64_t M, int64
             (const zc*)Z, ldz, structure, !(structure & GEMM_OUT_LOWER), false, cfg, nsplit);
     c->sync();
   });
+}
+
+chfsi_status chfsi_server_create(chfsi_server* out, const chfsi_server_config* cfg) {
+  if (!out || !cfg) return CHFSI_EINVAL;
+  *out = nullptr;
+  if (cfg->workers < 1 || cfg->workers > 64 || cfg->hbm_budget_bytes <= 0) return CHFSI_EINVAL;
+  chfsi_opts o = cfg->opts;
+  if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX ||
+      (o.precision != 0 && o.precision != 1) || (o.qr_mode != 0 && o.qr_mode != 1))
+    return CHFSI_EINVAL;
+  chfsi_server s = new (std::nothrow) chfsi_server_s();
+  if (!s) return CHFSI_ENOMEM;
+  s->cfg = *cfg;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return CHFSI_EHIP;
+  }
+  for (int i = 0; i < cfg->workers; i++) {
+    std::unique_ptr<Worker> w(new Worker());
+    if (hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking) != hipSuccess) {
+      chfsi_server_destroy(s);
+      return CHFSI_EHIP;
+    }
+    s->workers.push_back(std::move(w));
+  }
+  for (auto& w : s->workers) w->th = std::thread(server_worker, s, w.get());
+  *out = s;
+  return CHFSI_OK;
+}
+
+chfsi_status chfsi_server_submit(chfsi_server s, int64_t seq, int64_t n, const void* H, int64_t ldh, const void* S,
+                                 int64_t lds, int64_t nev, int64_t nex, double tol, double* evals, void* X, int64_t ldx,
+                                 int64_t* ticket) {
+  if (!s || !ticket) return CHFSI_EINVAL;
+  if (n < 1 || nev < 1 || nex < 0 || nev + nex > n || !(tol > 0.0) || !H || !S || !evals || ldh < n || lds < n ||
+      (X && ldx < n))
+    return CHFSI_EINVAL;
+  std::unique_ptr<Req> r(new Req());
+  r->seq = seq;
+  r->n = n;
+  r->nev = nev;
+  r->nex = nex;
+  r->H = (const zc*)H;
+  r->ldh = ldh;
+  r->S = (const zc*)S;
+  r->lds = lds;
+  r->tol = tol;
+  r->evals = evals;
+  r->X = (zc*)X;
+  r->ldx = ldx;
+  r->t_submit = std::chrono::steady_clock::now();
+  std::lock_guard<std::mutex> lk(s->m);
+  if (s->stop) return CHFSI_EINVAL;
+  r->ticket = s->next_ticket++;
+  *ticket = r->ticket;
+  if (!s->have_first) {
+    s->t_first = r->t_submit;
+    s->have_first = true;
+  }
+  s->submitted++;
+  s->queue.push_back(r.get());
+  s->reqs[r->ticket] = std::move(r);
+  s->cv_work.notify_all();
+  return CHFSI_OK;
+}
+
+chfsi_status chfsi_server_wait(chfsi_server s, int64_t ticket, chfsi_info* info, double* latency_seconds) {
+  if (!s) return CHFSI_EINVAL;
+  std::unique_lock<std::mutex> lk(s->m);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return CHFSI_EINVAL;
+  Req* r = it->second.get();
+  s->cv_done.wait(lk, [&] { return r->done; });
+  if (info) *info = r->info;
+  if (latency_seconds) *latency_seconds = std::chrono::duration<double>(r->t_end - r->t_submit).count();
+  const chfsi_status st = (chfsi_status)r->status;
+  if (st != CHFSI_OK) s->err = r->err;
+  s->reqs.erase(it);
+  return st;
+}
+
+chfsi_status chfsi_server_stats(chfsi_server s, chfsi_server_statistics* out) {
+  if (!s || !out) return CHFSI_EINVAL;
+  std::lock_guard<std::mutex> lk(s->m);
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->failed = s->failed;
+  out->queued = (int64_t)s->queue.size();
+  out->running = s->running;
+  out->bytes_in_use = (int64_t)s->used;
+  out->peak_bytes = (int64_t)s->peak;
+  out->budget_bytes = s->cfg.hbm_budget_bytes;
+  if (!s->lat.empty()) {
+    std::vector<double> v = s->lat;
+    std::sort(v.begin(), v.end());
+    auto q = [&](double f) {
+      const size_t i = (size_t)std::min<double>((double)v.size() - 1, std::ceil(f * v.size()) - 1);
+      return v[i];
+    };
+    out->p50_latency = q(0.50);
+    out->p99_latency = q(0.99);
+    double sum = 0;
+    for (double x : v) sum += x;
+    out->mean_latency = sum / v.size();
+    const double span = std::chrono::duration<double>(s->t_last - s->t_first).count();
+    out->solves_per_second = span > 0 ? s->completed / span : 0.0;
+  }
+  return CHFSI_OK;
+}
+
+chfsi_status chfsi_server_release_sequence(chfsi_server s, int64_t seq) {
+  if (!s) return CHFSI_EINVAL;
+  std::lock_guard<std::mutex> lk(s->m);
+  auto it = s->seqs.find(seq);
+  if (it == s->seqs.end()) return CHFSI_OK;
+  if (it->second->busy) return CHFSI_EINVAL;
+  for (Req* r : s->queue)
+    if (r->seq == seq) return CHFSI_EINVAL;
+  s->used -= it->second->X.bytes;
+  it->second->X.release();
+  s->seqs.erase(it);
+  s->cv_work.notify_all();
+  return CHFSI_OK;
+}
+
+const char* chfsi_server_last_error(chfsi_server s) { return s ? s->err.c_str() : "null server"; }
+
+void chfsi_server_destroy(chfsi_server s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->m);
+    s->stop = true;
+    for (Req* r : s->queue) {
+      r->status = CHFSI_EINVAL;
+      r->err = "server destroyed before the request ran";
+      r->done = true;
+    }
+    s->queue.clear();
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+  }
+  for (auto& w : s->workers)
+    if (w->th.joinable()) w->th.join();
+  for (auto& w : s->workers) {
+    if (w->ctx) chfsi_release(w->ctx);
+    if (w->st) (void)hipStreamDestroy(w->st);
+  }
+  for (auto& kv : s->seqs) kv.second->X.release();
+  delete s;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batching
+// ---------------------------------------------------------------------------
+chfsi_status chfsi_batch_create(chfsi_batch* out, int32_t count, const int64_t* n, const chfsi_opts* opts,
+                                int32_t use_graph) {
+  if (!out) return CHFSI_EINVAL;
+  *out = nullptr;
+  if (count < 1 || count > 1024 || !n || (use_graph != 0 && use_graph != 1)) return CHFSI_EINVAL;
+  for (int j = 0; j < count; j++)
+    if (n[j] < 1) return CHFSI_EINVAL;
+  chfsi_opts o;
+  chfsi_default_opts(&o);
+  if (opts) o = *opts;
+  o.profile = 0;
+  if (o.filter_tile != 0 && !zgemm_grouped_config_ok(o.filter_tile)) return CHFSI_EINVAL;
+  chfsi_batch b = new (std::nothrow) chfsi_batch_s();
+  if (!b) return CHFSI_ENOMEM;
+  try {
+    CHFSI_HIP(hipGetDevice(&b->device));
+    b->count = count;
+    b->use_graph = use_graph != 0;
+    b->opts = o;
+    b->threads = std::min(count, 8);
+    CHFSI_HIP(hipStreamCreateWithFlags(&b->gst, hipStreamNonBlocking));
+    CHFSI_HIP(hipEventCreateWithFlags(&b->gdone, hipEventDisableTiming));
+    for (int p = 0; p < 2; p++)
+      for (int q = 0; q < 2; q++) CHFSI_HIP(hipEventCreate(&b->gt[p][q]));
+    for (int j = 0; j < count; j++) {
+      hipStream_t x = nullptr;
+      CHFSI_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+      b->mst.push_back(x);
+      hipEvent_t e = nullptr;
+      CHFSI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->ready.push_back(e);
+      chfsi_ctx c = nullptr;
+      const chfsi_status st = chfsi_create(&c, n[j], &o, x);
+      if (st != CHFSI_OK) throw Error(st, "member context creation failed");
+      b->mem.push_back(c);
+    }
+    const size_t m = (size_t)o.degree;
+    for (int p = 0; p < 2; p++) {
+      b->gp[p].ensure(m * count * sizeof(ZGemmParams));
+      b->t0[p].ensure((size_t)(count + 1) * sizeof(int64_t));
+      CHFSI_HIP(hipHostMalloc((void**)&b->hgp[p], m * count * sizeof(ZGemmParams), hipHostMallocDefault));
+      CHFSI_HIP(hipHostMalloc((void**)&b->ht0[p], (size_t)(count + 1) * sizeof(int64_t), hipHostMallocDefault));
+    }
+    if (o.filter_tile) b->cfg[0] = b->cfg[1] = o.filter_tile;
+  } catch (const Error& e) {
+    b->destroy();
+    delete b;
+    (void)hipGetLastError();
+    return (chfsi_status)e.code;
+  }
+  *out = b;
+  return CHFSI_OK;
+}
+
+chfsi_status chfsi_batch_solve(chfsi_batch b, const void* const* H, const int64_t* ldh, const void* const* S,
+                               const int64_t* lds, const int64_t* nev, const int64_t* nex, double tol,
+                               double* const* evals, void* const* X, const int64_t* ldx, chfsi_info* infos,
+                               int32_t* statuses, chfsi_batch_report* report) {
+  if (!b) return CHFSI_EINVAL;
+  try {
+    b->err.clear();
+    batch_solve_impl(b, H, ldh, S, lds, nev, nex, tol, evals, X, ldx, infos, statuses, report);
+    return CHFSI_OK;
+  } catch (const Error& e) {
+    b->err = e.what();
+    (void)hipGetLastError();
+    return (chfsi_status)e.code;
+  } catch (const std::exception& e) {
+    b->err = e.what();
+    return CHFSI_EHIP;
+  }
+}
+
+chfsi_status chfsi_batch_reset(chfsi_batch b) {
+  if (!b) return CHFSI_EINVAL;
+  for (auto c : b->mem) c->warm_valid = false;
+  return CHFSI_OK;
+}
+
+const char* chfsi_batch_last_error(chfsi_batch b) { return b ? b->err.c_str() : "null batch"; }
+
+void chfsi_batch_release(chfsi_batch b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  b->destroy();
+  delete b;
 }
 
 }  // extern "C"

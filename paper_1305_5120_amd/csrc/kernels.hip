@@ -4,6 +4,8 @@
 // latency- or bandwidth-bound; the dense products live in zgemm.hip.
 #include "kernels.hpp"
 
+#include <mutex>
+
 namespace chfsi {
 
 namespace {
@@ -136,74 +138,86 @@ __global__ void k_nonfinite(const zc* A, int64_t lda, int64_t n, int64_t k, int*
 }
 
 // --------------------------------------------------------------------------
-// Cholesky diagonal block: unblocked right-looking factorization in LDS and
-// the inverse of the factor (forward substitution, one column per thread).
+// Cholesky diagonal block (nb <= 64): right-looking factorization and the
+// inverse of the factor in one sweep over the columns, with the block held in
+// registers.  Thread (r, q) = (tid % 64, tid / 64) owns row r of columns
+// c = q + 4t (t < 16) of both the matrix being factored and of X = L^{-1}, so
+// wave q holds whole columns.  Step j: the wave owning column j takes the
+// pivot from lane j, scales the column and publishes it in LDS; after one
+// barrier every thread
+//   * updates its trailing entries  A(r, c) -= l(r, j) conj(l(c, j)),  c > j,
+//   * applies step j of the column-oriented forward substitution for L X = I:
+//     row j of X is divided by l(j, j) and l(r, j) times it is subtracted from
+//     rows r > j.  Row j of X sits in lane j of the same wave, so it is taken
+//     with a cross-lane read, not through LDS.
+// X(r, c) is zero for c > j until step c, and the trailing update only touches
+// c > j, so each thread has about 16 complex updates per step.
 // --------------------------------------------------------------------------
 constexpr int CNB = CHOL_NB;
-constexpr int CLD = CNB + 1;
 
 __global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi,
                                                     int64_t j0, int nb, int* info) {
-  extern __shared__ zc smem[];
-  zc* Ls = smem;              // [CNB][CLD] row-major: Ls[i * CLD + c]
-  zc* Xs = smem + CNB * CLD;  // inverse
+  static_assert(CNB == 64, "one row per lane, four waves of columns");
+  __shared__ zc col[2][CNB];
   __shared__ int failed;
-  const int tid = threadIdx.x;
-  if (tid == 0) failed = -1;
-  for (int e = tid; e < nb * nb; e += blockDim.x) {
-    const int i = e % nb, c = e / nb;
-    Ls[i * CLD + c] = (i >= c) ? W[(j0 + i) + (j0 + c) * ldw] : zmk(0.0, 0.0);
+  const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
+  zc a[16], x[16];
+#pragma unroll
+  for (int t = 0; t < 16; t++) {
+    const int c = q + 4 * t;
+    a[t] = (r < nb && c < nb && r >= c) ? W[(j0 + r) + (j0 + c) * ldw] : zmk(0.0, 0.0);
+    x[t] = zmk(r == c ? 1.0 : 0.0, 0.0);
   }
+  if (tid == 0) failed = -1;
   __syncthreads();
-  // right-looking factorization: per column, scale (every thread reads the
-  // pivot itself), barrier, rank-1 update of the trailing lower triangle
   for (int j = 0; j < nb; j++) {
-    const double d = Ls[j * CLD + j].x;
-    if (!(d > 0.0)) {
-      if (tid == 0) failed = j;
-      break;  // uniform: every thread read the same pivot
+    const int buf = j & 1, tj = j >> 2;
+    if (q == (j & 3)) {
+      zc v = zmk(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < 16; t++)
+        if (t == tj) v = a[t];
+      const double d = __shfl(v.x, j, 64);
+      if (!(d > 0.0)) {
+        if (r == 0) failed = j;
+      } else {
+        const double ljj = sqrt(d), inv = 1.0 / ljj;
+        const zc l = r > j ? zscale(inv, v) : (r == j ? zmk(ljj, 0.0) : zmk(0.0, 0.0));
+#pragma unroll
+        for (int t = 0; t < 16; t++)
+          if (t == tj) a[t] = l;
+        col[buf][r] = l;
+      }
     }
-    const double ljj = sqrt(d), inv = 1.0 / ljj;
-    for (int i = j + 1 + tid; i < nb; i += blockDim.x) Ls[i * CLD + j] = zscale(inv, Ls[i * CLD + j]);
     __syncthreads();
-    if (tid == 0) Ls[j * CLD + j] = zmk(ljj, 0.0);
-    const int m = nb - j - 1;  // trailing size
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      const int i = j + 1 + e % m, c = j + 1 + e / m;
-      if (c <= i) Ls[i * CLD + c] = zsub(Ls[i * CLD + c], zmul(Ls[i * CLD + j], zconj(Ls[c * CLD + j])));
+    if (failed >= 0) break;  // uniform: read after the barrier
+    const zc lr = col[buf][r];
+    const double dinv = 1.0 / col[buf][j].x;
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+      const int c = q + 4 * t;  // uniform over the wave
+      if (c > j) {
+        const zc lc = col[buf][c];
+        if (r >= c) a[t] = zsub(a[t], zmul(lr, zconj(lc)));
+      } else {
+        const zc xj = zmk(__shfl(x[t].x, j, 64) * dinv, __shfl(x[t].y, j, 64) * dinv);
+        if (r == j) x[t] = xj;
+        else if (r > j) x[t] = zsub(x[t], zmul(lr, xj));
+      }
     }
-    __syncthreads();
   }
   __syncthreads();
   if (failed >= 0) {
     if (tid == 0) atomicMin(info, (int)(j0 + failed + 1));
     return;
   }
-  // inverse X = L^{-1} by forward substitution, one row at a time; row i of
-  // every column c <= i at once, each dot product split over 4 lanes
-  for (int e = tid; e < nb * nb; e += blockDim.x) {
-    const int i = e % nb, c = e / nb;
-    Xs[i * CLD + c] = zmk(0.0, 0.0);
-  }
-  __syncthreads();
-  const int c = tid >> 2, part = tid & 3;
-  for (int i = 0; i < nb; i++) {
-    const double dinv = 1.0 / Ls[i * CLD + i].x;
-    if (c < nb && c <= i) {
-      zc s = zmk(0.0, 0.0);
-      for (int q = c + part; q < i; q += 4) s = zadd(s, zmul(Ls[i * CLD + q], Xs[q * CLD + c]));
-      s.x += __shfl_xor(s.x, 1, 64);
-      s.y += __shfl_xor(s.y, 1, 64);
-      s.x += __shfl_xor(s.x, 2, 64);
-      s.y += __shfl_xor(s.y, 2, 64);
-      if (part == 0) Xs[i * CLD + c] = (i == c) ? zmk(dinv, 0.0) : zscale(-dinv, s);
+#pragma unroll
+  for (int t = 0; t < 16; t++) {
+    const int c = q + 4 * t;
+    if (r < nb && c < nb) {
+      L[(j0 + r) + (j0 + c) * ldl] = r >= c ? a[t] : zmk(0.0, 0.0);
+      Linv[(j0 + r) + (j0 + c) * ldi] = r >= c ? x[t] : zmk(0.0, 0.0);
     }
-    __syncthreads();
-  }
-  for (int e = tid; e < nb * nb; e += blockDim.x) {
-    const int i = e % nb, cc_ = e / nb;
-    L[(j0 + i) + (j0 + cc_) * ldl] = (i >= cc_) ? Ls[i * CLD + cc_] : zmk(0.0, 0.0);
-    Linv[(j0 + i) + (j0 + cc_) * ldi] = (i >= cc_) ? Xs[i * CLD + cc_] : zmk(0.0, 0.0);
   }
 }
 
@@ -470,7 +484,7 @@ __device__ inline void rot_cols(const Rot& s, zc& zp, zc& zq) {
 constexpr int JACOBI_ZLDS_MAX = 64;  // G and Z both in LDS up to this size
 
 __global__ void __launch_bounds__(1024) k_jacobi_small(const zc* G, int64_t ldg, int k, double* w, zc* Zout, int64_t ldz,
-                                                      zc* Zg, int* sweeps_out) {
+                                                      zc* Zg, double tau2, int* sweeps_out) {
   extern __shared__ zc Gs[];  // k x k, column-major ld k; then Z when k <= JACOBI_ZLDS_MAX
   __shared__ double red[16];
   __shared__ Rot prm[JACOBI_LDS_MAX / 2 + 1];
@@ -490,7 +504,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_small(const zc* G, int64_t ldg,
     f += zabs2(v);
   }
   const double fro2 = block_sum(f, red);
-  const double skip2 = 1e-36 * fro2;
+  const double skip2 = fmax(1e-36 * fro2, tau2);
   int sweep = 0;
   for (; sweep < 100; sweep++) {
     double o = 0.0;
@@ -590,14 +604,10 @@ __global__ void k_jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z
 }
 
 __global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
-                               int* rotated) {
-  // G is Hermitian: thread e < half (half + 1)/2 owns the 2x2 block of pair
-  // rows rt >= pair columns st and writes it and its mirror; the remaining
-  // threads update Z's columns.
+                               double tau2, int* rotated) {
   const int64_t K2 = k + (k & 1), half = K2 / 2;
-  const int64_t nblk = half * (half + 1) / 2;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double skip2 = 1e-36 * fro2[0];
+  const double skip2 = fmax(1e-36 * fro2[0], tau2);
   auto rot_of = [&](int64_t t, int64_t& p, int64_t& q) -> Rot {
     round_pair(K2, round, t, p, q);
     if (q >= k) {
@@ -607,12 +617,8 @@ __global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout,
     }
     return make_rot(Gin[p + p * k], Gin[q + q * k], Gin[p + q * k], skip2);
   };
-  if (e < nblk) {
-    // e -> (rt, st), rt >= st, e = rt (rt + 1)/2 + st
-    int64_t rt = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-    while (rt * (rt + 1) / 2 > e) rt--;
-    while ((rt + 1) * (rt + 2) / 2 <= e) rt++;
-    const int64_t st = e - rt * (rt + 1) / 2;
+  if (e < half * half) {
+    const int64_t rt = e % half, st = e / half;
     int64_t pr, qr, ps, qs;
     const Rot Rr = rot_of(rt, pr, qr);
     const Rot Rs = rot_of(st, ps, qs);
@@ -637,15 +643,9 @@ __global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout,
     if (qsv) Gout[pr + qs * k] = b01;
     if (qrv) Gout[qr + ps * k] = b10;
     if (qrv && qsv) Gout[qr + qs * k] = b11;
-    if (rt != st) {
-      Gout[ps + pr * k] = zconj(b00);
-      if (qsv) Gout[qs + pr * k] = zconj(b01);
-      if (qrv) Gout[ps + qr * k] = zconj(b10);
-      if (qrv && qsv) Gout[qs + qr * k] = zconj(b11);
-    }
     return;
   }
-  const int64_t e2 = e - nblk;
+  const int64_t e2 = e - half * half;
   if (e2 >= k * half) return;
   const int64_t i = e2 % k, st = e2 / k;
   int64_t ps, qs;
@@ -655,6 +655,106 @@ __global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout,
   if (Rs.active) rot_cols(Rs, zp, zq);
   Zout[i + ps * k] = zp;
   if (qs < k) Zout[i + qs * k] = zq;
+}
+
+// ---- sparse sweeps: only the pairs whose coupling is significant ----------
+// counts[j] = #{ i > j : |G(i, j)|^2 > thr_factor * fro2 }
+__global__ void k_jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau2, int* counts) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  const double thr = fmax(thr_factor * fro2[0], tau2);
+  int c = 0;
+  for (int64_t i = j + 1; i < k; i++)
+    if (zabs2(G[i + j * k]) > thr) c++;
+  counts[j] = c;
+}
+
+// pairs (j, i), i > j, of column j at offsets[j] (deterministic order)
+__global__ void k_jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau2,
+                              const int* offsets, int* pairs) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  const double thr = fmax(thr_factor * fro2[0], tau2);
+  int o = offsets[j];
+  for (int64_t i = j + 1; i < k; i++)
+    if (zabs2(G[i + j * k]) > thr) {
+      pairs[2 * o] = (int)j;
+      pairs[2 * o + 1] = (int)i;
+      o++;
+    }
+}
+
+// rotation parameters of one round's disjoint pairs (read before any update)
+__global__ void k_jacobi_params(const zc* G, int64_t k, const int* pairs, int np, const double* fro2, double tau2, Rot* prm,
+                                int* rotated) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= np) return;
+  const int64_t p = pairs[2 * a], q = pairs[2 * a + 1];
+  const Rot R = make_rot(G[p + p * k], G[q + q * k], G[p + q * k], fmax(1e-36 * fro2[0], tau2));
+  if (R.active) *rotated = 1;
+  prm[a] = R;
+}
+
+// In-place application of one round: work item (a, j) updates the block of
+// pair a's rows with index j's group (j's pair when j is its first member
+// and that pair is not after a; j alone when unpaired) and its mirror; the
+// second half of the items rotates Z's columns.
+__global__ void k_jacobi_apply(zc* G, zc* Z, int64_t k, const int* pairs, int np, const int* pairof, const Rot* prm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (int64_t)np * k) {
+    const int a = (int)(e / k);
+    const int64_t j = e % k;
+    const Rot Ra = prm[a];
+    const int64_t pa = pairs[2 * a], qa = pairs[2 * a + 1];
+    const int b = pairof[j];
+    if (b < 0) {
+      // unpaired column j: rows (pa, qa) rotate, column j does not
+      if (!Ra.active) return;
+      Rot I;
+      I.c = 1.0; I.s = 0.0; I.ur = 1.0; I.ui = 0.0; I.tg = 0.0; I.active = 0;
+      zc b00 = G[pa + j * k], b01 = zmk(0.0, 0.0), b10 = G[qa + j * k], b11 = zmk(0.0, 0.0);
+      rot_block(Ra, I, b00, b01, b10, b11);
+      G[pa + j * k] = b00;
+      G[qa + j * k] = b10;
+      G[j + pa * k] = zconj(b00);
+      G[j + qa * k] = zconj(b10);
+      return;
+    }
+    const int64_t pb = pairs[2 * b], qb = pairs[2 * b + 1];
+    if (j != pb || b > a) return;
+    const Rot Rb = prm[b];
+    if (!Ra.active && !Rb.active) return;
+    zc b00 = G[pa + pb * k], b01 = G[pa + qb * k], b10 = G[qa + pb * k], b11 = G[qa + qb * k];
+    if (a == b) {
+      const double app = b00.x, aqq = b11.x;
+      G[pa + pa * k] = zmk(app - Ra.tg, 0.0);
+      G[qa + qa * k] = zmk(aqq + Ra.tg, 0.0);
+      G[pa + qa * k] = zmk(0.0, 0.0);
+      G[qa + pa * k] = zmk(0.0, 0.0);
+      return;
+    }
+    rot_block(Ra, Rb, b00, b01, b10, b11);
+    G[pa + pb * k] = b00;
+    G[pa + qb * k] = b01;
+    G[qa + pb * k] = b10;
+    G[qa + qb * k] = b11;
+    G[pb + pa * k] = zconj(b00);
+    G[qb + pa * k] = zconj(b01);
+    G[pb + qa * k] = zconj(b10);
+    G[qb + qa * k] = zconj(b11);
+    return;
+  }
+  const int64_t e2 = e - (int64_t)np * k;
+  if (e2 >= (int64_t)np * k) return;
+  const int a = (int)(e2 / k);
+  const int64_t i = e2 % k;
+  const Rot Ra = prm[a];
+  if (!Ra.active) return;
+  const int64_t pa = pairs[2 * a], qa = pairs[2 * a + 1];
+  zc zp = Z[i + pa * k], zq = Z[i + qa * k];
+  rot_cols(Ra, zp, zq);
+  Z[i + pa * k] = zp;
+  Z[i + qa * k] = zq;
 }
 
 __global__ void k_jacobi_norms_part(const zc* G, int64_t k, double* part) {
@@ -849,14 +949,8 @@ void nonfinite_check(const zc* A, int64_t lda, int64_t n, int64_t k, int* flag, 
 
 void chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi, int64_t j0, int64_t nb, int* info,
                hipStream_t st) {
-  static bool attr = false;
-  const size_t shm = 2 * (size_t)CNB * CLD * sizeof(zc);
-  if (!attr) {
-    CHFSI_HIP(hipFuncSetAttribute((const void*)k_chol_diag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    attr = true;
-  }
   if (nb < 1 || nb > CNB) throw Error(ST_EINVAL, "chol_diag: block size out of range");
-  LAUNCH(k_chol_diag, dim3(1), dim3(256), shm, st, W, ldw, L, ldl, Linv, ldi, j0, (int)nb, info);
+  LAUNCH(k_chol_diag, dim3(1), dim3(256), 0, st, W, ldw, L, ldl, Linv, ldi, j0, (int)nb, info);
 }
 
 void hh_panel_setup(HHPanel& p) {
@@ -887,16 +981,15 @@ void hh_build_t(const zc* gram, const zc* tau, int64_t cnt, zc* T, hipStream_t s
 }
 
 void jacobi_small(const zc* G, int64_t ldg, int64_t k, double* w, zc* Z, int64_t ldz, zc* Ztmp, int* sweeps_out,
-                  hipStream_t st) {
+                  hipStream_t st, double tau) {
   if (k < 1 || k > JACOBI_LDS_MAX) throw Error(ST_EINVAL, "jacobi_small: size out of range");
-  static bool attr = false;
+  static std::once_flag attr;
   const size_t shm = (size_t)JACOBI_LDS_MAX * JACOBI_LDS_MAX * sizeof(zc);
-  if (!attr) {
+  std::call_once(attr, [&] {
     CHFSI_HIP(hipFuncSetAttribute((const void*)k_jacobi_small, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    attr = true;
-  }
+  });
   const size_t dyn = (size_t)k * k * sizeof(zc) * (k <= JACOBI_ZLDS_MAX ? 2 : 1);
-  LAUNCH(k_jacobi_small, dim3(1), dim3(1024), dyn, st, G, ldg, (int)k, w, Z, ldz, Ztmp, sweeps_out);
+  LAUNCH(k_jacobi_small, dim3(1), dim3(1024), dyn, st, G, ldg, (int)k, w, Z, ldz, Ztmp, tau * tau, sweeps_out);
 }
 
 void jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0, hipStream_t st) {
@@ -904,11 +997,30 @@ void jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0, hipStream_
 }
 
 void jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
-                  int* rotated, hipStream_t st) {
+                  int* rotated, hipStream_t st, double tau) {
   const int64_t half = (k + (k & 1)) / 2;
-  LAUNCH(k_jacobi_round, grid1(half * (half + 1) / 2 + k * half), dim3(NT), 0, st, Gin, Gout, Zin, Zout, k, round, fro2,
+  LAUNCH(k_jacobi_round, grid1(half * half + k * half), dim3(NT), 0, st, Gin, Gout, Zin, Zout, k, round, fro2, tau * tau,
          rotated);
 }
+
+void jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, int* counts, hipStream_t st) {
+  LAUNCH(k_jacobi_count, grid1(k, 64), dim3(64), 0, st, G, k, fro2, thr_factor, tau * tau, counts);
+}
+
+void jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, const int* offsets,
+                 int* pairs, hipStream_t st) {
+  LAUNCH(k_jacobi_list, grid1(k, 64), dim3(64), 0, st, G, k, fro2, thr_factor, tau * tau, offsets, pairs);
+}
+
+void jacobi_sparse_round(zc* G, zc* Z, int64_t k, const int* pairs, int np, const int* pairof, void* prm_scratch,
+                         const double* fro2, double tau, int* rotated, hipStream_t st) {
+  if (np == 0) return;
+  Rot* prm = static_cast<Rot*>(prm_scratch);
+  LAUNCH(k_jacobi_params, grid1(np), dim3(NT), 0, st, G, k, pairs, np, fro2, tau * tau, prm, rotated);
+  LAUNCH(k_jacobi_apply, grid1(2 * (int64_t)np * k), dim3(NT), 0, st, G, Z, k, pairs, np, pairof, prm);
+}
+
+size_t jacobi_rot_bytes() { return sizeof(Rot); }
 
 void jacobi_norms(const zc* G, int64_t k, double* part, double* out, hipStream_t st) {
   const int nb = (int)std::min<int64_t>(256, std::max<int64_t>(1, cdiv(k * k, 1024)));

@@ -60,15 +60,25 @@ void hh_build_t(const zc* gram, const zc* tau, int64_t cnt, zc* T, hipStream_t s
 // ---- Jacobi eigensolver for Hermitian k x k --------------------------------
 constexpr int JACOBI_LDS_MAX = 96;
 // Single-workgroup solver (k <= JACOBI_LDS_MAX): w ascending, Z (ld ldz).
+// tau: couplings |G(p,q)| <= tau count as converged (0: working accuracy)
 void jacobi_small(const zc* G, int64_t ldg, int64_t k, double* w, zc* Z, int64_t ldz, zc* Ztmp, int* sweeps_out,
-                  hipStream_t st);
+                  hipStream_t st, double tau = 0.0);
 // Multi-launch pieces for larger k.
 void jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0, hipStream_t st);
 void jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
-                  int* rotated, hipStream_t st);
+                  int* rotated, hipStream_t st, double tau = 0.0);
 // out[0] = sum |G_ij|^2 off the diagonal, out[1] = sum over all (two-stage)
 void jacobi_norms(const zc* G, int64_t k, double* part, double* out, hipStream_t st);
 void jacobi_sort(const zc* G, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz, hipStream_t st);
+// Sparse sweeps: count / list the pairs with |G(i,j)|^2 > thr_factor * fro2
+// (i > j, per column j), then apply one round of disjoint pairs in place.
+void jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, int* counts, hipStream_t st);
+void jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, const int* offsets,
+                 int* pairs, hipStream_t st);
+// pairs: 2 np ints (p < q); pairof: k ints, the pair index of each row or -1
+void jacobi_sparse_round(zc* G, zc* Z, int64_t k, const int* pairs, int np, const int* pairof, void* prm_scratch,
+                         const double* fro2, double tau, int* rotated, hipStream_t st);
+size_t jacobi_rot_bytes();
 
 // ---- Lanczos pieces ---------------------------------------------------------
 // y = A x (A n x n, lda); part: work of JMV_SPLITS * n

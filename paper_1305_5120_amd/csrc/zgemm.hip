@@ -72,8 +72,16 @@ struct ZTile {
   static_assert(BK % 4 == 0, "BK multiple of the MFMA depth");
 };
 
+// Workgroup -> tile order with the XCD-aware remap (workgroup i runs on XCD
+// i % 8): each XCD works through a contiguous range of tiles, so tiles that
+// share a row panel of op(A) meet in the same L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles) {
+  const int64_t full = (ntiles / 8) * 8;
+  return bid < full ? (bid % 8) * (ntiles / 8) + bid / 8 : bid;
+}
+
 template <class PT, int OPA, int OPB, int BM, int BN, int BK>
-__device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
+__device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int batch, int split) {
   using T = ZTile<BM, BN, BK>;
   using E = typename PT::E;
   using R = typename PT::R;
@@ -87,18 +95,10 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
   const int wm0 = (wave & 1) * (BM / 2);
   const int wn0 = (wave >> 1) * (BN / 2);
 
-  // tile index with XCD-aware remap (workgroup i runs on XCD i % 8)
-  const int64_t T_ = (int64_t)p.tiles_m * p.tiles_n;
-  int64_t bid = blockIdx.x, t;
-  const int64_t full = (T_ / 8) * 8;
-  if (bid < full) t = (bid % 8) * (T_ / 8) + bid / 8;
-  else t = bid;
   const int64_t mt = t / p.tiles_n, nt = t % p.tiles_n;
   const int64_t m0 = mt * BM, n0 = nt * BN;
   if ((p.flags & GEMM_OUT_LOWER) && n0 > m0 + BM - 1) return;  // tile entirely above the diagonal
 
-  const int bz = blockIdx.y;
-  const int batch = bz / p.splitk, split = bz % p.splitk;
   const E* __restrict__ A = static_cast<const E*>(p.A) + (int64_t)batch * p.sA;
   const E* __restrict__ B = static_cast<const E*>(p.B) + (int64_t)batch * p.sB;
 
@@ -275,23 +275,67 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p) {
       }
 }
 
+#define ZGEMM_TILE_ARGS(p) xcd_tile(blockIdx.x, (int64_t)(p).tiles_m * (p).tiles_n), \
+                                 (int)(blockIdx.y / (p).splitk), (int)(blockIdx.y % (p).splitk)
+
 template <int OPA, int OPB, int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) zgemm_kernel(ZGemmParams p) {
-  zgemm_body<PF64, OPA, OPB, BM, BN, BK>(p);
+  zgemm_body<PF64, OPA, OPB, BM, BN, BK>(p, ZGEMM_TILE_ARGS(p));
 }
 
 // One degree step of the Chebyshev filter: the same body, launched under its
 // own symbol so that profiles separate the filter from the other products.
 template <int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) chebyshev_step_f64(ZGemmParams p) {
-  zgemm_body<PF64, OP_N, OP_N, BM, BN, BK>(p);
+  zgemm_body<PF64, OP_N, OP_N, BM, BN, BK>(p, ZGEMM_TILE_ARGS(p));
 }
 
 // The mixed-precision filter step: complex FP32 operands on the FP32 matrix
 // cores with FP32 accumulation.
 template <int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) chebyshev_step_f32(ZGemmParams p) {
-  zgemm_body<PF32, OP_N, OP_N, BM, BN, BK>(p);
+  zgemm_body<PF32, OP_N, OP_N, BM, BN, BK>(p, ZGEMM_TILE_ARGS(p));
+}
+
+// One degree step for a batch of problems of different sizes in one
+// persistent launch: gp[g] describes problem g's step (no split), tile0[g]
+// its first tile in the batch-wide tile range (tile0[G] = total; a problem
+// with no work this step has tile0[g] == tile0[g + 1]).  The grid is a fixed
+// multiple of 8 workgroups; workgroup i walks the tiles of XCD i % 8's
+// contiguous share, so the launch does not depend on the problems' sizes and
+// a captured graph of these launches stays valid while the active widths
+// shrink.
+template <class PT, int BM, int BN, int BK>
+__device__ __forceinline__ void grouped_body(const ZGemmParams* __restrict__ gp, const int64_t* __restrict__ tile0,
+                                             int G) {
+  const int64_t total = tile0[G];
+  const int64_t xcd = blockIdx.x % 8, slot = blockIdx.x / 8, nslot = gridDim.x / 8;
+  const int64_t chunk = (total + 7) / 8;
+  for (int64_t i = slot; i < chunk; i += nslot) {
+    const int64_t t = xcd * chunk + i;
+    if (t >= total) break;
+    // last g with tile0[g] <= t (that problem has at least one tile)
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile0[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    zgemm_body<PT, OP_N, OP_N, BM, BN, BK>(gp[lo], t - tile0[lo], 0, 0);
+    __syncthreads();  // LDS of this tile fully consumed before the next one
+  }
+}
+
+template <int BM, int BN, int BK, int MINB>
+__global__ void __launch_bounds__(256, MINB) chebyshev_step_grouped_f64(const ZGemmParams* __restrict__ gp,
+                                                                       const int64_t* __restrict__ tile0, int G) {
+  grouped_body<PF64, BM, BN, BK>(gp, tile0, G);
+}
+
+template <int BM, int BN, int BK, int MINB>
+__global__ void __launch_bounds__(256, MINB) chebyshev_step_grouped_f32(const ZGemmParams* __restrict__ gp,
+                                                                       const int64_t* __restrict__ tile0, int G) {
+  grouped_body<PF32, BM, BN, BK>(gp, tile0, G);
 }
 
 // Combine split-K partial tiles and apply the epilogue.
@@ -408,9 +452,71 @@ void launch_ops(int cfg, int opA, int opB, ZGemmParams& p, int batch, bool filte
   else launch_cfg<OP_C, OP_C>(cfg, p, batch, filter_step, st);
 }
 
+template <int BM, int BN, int BK, int MINB>
+void launch_grouped(int prec, const ZGemmParams* gp, const int64_t* tile0, int G, int grid, hipStream_t st) {
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL((chebyshev_step_grouped_f32<BM, BN, BK, MINB>), dim3(grid), dim3(256), 0, st, gp, tile0, G);
+  else
+    hipLaunchKernelGGL((chebyshev_step_grouped_f64<BM, BN, BK, MINB>), dim3(grid), dim3(256), 0, st, gp, tile0, G);
+  CHFSI_CHECK_LAUNCH();
+}
+
+// Resident workgroups per CU of the grouped kernel.
+template <int BM, int BN, int BK, int MINB>
+int grouped_occupancy(int prec) {
+  int nb = 0;
+  if (prec == PREC_F32)
+    CHFSI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, chebyshev_step_grouped_f32<BM, BN, BK, MINB>, 256, 0));
+  else
+    CHFSI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, chebyshev_step_grouped_f64<BM, BN, BK, MINB>, 256, 0));
+  return nb;
+}
+
 }  // namespace
 
 int zgemm_num_configs() { return NCFG; }
+
+int zgemm_tile_shape(int cfg, int* bm, int* bn) {
+  if (cfg < 1 || cfg >= NCFG) return -1;
+  *bm = CFGS[cfg].bm;
+  *bn = CFGS[cfg].bn;
+  return 0;
+}
+
+bool zgemm_grouped_config_ok(int cfg) { return cfg == 1 || cfg == 2 || cfg == 3 || cfg == 4 || cfg == 5 || cfg == 7; }
+
+int zgemm_grouped_grid(int prec, int cfg) {
+  int nb = 0;
+  switch (cfg) {
+    case 1: nb = grouped_occupancy<64, 64, 16, 2>(prec); break;
+    case 2: nb = grouped_occupancy<32, 32, 16, 2>(prec); break;
+    case 3: nb = grouped_occupancy<64, 64, 8, 2>(prec); break;
+    case 4: nb = grouped_occupancy<128, 64, 8, 2>(prec); break;
+    case 5: nb = grouped_occupancy<64, 128, 8, 2>(prec); break;
+    case 7: nb = grouped_occupancy<64, 32, 16, 2>(prec); break;
+    default: throw Error(ST_EINVAL, "grouped filter: bad tile configuration");
+  }
+  int dev = 0, cus = 0;
+  CHFSI_HIP(hipGetDevice(&dev));
+  CHFSI_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int grid = std::max(1, nb) * std::max(1, cus);
+  return std::max(8, grid / 8 * 8);
+}
+
+void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const int64_t* tile0, int G, int grid,
+                               hipStream_t st) {
+  if (grid < 8 || grid % 8) throw Error(ST_EINVAL, "grouped filter: grid must be a positive multiple of 8");
+  if (G < 1) throw Error(ST_EINVAL, "grouped filter: no problems");
+  switch (cfg) {
+    case 1: launch_grouped<64, 64, 16, 2>(prec, gp, tile0, G, grid, st); break;
+    case 2: launch_grouped<32, 32, 16, 2>(prec, gp, tile0, G, grid, st); break;
+    case 3: launch_grouped<64, 64, 8, 2>(prec, gp, tile0, G, grid, st); break;
+    case 4: launch_grouped<128, 64, 8, 2>(prec, gp, tile0, G, grid, st); break;
+    case 5: launch_grouped<64, 128, 8, 2>(prec, gp, tile0, G, grid, st); break;
+    case 7: launch_grouped<64, 32, 16, 2>(prec, gp, tile0, G, grid, st); break;
+    default: throw Error(ST_EINVAL, "grouped filter: bad tile configuration");
+  }
+}
 
 // Choose the tile configuration and the K split: maximise the estimated
 // throughput = per-tile efficiency x occupancy of the chip's workgroup slots
@@ -432,12 +538,31 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
     else c = 7;                   // 64 x 32 x 16
     int sk = (int)std::min<int64_t>(8, std::max<int64_t>(1, (g.K + 500) / 1000));
     if (g.N < 96) sk = 8;
+    // a triangular op(A) leaves the top row panels short: deeper splits
+    // rebalance the workgroups
+    if (g.flags & (GEMM_TRI_A_LOWER | GEMM_TRI_A_UPPER)) sk = std::min(16, 2 * sk);
     const size_t cap = (size_t)P_elems * (g.prec == PREC_F32 ? 2 : 1);
     while (sk > 1 && (!g.allow_splitk || !P_elems || (size_t)sk * g.M * g.N > cap ||
                       g.K < (int64_t)sk * 4 * CFGS[c].bk))
       sk /= 2;
     cfg = c;
     splitk = sk;
+    return;
+  }
+  // Small outputs of deep products (Gram matrices Y^H Y, Q^H W): 32 x 32
+  // tiles split 16 ways; tall products with a short K (n x k times k x k):
+  // 32 x 32 tiles, no split (both read off the same sweep).
+  if (batch == 1 && g.M * g.N <= 512 * 512 && g.K >= 2048 && g.allow_splitk && P_elems &&
+      !(g.flags & GEMM_OUT_LOWER) && g.prec == PREC_F64) {
+    int sk = 16;
+    while (sk > 1 && ((size_t)sk * g.M * g.N > (size_t)P_elems || g.K < (int64_t)sk * 4 * CFGS[2].bk)) sk /= 2;
+    cfg = 2;
+    splitk = sk;
+    return;
+  }
+  if (batch == 1 && g.K <= 512 && g.M >= 1024 && g.N <= 512) {
+    cfg = 2;
+    splitk = 1;
     return;
   }
   double best = -1.0;

@@ -1,0 +1,108 @@
+"""The serving loop: many sequences, concurrent workers, resident warm state,
+admission by device-memory budget.  Each result must be the same whether its
+sequence runs alone or mixed with the others (deterministic kernels, one
+context and stream per solve), and must meet the FP64 tolerance."""
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+import workloads
+from tests import _checks
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    a = np.asarray(a, dtype=np.complex128)
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to("cuda").mT
+
+
+SIZES = {0: 150, 1: 220, 2: 260, 3: 300}
+STEPS = 3
+
+
+@pytest.fixture(scope="module")
+def sequences(gpu):
+    out = {}
+    for s, n in SIZES.items():
+        seq = list(workloads.make_sequence(n, STEPS, 500 + s))
+        out[s] = [(p, _t(p.H), _t(p.S)) for p in seq]
+    return out
+
+
+def _nev(n):
+    return max(4, n // 12), max(2, n // 60)
+
+
+def _run(lib, sequences, order, workers):
+    srv = lib.Server(workers=workers, hbm_budget_bytes=8 << 30, degree=10, seed=0)
+    tickets = {}
+    for s, ell in order:
+        p, H, S = sequences[s][ell]
+        nev, nex = _nev(p.n)
+        tickets[(s, ell)] = srv.submit(s, H, S, nev, nex, tol=1e-10)
+    res = {}
+    for key, t in tickets.items():
+        ev, X, info, lat, st = srv.wait(t)
+        assert st == 0
+        res[key] = (ev, X.cpu().numpy(), info)
+    stats = srv.stats()
+    srv.close()
+    return res, stats
+
+
+def test_server_results_same_alone_and_in_the_mix(lib, sequences):
+    alone = {}
+    for s in SIZES:
+        r, _ = _run(lib, sequences, [(s, ell) for ell in range(STEPS)], workers=1)
+        alone.update(r)
+    mix_order = [(s, ell) for ell in range(STEPS) for s in SIZES]
+    mixed, stats = _run(lib, sequences, mix_order, workers=3)
+    assert stats["completed"] == len(mix_order) and stats["failed"] == 0
+    assert stats["p99_latency"] >= stats["p50_latency"] > 0
+    for key in alone:
+        ev_a, X_a, info_a = alone[key]
+        ev_m, X_m, info_m = mixed[key]
+        # same arithmetic: identical to the last bit
+        assert np.array_equal(ev_a, ev_m), key
+        assert np.array_equal(X_a, X_m), key
+        s, ell = key
+        p = sequences[s][ell][0]
+        nev = len(ev_a)
+        hn = _checks.spectral_norm(p.H)
+        ref = sl.eigh(p.H, p.S, eigvals_only=True)[:nev]
+        assert _checks.eig_ok(ev_a, ref, hn)[0]
+        r = _checks.gen_residuals(p.H, p.S, X_a, ev_a)
+        assert r.max() <= 1e-10 * hn
+        assert info_a["warm_start"] == (1 if ell > 0 else 0)
+
+
+@pytest.fixture(scope="module")
+def lib(gpu):
+    from paper_1305_5120_amd import chfsi
+    return chfsi
+
+
+def test_server_admits_within_budget(lib, sequences):
+    # room for about one context at a time: requests are serialized, peak
+    # memory stays under the budget, every request still completes
+    p, H, S = sequences[3][0]
+    budget = 60 * 300 * 300 * 16
+    srv = lib.Server(workers=3, hbm_budget_bytes=budget, degree=10)
+    tickets = [srv.submit(s, *sequences[s][0][1:], *_nev(sequences[s][0][0].n)) for s in SIZES]
+    for t in tickets:
+        ev, X, info, lat, st = srv.wait(t)
+        assert st == 0
+    st = srv.stats()
+    assert st["peak_bytes"] <= budget and st["completed"] == len(SIZES)
+    srv.close()
+
+
+def test_server_rejects_request_larger_than_budget(lib, sequences):
+    p, H, S = sequences[0][0]
+    srv = lib.Server(workers=2, hbm_budget_bytes=1 << 20, degree=10)
+    t = srv.submit(0, H, S, *_nev(p.n))
+    ev, X, info, lat, st = srv.wait(t, raise_on_error=False)
+    assert st == -5
+    srv.close()
