@@ -164,12 +164,286 @@ def cpu_baseline(cfg, gpu_filter_flops_per_solve, target_seconds=12.0):
     }
 
 
+# --------------------------------------------------------------------------
+# Further forms of the method, each printing its own JSON line: the
+# precision form (FP64 vs mixed on one large problem), the batching form
+# (many k-point sequences in lockstep), the serving form (Poisson arrivals),
+# and the warm-versus-cold study along a sequence.
+# --------------------------------------------------------------------------
+
+def _base(metric, value, unit, steps, warmup, ms, dtype, config, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def _exact_errors(p, evals):
+    """max |lambda_i - lambda_i(exact)| / ||A||_2 over the returned pairs,
+    against the spectrum the problem was built with."""
+    import numpy as np
+    lam = np.sort(p["lam"])[:len(evals)]
+    return float(np.abs(np.asarray(evals) - lam).max() / np.abs(p["lam"]).max())
+
+
+def run_precision(args):
+    """One n = 10000 problem solved cold in FP64 and with the mixed filter."""
+    import torch
+    from paper_1305_5120_amd import chfsi
+    import workloads
+    n, nev, nex, m = 10000, 600, 60, 20
+    p = workloads.make_problem_torch(n, 2, device="cuda")
+    torch.cuda.synchronize()
+    res = {}
+    for prec in (0, 1):
+        ctx = chfsi.create(n, degree=m, seed=0, precision=prec, profile=1)
+        times = []
+        for i in range(args.warmup + args.steps):
+            ctx.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev, X, info, st = chfsi.solve(ctx, p["H"], p["S"], nev, nex, tol=1e-10)
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                times.append(time.perf_counter() - t0)
+        res[prec] = dict(t=sum(times) / len(times), info=info, err=_exact_errors(p, ev),
+                         res=residual_check(p, ev, X))
+        log(f"[bench] precision {prec}: {res[prec]['t']:.3f} s/solve, {info['iterations']} iterations "
+            f"({info['iterations_fp32']} FP32), max eigenvalue error {res[prec]['err']:.2e}, "
+            f"residual {res[prec]['res']:.2e}")
+        ctx.release()
+    i64, i32 = res[0]["info"], res[1]["info"]
+    f32 = i32["filter_flops_fp32"] / i32["filter_kernel_seconds_fp32"] / 1e12 if i32["filter_kernel_seconds_fp32"] else None
+    f64 = i64["filter_flops"] / i64["filter_kernel_seconds"] / 1e12 if i64["filter_kernel_seconds"] else None
+    out = _base("eigensolves/s, mixed-precision filter (FP32 MFMA) with FP64 final sweeps, residual <=1e-10",
+                1.0 / res[1]["t"], "solves/s", args.steps, args.warmup, 1e3 * res[1]["t"], "complex64 filter + f64",
+                {"workload": "single complex Hermitian DGEVP, FLAPW-shaped synthetic spectrum", "n": n, "nev": nev,
+                 "nex": nex, "degree": m, "tol": 1e-10, "precision": "mixed", "warm_start": False})
+    out.update({"fp64_solves_per_s": 1.0 / res[0]["t"], "speedup_vs_fp64": res[0]["t"] / res[1]["t"],
+                "fp64": {"iterations": i64["iterations"], "max_eig_error_rel": res[0]["err"],
+                         "max_rel_residual": res[0]["res"], "filter_tflops": f64},
+                "mixed": {"iterations": i32["iterations"], "iterations_fp32": i32["iterations_fp32"],
+                          "max_eig_error_rel": res[1]["err"], "max_rel_residual": res[1]["res"],
+                          "filter_tflops_fp32": f32},
+                "roofline": {"bound": "mfma", "achieved": f32, "peak": 157.3, "unit": "TFLOP/s",
+                             "frac": f32 / 157.3 if f32 else None, "traffic": None}})
+    print(json.dumps(out), flush=True)
+
+
+def _batch_sizes(count, seed):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return [int(v) for v in rng.integers(2000, 6001, count)]
+
+
+def run_batch(args):
+    """k-point sequences in lockstep (grouped filter launches, captured
+    graphs, online tile choice, mixed precision) against the same problems
+    solved one after another with one context per sequence."""
+    import torch
+    from paper_1305_5120_amd import chfsi
+    import workloads
+    G, steps = args.members, args.seq_steps
+    sizes = _batch_sizes(G, 3)
+    nevs = [n // 10 for n in sizes]
+    nexs = [max(1, v // 10) for v in nevs]
+    seqs = []
+    for i, n in enumerate(sizes):
+        seqs.append(list(workloads.make_sequence_torch(n, steps, 3 + i, device="cuda")))
+        log(f"[bench] generated sequence {i + 1}/{G} (n={n})")
+    torch.cuda.synchronize()
+    prec = 1
+
+    def step_inputs(ell):
+        H = [s[ell]["H"] for s in seqs]
+        S = [s[0]["S"] if ell == 0 else None for s in seqs]
+        return H, S
+
+    # batched: step 0 cold (and the online tile choice), steps 1.. timed
+    b = chfsi.Batch(sizes, use_graph=True, degree=20, seed=0, precision=prec)
+    H, S = step_inputs(0)
+    _, _, _, st, rep0 = b.solve(H, S, nevs, nexs, tol=1e-10)
+    log(f"[bench] batch cold step: {rep0['seconds']:.2f} s, tile {rep0['tile_config']}/{rep0['tile_config_fp32']}")
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ell in range(1, steps):
+        H, S = step_inputs(ell)
+        ev, X, infos, st, rep = b.solve(H, S, nevs, nexs, tol=1e-10)
+        reps.append(rep)
+        log(f"[bench] batch step {ell}: {rep['seconds']:.2f} s, {rep['outer_iterations']} outer iterations")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    worst = max(residual_check({"H": seqs[i][steps - 1]["H"], "S": seqs[i][0]["S"]}, ev[i], X[i])
+                for i in range(0, G, max(1, G // 4)))
+    b.close()
+    del ev, X
+    # one after another
+    ctxs = [chfsi.create(n, degree=20, seed=0, precision=prec) for n in sizes]
+    H, S = step_inputs(0)
+    for i in range(G):
+        chfsi.solve(ctxs[i], H[i], S[i], nevs[i], nexs[i], tol=1e-10, want_vectors=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ell in range(1, steps):
+        H, S = step_inputs(ell)
+        for i in range(G):
+            chfsi.solve(ctxs[i], H[i], S[i], nevs[i], nexs[i], tol=1e-10)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    for c in ctxs:
+        c.release()
+    solves = G * (steps - 1)
+    ff = sum(r["filter_flops"] for r in reps)
+    fs = sum(r["filter_seconds"] for r in reps)
+    out = _base("batched eigensolves/s over k-point sequences (grouped filter launches), residual <=1e-10",
+                solves / tb, "solves/s", steps - 1, 1, 1e3 * tb / (steps - 1), "complex64 filter + f64",
+                {"workload": "independent k-point sequences of correlated complex Hermitian DGEVPs",
+                 "sequences": G, "n": f"uniform integers in [2000, 6000] (seed 3): {sizes}",
+                 "nev": "n/10", "nex": "nev/10", "degree": 20, "tol": 1e-10, "precision": "mixed",
+                 "warm_start": True, "sequence_steps_timed": steps - 1})
+    out.update({"sequential_solves_per_s": solves / ts, "speedup_vs_sequential": ts / tb,
+                "grouped_filter_tflops": ff / fs / 1e12 if fs else None,
+                "tile_config": rep0["tile_config"], "tile_config_fp32": rep0["tile_config_fp32"],
+                "tile_rate_tflops": rep0["tile_rate"], "graph": reps[-1]["graph"] if reps else None,
+                "max_rel_residual_sampled": worst})
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Poisson arrivals of problems from many k-point sequences into the
+    serving loop (workers with their own streams, device-memory admission,
+    resident warm state)."""
+    import numpy as np
+    import torch
+    from paper_1305_5120_amd import chfsi
+    import workloads
+    nseq, steps = args.members, args.seq_steps
+    rng = np.random.default_rng(4)
+    sizes = [int(round(math.exp(v))) for v in rng.uniform(math.log(1000), math.log(6000), nseq)]
+    nevs = [max(4, int(n * f)) for n, f in zip(sizes, rng.uniform(0.03, 0.20, nseq))]
+    nexs = [max(1, v // 10) for v in nevs]
+    seqs = []
+    for i, n in enumerate(sizes):
+        seqs.append(list(workloads.make_sequence_torch(n, steps, 400 + i, device="cuda")))
+        log(f"[bench] generated sequence {i + 1}/{nseq} (n={n}, nev={nevs[i]})")
+    torch.cuda.synchronize()
+    order = [(s, ell) for ell in range(steps) for s in range(nseq)]
+    gaps = rng.exponential(1.0 / args.rate, len(order))
+    srv = chfsi.Server(workers=args.workers, hbm_budget_bytes=int(args.budget_gb * (1 << 30)), degree=20, seed=0)
+    t0 = time.perf_counter()
+    tickets = []
+    t_next = t0
+    for (s, ell), g in zip(order, gaps):
+        t_next += g
+        d = t_next - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        tickets.append(srv.submit(s, seqs[s][ell]["H"], seqs[s][0]["S"], nevs[s], nexs[s], tol=1e-10,
+                                  want_vectors=False))
+    for t in tickets:
+        srv.wait(t)
+    elapsed = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    log(f"[bench] served {stats['completed']} requests in {elapsed:.1f} s")
+    out = _base("eigensolves/s and p50/p99 latency under Poisson arrivals, residual <=1e-10",
+                stats["solves_per_second"], "solves/s", len(order), 0, 1e3 * elapsed / len(order), "complex128 (f64)",
+                {"workload": "Poisson arrivals of DGEVP requests from k-point sequences", "sequences": nseq,
+                 "n": f"log-uniform in [1000, 6000] (seed 4): {sizes}", "nev": "uniform 3-20% of n",
+                 "nex": "nev/10", "steps_per_sequence": steps, "arrival_rate_per_s": args.rate,
+                 "workers": args.workers, "hbm_budget_gb": args.budget_gb, "degree": 20, "tol": 1e-10})
+    out.update({"p50_latency_s": stats["p50_latency"], "p99_latency_s": stats["p99_latency"],
+                "mean_latency_s": stats["mean_latency"], "completed": stats["completed"], "failed": stats["failed"],
+                "peak_bytes": stats["peak_bytes"]})
+    print(json.dumps(out), flush=True)
+
+
+def run_warmcold(args):
+    """Warm versus cold starts along a correlated sequence (fixed S and a
+    varying-S variant that goes through the generalized-space map of the
+    block), with the eigenvector correlation between consecutive problems."""
+    import numpy as np
+    import torch
+    from paper_1305_5120_amd import chfsi
+    import workloads
+    n, nev, nex, steps = args.wc_n, args.wc_n // 10, max(1, args.wc_n // 100), args.seq_steps
+    seq = list(workloads.make_sequence_torch(n, steps, 5, device="cuda"))
+    S0 = seq[0]["S"]
+    # varying-S variant: S_l = L_l L_l^H with L_l = L_0 + 1e-4 (strict lower Gaussian)/sqrt(n) per step
+    gen = torch.Generator(device="cpu").manual_seed(55)
+    Ls = [seq[0]["L"]]
+    for _ in range(1, steps):
+        E = torch.complex(torch.randn(n, n, generator=gen, dtype=torch.float64),
+                          torch.randn(n, n, generator=gen, dtype=torch.float64)).to("cuda") / math.sqrt(2)
+        Ls.append(Ls[-1] + 1e-4 * torch.tril(E, -1) / math.sqrt(n))
+    A_of = [seq[0]["A"]]
+    Linv0 = torch.linalg.inv(seq[0]["L"])
+    for ell in range(1, steps):
+        A_of.append(Linv0 @ seq[ell]["H"] @ Linv0.conj().T)
+    Hs_v = [(L @ A @ L.conj().T) for L, A in zip(Ls, A_of)]
+    Hs_v = [((h + h.conj().T) / 2).mT.contiguous().mT for h in Hs_v]
+    Ss_v = [((L @ L.conj().T + (L @ L.conj().T).conj().T) / 2).mT.contiguous().mT for L in Ls]
+    torch.cuda.synchronize()
+    rows = {}
+    for variant in ("fixed_S", "varying_S"):
+        warm = chfsi.create(n, degree=20, seed=0)
+        cold = chfsi.create(n, degree=20, seed=0)
+        prevX = None
+        recs = []
+        for ell in range(steps):
+            if variant == "fixed_S":
+                H, S_w, S_c = seq[ell]["H"], (S0 if ell == 0 else None), S0
+            else:
+                H, S_w, S_c = Hs_v[ell], Ss_v[ell], Ss_v[ell]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev, X, iw, _ = chfsi.solve(warm, H, S_w, nev, nex, tol=1e-10)
+            torch.cuda.synchronize()
+            tw = time.perf_counter() - t0
+            cold.reset()
+            t0 = time.perf_counter()
+            evc, Xc, ic, _ = chfsi.solve(cold, H, S_c, nev, nex, tol=1e-10, want_vectors=False)
+            torch.cuda.synchronize()
+            tc = time.perf_counter() - t0
+            theta = None
+            if prevX is not None:
+                Sm = S0 if variant == "fixed_S" else Ss_v[ell]
+                c = torch.abs(torch.sum(prevX.conj() * (Sm @ X), dim=0)).cpu().numpy()
+                theta = float(np.median(1.0 - np.minimum(c, 1.0)))
+            prevX = X
+            recs.append({"step": ell, "warm_iterations": iw["iterations"], "cold_iterations": ic["iterations"],
+                         "warm_s": tw, "cold_s": tc, "warm_start": iw["warm_start"], "median_1_minus_corr": theta})
+            log(f"[bench] {variant} step {ell}: warm {iw['iterations']} it {tw:.3f} s, cold {ic['iterations']} it "
+                f"{tc:.3f} s, 1-corr {theta}")
+        warm.release()
+        cold.release()
+        rows[variant] = recs
+    r = rows["fixed_S"][1:]
+    speed = sum(x["cold_s"] for x in r) / sum(x["warm_s"] for x in r)
+    out = _base("speed-up of warm over cold starts along a correlated sequence (eigensolves)", speed, "x",
+                steps - 1, 1, 1e3 * sum(x["warm_s"] for x in r) / len(r), "complex128 (f64)",
+                {"workload": "sequence of correlated complex Hermitian DGEVPs, FLAPW-shaped synthetic spectrum",
+                 "n": n, "nev": nev, "nex": nex, "degree": 20, "tol": 1e-10, "steps": steps,
+                 "perturbation": 1e-4})
+    out["per_step"] = rows
+    out["speedup_varying_S"] = (sum(x["cold_s"] for x in rows["varying_S"][1:]) /
+                                sum(x["warm_s"] for x in rows["varying_S"][1:]))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="seq4000", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="seq4000",
+                    choices=sorted(WORKLOADS) + ["precision", "batch", "serve", "warmcold"])
+    ap.add_argument("--members", type=int, default=16, help="sequences (batch / serve forms)")
+    ap.add_argument("--seq-steps", type=int, default=3, help="problems per sequence (batch / serve / warmcold)")
+    ap.add_argument("--rate", type=float, default=6.0, help="Poisson arrival rate per second (serve form)")
+    ap.add_argument("--workers", type=int, default=4, help="serving workers")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serving device-memory budget")
+    ap.add_argument("--wc-n", type=int, default=4000, help="problem size of the warm/cold study")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not time filter launches with events")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -185,6 +459,10 @@ def main():
     import torch
     from paper_1305_5120_amd import chfsi
     chfsi.load()
+    forms = {"precision": run_precision, "batch": run_batch, "serve": run_serve, "warmcold": run_warmcold}
+    if args.workload in forms:
+        forms[args.workload](args)
+        return
     dev = torch.device("cuda:0")
     cfg = WORKLOADS[args.workload]
     total = args.warmup + args.steps

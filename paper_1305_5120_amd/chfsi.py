@@ -465,3 +465,115 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------
+# batching
+# --------------------------------------------------------------------------
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [("tile_config", c_i32), ("tile_config_fp32", c_i32), ("graph", c_i32), ("outer_iterations", c_i32),
+                ("grouped_launches", c_i32), ("converged_members", c_i32), ("filter_flops", c_dbl),
+                ("filter_seconds", c_dbl), ("seconds", c_dbl), ("tile_rate", c_dbl * 8)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "tile_rate"}
+        d["tile_rate"] = list(self.tile_rate)
+        return d
+
+
+def _load_batch(L):
+    if getattr(L, "_batch_ready", False):
+        return
+    P = ctypes.POINTER
+    L.chfsi_batch_create.argtypes = [P(c_vp), c_i32, P(c_i64), P(Opts), c_i32]
+    L.chfsi_batch_create.restype = ctypes.c_int
+    L.chfsi_batch_solve.argtypes = [c_vp, P(c_vp), P(c_i64), P(c_vp), P(c_i64), P(c_i64), P(c_i64), c_dbl, P(c_vp),
+                                    P(c_vp), P(c_i64), P(Info), P(c_i32), P(BatchReport)]
+    L.chfsi_batch_solve.restype = ctypes.c_int
+    L.chfsi_batch_reset.argtypes = [c_vp]
+    L.chfsi_batch_reset.restype = ctypes.c_int
+    L.chfsi_batch_last_error.argtypes = [c_vp]
+    L.chfsi_batch_last_error.restype = ctypes.c_char_p
+    L.chfsi_batch_release.argtypes = [c_vp]
+    L._batch_ready = True
+
+
+class Batch:
+    """Lockstep solver for a fixed set of independent problems whose filters
+    share grouped launches (chfsi_batch_*).  Member i solves problems of size
+    sizes[i] and keeps its warm state between calls."""
+
+    def __init__(self, sizes, use_graph=True, **opts):
+        self.lib = load()
+        _load_batch(self.lib)
+        self.sizes = [int(n) for n in sizes]
+        arr = (c_i64 * len(self.sizes))(*self.sizes)
+        o = default_opts(**opts)
+        h = c_vp()
+        st = self.lib.chfsi_batch_create(ctypes.byref(h), len(self.sizes), arr, ctypes.byref(o), 1 if use_graph else 0)
+        if st != 0:
+            raise ChfsiError(st, "chfsi_batch_create failed")
+        self.h = h
+
+    def solve(self, H, S, nev, nex, tol=1e-10, want_vectors=True, raise_on_error=True):
+        """H, S: lists of device matrices (S entries may be None); nev, nex:
+        lists of ints.  Returns (evals list, X list, infos, statuses, report)."""
+        import torch
+        G = len(self.sizes)
+        if not (len(H) == len(S) == len(nev) == len(nex) == G):
+            raise ValueError("one H, S, nev, nex per member")
+        keep = []
+        hp, lh, sp, ls, xp, lx, ev = [], [], [], [], [], [], []
+        evals, Xs = [], []
+        for i in range(G):
+            n = self.sizes[i]
+            _check_dev(H[i], f"H[{i}]")
+            if H[i].shape != (n, n):
+                raise ValueError(f"H[{i}] must be {n} x {n}")
+            Hc, ldh = colmajor(H[i])
+            keep.append(Hc)
+            hp.append(Hc.data_ptr())
+            lh.append(ldh)
+            if S[i] is not None:
+                _check_dev(S[i], f"S[{i}]")
+                Sc, lds = colmajor(S[i])
+                keep.append(Sc)
+                sp.append(Sc.data_ptr())
+                ls.append(lds)
+            else:
+                sp.append(None)
+                ls.append(n)
+            e = np.zeros(int(nev[i]))
+            evals.append(e)
+            ev.append(e.ctypes.data)
+            X = empty_colmajor(n, int(nev[i]), H[i].device) if want_vectors else None
+            Xs.append(X)
+            xp.append(X.data_ptr() if X is not None else None)
+            lx.append(n)
+        torch.cuda.current_stream().synchronize()
+        infos = (Info * G)()
+        stats = (c_i32 * G)()
+        rep = BatchReport()
+        st = self.lib.chfsi_batch_solve(self.h, (c_vp * G)(*hp), (c_i64 * G)(*lh), (c_vp * G)(*sp), (c_i64 * G)(*ls),
+                                        (c_i64 * G)(*[int(v) for v in nev]), (c_i64 * G)(*[int(v) for v in nex]),
+                                        float(tol), (c_vp * G)(*ev), (c_vp * G)(*xp), (c_i64 * G)(*lx), infos, stats,
+                                        ctypes.byref(rep))
+        if st != 0 and raise_on_error:
+            msg = self.lib.chfsi_batch_last_error(self.h)
+            raise ChfsiError(st, msg.decode() if msg else "")
+        return evals, Xs, [infos[i].as_dict() for i in range(G)], list(stats), rep.as_dict()
+
+    def reset(self):
+        self.lib.chfsi_batch_reset(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.chfsi_batch_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -108,6 +108,8 @@ struct chfsi_ctx_s {
   DBuf LV, Lw, Lh, Lab, mvpart, Tsm, Tz, Tz2, Tw, npart;
   // sparse Jacobi schedules
   DBuf jint, jrot;
+  // eigenvector refinement: six k x k blocks, Rayleigh quotients, max correction
+  DBuf rf, rfl, rfc;
   // host staging (pinned)
   double* hbuf = nullptr;
   size_t hbuf_elems = 0;
@@ -173,6 +175,8 @@ struct chfsi_ctx_s {
       b->release();
       b->ensure(kk2);
     }
+    rf.release(); rf.ensure((size_t)6 * kk * kk * sizeof(zc));
+    rfl.release(); rfl.ensure((size_t)kk * sizeof(double));
     mu.release(); mu.ensure((size_t)kk * sizeof(double));
     rho.release(); rho.ensure((size_t)kk * sizeof(double));
     rank.release(); rank.ensure((size_t)kk * sizeof(int));
@@ -199,6 +203,7 @@ struct chfsi_ctx_s {
 
   void ensure_small() {
     norms.ensure(8 * sizeof(double));
+    rfc.ensure(sizeof(unsigned long long));
     flags.ensure(8 * sizeof(int));
     const int steps = std::max(1, opts.lanczos_steps);
     LV.ensure((size_t)n * (steps + 1) * sizeof(zc));
@@ -219,7 +224,7 @@ struct chfsi_ctx_s {
   void free_all() {
     for (DBuf* b : {&A32, &Y32, &Y32b, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
                     &flags, &P, &hpart, &htop, &tau, &Tall, &gram, &Vp, &Wt, &W2, &LV, &Lw, &Lh, &Lab, &mvpart, &Tsm,
-                    &Tz, &Tz2, &Tw, &npart, &jint, &jrot})
+                    &Tz, &Tz2, &Tw, &npart, &jint, &jrot, &rf, &rfl, &rfc})
       b->release();
     if (hbuf) (void)hipHostFree(hbuf);
     hbuf = nullptr;
@@ -351,6 +356,8 @@ struct chfsi_ctx_s {
     int* pairs = offsets + k;
     int* rounds_d = pairs + 2 * max_sparse;
     for (int sweep = 0; sweep < 100; sweep++) {
+      // once the matrix is close to diagonal, refinement finishes the job
+      if (refine(g0, sweep > 0 ? z0 : nullptr, k, w, Zo, ldz, tau)) return;
       jacobi_count(g0, k, nr + 1, THR, tau, counts, st);
       CHFSI_HIP(hipMemcpyAsync(hbuf, counts, k * sizeof(int), hipMemcpyDeviceToHost, st));
       sync();
@@ -428,6 +435,60 @@ struct chfsi_ctx_s {
       }
     }
     jacobi_sort(g0, z0, k, w, rank.i(), Zo, ldz, st);
+  }
+
+  // Eigen-decomposition of a nearly diagonal Hermitian Gm (k x k, ld k) by
+  // iterative refinement of X = I (refine_coeffs).  Zpre (nullable, k x k)
+  // holds rotations already applied to the caller's matrix; the result is
+  // Zpre X.  Returns false, with w and Zo untouched, when some coupled pair's
+  // correction exceeds ETA (the matrix is not close enough to diagonal for
+  // the iteration to converge fast) or the corrections do not fall below
+  // DONE within MAX_STEPS steps; the caller then continues with Jacobi.
+  bool refine(const zc* Gm, const zc* Zpre, int64_t k, double* w, zc* Zo, int64_t ldz, double tau) {
+    const double ETA = 0.02, DONE = 1e-10;
+    const int MAX_STEPS = 8;
+    const int64_t kk = k * k;
+    zc* X = rf.z();
+    zc* Xn = X + kk;
+    zc* Wb = Xn + kk;
+    zc* Sb = Wb + kk;
+    zc* Pb = Sb + kk;
+    zc* Eb = Pb + kk;
+    double* lam = rfl.d();
+    auto* corr = static_cast<unsigned long long*>(rfc.p);
+    auto read_corr = [&]() {
+      CHFSI_HIP(hipMemcpyAsync(hbuf, corr, sizeof(double), hipMemcpyDeviceToHost, st));
+      sync();
+      double c;
+      std::memcpy(&c, hbuf, sizeof(double));
+      return c;
+    };
+    // step 0: X = I, S = Gm, P = I
+    CHFSI_HIP(hipMemsetAsync(corr, 0, sizeof(unsigned long long), st));
+    refine_coeffs(Gm, nullptr, k, tau, Eb, X, lam, corr, st);
+    double c = read_corr();
+    if (!(c <= ETA)) return false;
+    for (int step = 1; !(c < DONE); step++) {
+      if (step > MAX_STEPS) return false;
+      gemm(OP_N, OP_N, k, k, k, 1.0, Gm, k, X, k, Wb, k);
+      gemm(OP_C, OP_N, k, k, k, 1.0, X, k, Wb, k, Sb, k);
+      gemm(OP_C, OP_N, k, k, k, 1.0, X, k, X, k, Pb, k);
+      hermitize(Sb, k, k, st);
+      hermitize(Pb, k, k, st);
+      CHFSI_HIP(hipMemsetAsync(corr, 0, sizeof(unsigned long long), st));
+      refine_coeffs(Sb, Pb, k, tau, Eb, nullptr, lam, corr, st);
+      gemm(OP_N, OP_N, k, k, k, 1.0, X, k, Eb, k, Xn, k, 1.0, X, k);  // X + X E
+      std::swap(X, Xn);
+      c = read_corr();
+      if (!(c <= ETA)) return false;
+    }
+    const zc* Zf = X;
+    if (Zpre) {
+      gemm(OP_N, OP_N, k, k, k, 1.0, Zpre, k, X, k, Wb, k);
+      Zf = Wb;
+    }
+    sort_by_values(lam, Zf, k, w, rank.i(), Zo, ldz, st);
+    return true;
   }
 
   // ------------------------------------------------------------------------
@@ -1287,6 +1348,7 @@ struct chfsi_batch_s {
     if (gexec[prec]) (void)hipGraphExecDestroy(gexec[prec]);
     gexec[prec] = nullptr;
     hipGraph_t graph = nullptr;
+    (void)grid_of(prec, c);  // device queries stay outside the capture
     CHFSI_HIP(hipStreamBeginCapture(gst, hipStreamCaptureModeThreadLocal));
     try {
       launch_steps(prec, c, m);

@@ -148,8 +148,7 @@ __global__ void k_nonfinite(const zc* A, int64_t lda, int64_t n, int64_t k, int*
 //   * updates its trailing entries  A(r, c) -= l(r, j) conj(l(c, j)),  c > j,
 //   * applies step j of the column-oriented forward substitution for L X = I:
 //     row j of X is divided by l(j, j) and l(r, j) times it is subtracted from
-//     rows r > j.  Row j of X sits in lane j of the same wave, so it is taken
-//     with a cross-lane read, not through LDS.
+//     rows r > j (lane j of each wave publishes its part of row j in LDS).
 // X(r, c) is zero for c > j until step c, and the trailing update only touches
 // c > j, so each thread has about 16 complex updates per step.
 // --------------------------------------------------------------------------
@@ -158,9 +157,11 @@ constexpr int CNB = CHOL_NB;
 __global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi,
                                                     int64_t j0, int nb, int* info) {
   static_assert(CNB == 64, "one row per lane, four waves of columns");
-  __shared__ zc col[2][CNB];
+  __shared__ zc col[2][CNB];   // column j of L
+  __shared__ zc xrow[2][CNB];  // row j of X before its division by l(j, j)
   __shared__ int failed;
-  const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
+  const int tid = threadIdx.x, r = tid & 63;
+  const int q = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index: uniform branches below
   zc a[16], x[16];
 #pragma unroll
   for (int t = 0; t < 16; t++) {
@@ -189,20 +190,38 @@ __global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc*
         col[buf][r] = l;
       }
     }
+    if (r == j) {
+#pragma unroll
+      for (int t = 0; t < 16; t++) xrow[buf][q + 4 * t] = x[t];
+    }
     __syncthreads();
     if (failed >= 0) break;  // uniform: read after the barrier
+    // every operand of this step first (broadcast LDS reads), then the updates
     const zc lr = col[buf][r];
     const double dinv = 1.0 / col[buf][j].x;
+    // slot t needs l(c, j) for c > j (trailing update) or X(j, c) for c <= j
+    zc o[16];
 #pragma unroll
     for (int t = 0; t < 16; t++) {
-      const int c = q + 4 * t;  // uniform over the wave
+      const int c = q + 4 * t;
+      o[t] = (c > j ? col[buf] : xrow[buf])[c];
+    }
+    // branch-free per lane: the slot's case is uniform over the wave, the
+    // row conditions are selects
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+      const int c = q + 4 * t;
       if (c > j) {
-        const zc lc = col[buf][c];
-        if (r >= c) a[t] = zsub(a[t], zmul(lr, zconj(lc)));
+        // a -= lr conj(o) on rows r >= c
+        const double ux = fma(-lr.x, o[t].x, fma(-lr.y, o[t].y, a[t].x));
+        const double uy = fma(-lr.y, o[t].x, fma(lr.x, o[t].y, a[t].y));
+        if (r >= c) a[t] = zmk(ux, uy);
       } else {
-        const zc xj = zmk(__shfl(x[t].x, j, 64) * dinv, __shfl(x[t].y, j, 64) * dinv);
-        if (r == j) x[t] = xj;
-        else if (r > j) x[t] = zsub(x[t], zmul(lr, xj));
+        const double vx = dinv * o[t].x, vy = dinv * o[t].y;
+        // rows below j: x -= lr v; row j: x = v
+        const double ux = fma(-lr.x, vx, fma(lr.y, vy, x[t].x));
+        const double uy = fma(-lr.x, vy, fma(-lr.y, vx, x[t].y));
+        x[t] = r == j ? zmk(vx, vy) : (r > j ? zmk(ux, uy) : x[t]);
       }
     }
   }
@@ -806,6 +825,76 @@ __global__ void k_jacobi_permute(const zc* Z, int64_t k, const int* rank, zc* Zo
 }
 
 // --------------------------------------------------------------------------
+// Iterative refinement of the eigenvectors of a nearly diagonal Hermitian G
+// (the projected matrix once the block is close to invariant).  X holds
+// approximate eigenvectors; with S = X^H G X, P = X^H X, R = I - P and the
+// Rayleigh quotients lam_i = Re S_ii / P_ii, one step sets
+//   E_ij = (S_ij + lam_j R_ij) / (lam_j - lam_i)   for coupled pairs,
+//   E_ij = R_ij / 2                                for pairs whose coupling is
+//                                                  below tau (and i = j),
+//   X <- X + X E.
+// (Ogita and Aishima's refinement for symmetric eigenproblems, with a
+// threshold instead of their cluster test.)  The decision for a pair uses
+// max(|S_ij + lam_j R_ij|, |S_ij + lam_i R_ij|), which is the same for (i, j)
+// and (j, i) when S and P are exactly Hermitian, so E_ij + conj(E_ji) = R_ij
+// and the orthogonality error is corrected together with the coupling.
+// corr (bit pattern of a non-negative double) receives max |E_ij| over i != j,
+// +inf for a non-finite value.
+// --------------------------------------------------------------------------
+__global__ void k_refine_coeffs(const zc* S, const zc* P, int64_t k, double tau, zc* E, zc* Xout, double* lam,
+                                unsigned long long* corr) {
+  __shared__ double red[NT / 64];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double c = 0.0;
+  if (e < k * k) {
+    const int64_t i = e % k, j = e / k;
+    const double pii = P ? P[i + i * k].x : 1.0, pjj = P ? P[j + j * k].x : 1.0;
+    const double li = S[i + i * k].x / pii, lj = S[j + j * k].x / pjj;
+    zc ev;
+    if (i == j) {
+      ev = zmk(0.5 * (1.0 - pii), 0.0);
+      if (lam) lam[i] = li;
+    } else {
+      const zc r = P ? zmk(-P[e].x, -P[e].y) : zmk(0.0, 0.0);
+      const zc sij = S[e];
+      const zc n1 = zadd(sij, zscale(lj, r)), n2 = zadd(sij, zscale(li, r));
+      const double m2 = fmax(zabs2(n1), zabs2(n2));
+      if (m2 > tau * tau) ev = zscale(1.0 / (lj - li), n1);
+      else ev = zscale(0.5, r);
+      c = sqrt(zabs2(ev));
+      if (!(c <= 1.7976931348623157e308)) c = INFINITY;
+    }
+    E[e] = ev;
+    if (Xout) Xout[e] = i == j ? zmk(1.0 + ev.x, ev.y) : ev;
+  }
+  // block max (non-negative values: max of the bit patterns)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c = fmax(c, __shfl_xor(c, off, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); q++) m = fmax(m, red[q]);
+    atomicMax(corr, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// rank of each value (ties by index) and the sorted values
+__global__ void k_rank_values(const double* lam, int64_t k, int* rank, double* w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const double di = lam[i];
+  int r = 0;
+  for (int64_t j = 0; j < k; j++) {
+    const double dj = lam[j];
+    if (dj < di || (dj == di && j < i)) r++;
+  }
+  rank[i] = r;
+  w[r] = di;
+}
+
+// --------------------------------------------------------------------------
 // Lanczos pieces
 // --------------------------------------------------------------------------
 constexpr int MV_SPLITS = 32;
@@ -1030,6 +1119,17 @@ void jacobi_norms(const zc* G, int64_t k, double* part, double* out, hipStream_t
 
 void jacobi_sort(const zc* G, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz, hipStream_t st) {
   LAUNCH(k_jacobi_rank, grid1(k), dim3(NT), 0, st, G, k, rank, w);
+  LAUNCH(k_jacobi_permute, grid1(k * k), dim3(NT), 0, st, Z, k, rank, Zout, ldz);
+}
+
+void refine_coeffs(const zc* S, const zc* P, int64_t k, double tau, zc* E, zc* Xout, double* lam,
+                   unsigned long long* corr, hipStream_t st) {
+  LAUNCH(k_refine_coeffs, grid1(k * k), dim3(NT), 0, st, S, P, k, tau, E, Xout, lam, corr);
+}
+
+void sort_by_values(const double* lam, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz,
+                    hipStream_t st) {
+  LAUNCH(k_rank_values, grid1(k), dim3(NT), 0, st, lam, k, rank, w);
   LAUNCH(k_jacobi_permute, grid1(k * k), dim3(NT), 0, st, Z, k, rank, Zout, ldz);
 }
 

@@ -80,6 +80,16 @@ void jacobi_sparse_round(zc* G, zc* Z, int64_t k, const int* pairs, int np, cons
                          const double* fro2, double tau, int* rotated, hipStream_t st);
 size_t jacobi_rot_bytes();
 
+// ---- Eigenvector refinement for nearly diagonal Hermitian k x k -------------
+// One step's coefficients E (k x k) from S = X^H G X and P = X^H X (P null:
+// X = I, then also Xout = I + E); lam = Rayleigh quotients; *corr (zeroed by
+// the caller) = max off-diagonal |E| as double bits.
+void refine_coeffs(const zc* S, const zc* P, int64_t k, double tau, zc* E, zc* Xout, double* lam,
+                   unsigned long long* corr, hipStream_t st);
+// w ascending = lam sorted; Zout (ld ldz) = Z's columns in that order
+void sort_by_values(const double* lam, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz,
+                    hipStream_t st);
+
 // ---- Lanczos pieces ---------------------------------------------------------
 // y = A x (A n x n, lda); part: work of JMV_SPLITS * n
 void zgemv(const zc* A, int64_t lda, int64_t n, const zc* x, zc* y, zc* part, hipStream_t st);

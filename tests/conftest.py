@@ -23,3 +23,10 @@ def gpu():
     from paper_1305_5120_amd import chfsi
     chfsi.load()  # raises if the HIP library is absent
     return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="session")
+def lib(gpu):
+    """The Python binding of the HIP library (loaded by the gpu fixture)."""
+    from paper_1305_5120_amd import chfsi
+    return chfsi

@@ -88,3 +88,27 @@ def test_solve_argument_validation_without_device_work():
         assert lib.chfsi_zgemm(h, 2, 0, 1, 1, 1, 1.0, fake, 1, fake, 1, 0.0, None, 1, 0.0, None, 1, fake, 1, 0) == -1
     finally:
         lib.chfsi_release(h)
+
+
+def test_batch_create_and_solve_validation_without_device_work():
+    """Batch creation rejects bad member counts, sizes and tile shapes before
+    any device call; a null batch is rejected by every entry point."""
+    lib = chfsi.load()
+    chfsi._load_batch(lib)
+    h = ctypes.c_void_p()
+    o = chfsi.default_opts()
+    sizes = (ctypes.c_int64 * 2)(64, 80)
+    assert lib.chfsi_batch_create(None, 2, sizes, ctypes.byref(o), 0) == -1
+    assert lib.chfsi_batch_create(ctypes.byref(h), 0, sizes, ctypes.byref(o), 0) == -1
+    assert lib.chfsi_batch_create(ctypes.byref(h), 2, None, ctypes.byref(o), 0) == -1
+    assert lib.chfsi_batch_create(ctypes.byref(h), 2, sizes, ctypes.byref(o), 2) == -1
+    bad = (ctypes.c_int64 * 2)(64, 0)
+    assert lib.chfsi_batch_create(ctypes.byref(h), 2, bad, ctypes.byref(o), 0) == -1
+    o6 = chfsi.default_opts(filter_tile=6)  # 128 x 128 has no grouped kernel
+    assert lib.chfsi_batch_create(ctypes.byref(h), 2, sizes, ctypes.byref(o6), 0) == -1
+    assert not h.value
+    assert lib.chfsi_batch_solve(None, None, None, None, None, None, None, 1e-10, None, None, None, None, None,
+                                 None) == -1
+    assert lib.chfsi_batch_reset(None) == -1
+    assert lib.chfsi_batch_last_error(None) == b"null batch"
+    lib.chfsi_batch_release(None)

@@ -78,12 +78,6 @@ def test_server_results_same_alone_and_in_the_mix(lib, sequences):
         assert info_a["warm_start"] == (1 if ell > 0 else 0)
 
 
-@pytest.fixture(scope="module")
-def lib(gpu):
-    from paper_1305_5120_amd import chfsi
-    return chfsi
-
-
 def test_server_admits_within_budget(lib, sequences):
     # room for about one context at a time: requests are serialized, peak
     # memory stays under the budget, every request still completes
