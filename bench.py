@@ -206,10 +206,14 @@ def run_precision(args):
             if i >= args.warmup:
                 times.append(time.perf_counter() - t0)
         res[prec] = dict(t=sum(times) / len(times), info=info, err=_exact_errors(p, ev),
-                         res=residual_check(p, ev, X))
+                         res=residual_check(p, ev, X),
+                         phases={k: info[k] for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid")})
         log(f"[bench] precision {prec}: {res[prec]['t']:.3f} s/solve, {info['iterations']} iterations "
             f"({info['iterations_fp32']} FP32), max eigenvalue error {res[prec]['err']:.2e}, "
-            f"residual {res[prec]['res']:.2e}")
+            f"residual {res[prec]['res']:.2e}; phases " +
+            ", ".join(f"{k[2:]} {info[k]:.2f}" for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid")) +
+            f"; filter kernels FP64 {info['filter_kernel_seconds'] - info['filter_kernel_seconds_fp32']:.2f} s, "
+            f"FP32 {info['filter_kernel_seconds_fp32']:.2f} s")
         ctx.release()
     i64, i32 = res[0]["info"], res[1]["info"]
     f32 = i32["filter_flops_fp32"] / i32["filter_kernel_seconds_fp32"] / 1e12 if i32["filter_kernel_seconds_fp32"] else None
@@ -220,10 +224,11 @@ def run_precision(args):
                  "nex": nex, "degree": m, "tol": 1e-10, "precision": "mixed", "warm_start": False})
     out.update({"fp64_solves_per_s": 1.0 / res[0]["t"], "speedup_vs_fp64": res[0]["t"] / res[1]["t"],
                 "fp64": {"iterations": i64["iterations"], "max_eig_error_rel": res[0]["err"],
-                         "max_rel_residual": res[0]["res"], "filter_tflops": f64},
+                         "max_rel_residual": res[0]["res"], "filter_tflops": f64, "phase_seconds": res[0]["phases"]},
                 "mixed": {"iterations": i32["iterations"], "iterations_fp32": i32["iterations_fp32"],
                           "max_eig_error_rel": res[1]["err"], "max_rel_residual": res[1]["res"],
-                          "filter_tflops_fp32": f32},
+                          "filter_tflops_fp32": f32, "phase_seconds": res[1]["phases"],
+                          "filter_flops_fp32_share": i32["filter_flops_fp32"] / i32["filter_flops"]},
                 "roofline": {"bound": "mfma", "achieved": f32, "peak": 157.3, "unit": "TFLOP/s",
                              "frac": f32 / 157.3 if f32 else None, "traffic": None}})
     print(json.dumps(out), flush=True)
@@ -270,7 +275,8 @@ def run_batch(args):
         H, S = step_inputs(ell)
         ev, X, infos, st, rep = b.solve(H, S, nevs, nexs, tol=1e-10)
         reps.append(rep)
-        log(f"[bench] batch step {ell}: {rep['seconds']:.2f} s, {rep['outer_iterations']} outer iterations")
+        log(f"[bench] batch step {ell}: {rep['seconds']:.2f} s, {rep['outer_iterations']} outer iterations, "
+            f"grouped filter {rep['filter_seconds']:.2f} s ({rep['filter_flops'] / max(rep['filter_seconds'], 1e-9) / 1e12:.1f} TFLOP/s)")
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     worst = max(residual_check({"H": seqs[i][steps - 1]["H"], "S": seqs[i][0]["S"]}, ev[i], X[i])
@@ -284,12 +290,15 @@ def run_batch(args):
         chfsi.solve(ctxs[i], H[i], S[i], nevs[i], nexs[i], tol=1e-10, want_vectors=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    seq_filter = 0.0
     for ell in range(1, steps):
         H, S = step_inputs(ell)
         for i in range(G):
-            chfsi.solve(ctxs[i], H[i], S[i], nevs[i], nexs[i], tol=1e-10)
+            _, _, inf, _ = chfsi.solve(ctxs[i], H[i], S[i], nevs[i], nexs[i], tol=1e-10)
+            seq_filter += inf["t_filter"]
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
+    log(f"[bench] one after another: {ts:.2f} s for {G * (steps - 1)} solves, filter phases {seq_filter:.2f} s")
     for c in ctxs:
         c.release()
     solves = G * (steps - 1)
@@ -376,10 +385,7 @@ def run_warmcold(args):
         E = torch.complex(torch.randn(n, n, generator=gen, dtype=torch.float64),
                           torch.randn(n, n, generator=gen, dtype=torch.float64)).to("cuda") / math.sqrt(2)
         Ls.append(Ls[-1] + 1e-4 * torch.tril(E, -1) / math.sqrt(n))
-    A_of = [seq[0]["A"]]
-    Linv0 = torch.linalg.inv(seq[0]["L"])
-    for ell in range(1, steps):
-        A_of.append(Linv0 @ seq[ell]["H"] @ Linv0.conj().T)
+    A_of = [p["A"] for p in seq]
     Hs_v = [(L @ A @ L.conj().T) for L, A in zip(Ls, A_of)]
     Hs_v = [((h + h.conj().T) / 2).mT.contiguous().mT for h in Hs_v]
     Ss_v = [((L @ L.conj().T + (L @ L.conj().T).conj().T) / 2).mT.contiguous().mT for L in Ls]
@@ -440,7 +446,7 @@ def main():
                     choices=sorted(WORKLOADS) + ["precision", "batch", "serve", "warmcold"])
     ap.add_argument("--members", type=int, default=16, help="sequences (batch / serve forms)")
     ap.add_argument("--seq-steps", type=int, default=3, help="problems per sequence (batch / serve / warmcold)")
-    ap.add_argument("--rate", type=float, default=6.0, help="Poisson arrival rate per second (serve form)")
+    ap.add_argument("--rate", type=float, default=1.5, help="Poisson arrival rate per second (serve form)")
     ap.add_argument("--workers", type=int, default=4, help="serving workers")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving device-memory budget")
     ap.add_argument("--wc-n", type=int, default=4000, help="problem size of the warm/cold study")

@@ -120,11 +120,11 @@ struct chfsi_ctx_s {
   double warm_a0 = 0, warm_a = 0;
 
   // filter timing and work, per precision (0 FP64, 1 FP32)
-  std::vector<EventPair> fev;
+  std::vector<EventPair> fev[2];  // per precision
   double filt_kernel_s[2] = {0, 0};
   int filt_launches[2] = {0, 0};
   double filt_flops[2] = {0, 0};
-  int last_filter_prec = 0;
+  bool filt_pending[2] = {false, false};  // events recorded since the last collection
   void reset_filter_stats() {
     for (int i = 0; i < 2; i++) {
       filt_kernel_s[i] = 0;
@@ -228,11 +228,13 @@ struct chfsi_ctx_s {
       b->release();
     if (hbuf) (void)hipHostFree(hbuf);
     hbuf = nullptr;
-    for (auto& e : fev) {
-      if (e.a) (void)hipEventDestroy(e.a);
-      if (e.b) (void)hipEventDestroy(e.b);
+    for (auto& v : fev) {
+      for (auto& e : v) {
+        if (e.a) (void)hipEventDestroy(e.a);
+        if (e.b) (void)hipEventDestroy(e.b);
+      }
+      v.clear();
     }
-    fev.clear();
   }
 
   // ------------------------------------------------------------------------
@@ -334,10 +336,13 @@ struct chfsi_ctx_s {
       jacobi_small(Gp, ldg, k, w, Zo, ldz, Ztmp.z(), nullptr, st, tau);
       return;
     }
-    // Larger k: sweeps of the parallel (round-robin) ordering while the
-    // matrix is far from diagonal; once few couplings remain significant
-    // (|g|^2 > 1e-34 ||G||_F^2), sparse sweeps rotate only those pairs,
-    // grouped into disjoint rounds.
+    // Larger k.  Each pass: if the matrix is nearly diagonal, refinement
+    // finishes (refine); else, if the pairs that block the refinement (a
+    // coupling above REF_ETA times the gap of their diagonal entries) are
+    // few, a sparse sweep rotates only those; else a sparse sweep over all
+    // significant couplings (|g|^2 > 1e-34 ||G||_F^2) when they are few, or
+    // a dense sweep of the parallel (round-robin) ordering.  Sparse sweeps
+    // group their pairs into disjoint rounds.
     zc *g0 = G2.z(), *z0 = Ztmp.z(), *g1 = Z2.z();
     zc* z1 = Wz.z();  // Wz (n x k) doubles as the second Z buffer
     jacobi_init(Gp, ldg, k, g0, z0, st);
@@ -355,10 +360,11 @@ struct chfsi_ctx_s {
     int* offsets = counts + k;
     int* pairs = offsets + k;
     int* rounds_d = pairs + 2 * max_sparse;
-    for (int sweep = 0; sweep < 100; sweep++) {
-      // once the matrix is close to diagonal, refinement finishes the job
-      if (refine(g0, sweep > 0 ? z0 : nullptr, k, w, Zo, ldz, tau)) return;
-      jacobi_count(g0, k, nr + 1, THR, tau, counts, st);
+    // One sparse sweep over the pairs selected by (thr, ratio); returns the
+    // number of selected pairs, or -1 (nothing applied) when they are too
+    // many or cannot be packed into max_rounds disjoint rounds.
+    auto sparse_sweep = [&](double ratio) -> int64_t {
+      jacobi_count(g0, k, nr + 1, THR, tau, ratio, counts, st);
       CHFSI_HIP(hipMemcpyAsync(hbuf, counts, k * sizeof(int), hipMemcpyDeviceToHost, st));
       sync();
       const int* hc = reinterpret_cast<const int*>(hbuf);
@@ -368,64 +374,61 @@ struct chfsi_ctx_s {
         off[j] = (int)total;
         total += hc[j];
       }
-      if (total == 0) break;
-      bool sparse = total > 0 && total <= max_sparse;
+      if (total == 0) return 0;
+      if (total > max_sparse) return -1;
+      std::memcpy(hbuf, off.data(), k * sizeof(int));
+      CHFSI_HIP(hipMemcpyAsync(offsets, hbuf, k * sizeof(int), hipMemcpyHostToDevice, st));
+      jacobi_list(g0, k, nr + 1, THR, tau, ratio, offsets, pairs, st);
+      CHFSI_HIP(hipMemcpyAsync(hbuf, pairs, 2 * total * sizeof(int), hipMemcpyDeviceToHost, st));
+      sync();
+      const int* hp = reinterpret_cast<const int*>(hbuf);
+      // greedy assignment of each pair to the first round where both of its
+      // indices are free
       std::vector<std::vector<int>> rounds;
-      if (sparse) {
-        std::memcpy(hbuf, off.data(), k * sizeof(int));
-        CHFSI_HIP(hipMemcpyAsync(offsets, hbuf, k * sizeof(int), hipMemcpyHostToDevice, st));
-        jacobi_list(g0, k, nr + 1, THR, tau, offsets, pairs, st);
-        CHFSI_HIP(hipMemcpyAsync(hbuf, pairs, 2 * total * sizeof(int), hipMemcpyDeviceToHost, st));
-        sync();
-        const int* hp = reinterpret_cast<const int*>(hbuf);
-        // greedy assignment of each pair to the first round where both of its
-        // indices are free
-        std::vector<uint64_t> busy((size_t)k, 0);
-        for (int64_t t = 0; t < total && sparse; t++) {
-          const int p = hp[2 * t], q = hp[2 * t + 1];
-          const uint64_t free_mask = ~(busy[p] | busy[q]);
-          if (!free_mask) {
-            sparse = false;
-            break;
-          }
-          const int r = __builtin_ctzll(free_mask);
-          if (r >= max_rounds) {
-            sparse = false;
-            break;
-          }
-          if ((int)rounds.size() <= r) rounds.resize(r + 1);
-          rounds[r].push_back(p);
-          rounds[r].push_back(q);
-          busy[p] |= (1ull << r);
-          busy[q] |= (1ull << r);
-        }
+      std::vector<uint64_t> busy((size_t)k, 0);
+      for (int64_t t = 0; t < total; t++) {
+        const int p = hp[2 * t], q = hp[2 * t + 1];
+        const uint64_t free_mask = ~(busy[p] | busy[q]);
+        if (!free_mask) return -1;
+        const int r = __builtin_ctzll(free_mask);
+        if (r >= max_rounds) return -1;
+        if ((int)rounds.size() <= r) rounds.resize(r + 1);
+        rounds[r].push_back(p);
+        rounds[r].push_back(q);
+        busy[p] |= (1ull << r);
+        busy[q] |= (1ull << r);
       }
-      if (sparse) {
-        // device layout per round: pairs (2 np ints), then pair index per row (k ints)
-        int* hr = reinterpret_cast<int*>(hbuf);
-        size_t pos = 0;
-        std::vector<size_t> start(rounds.size());
-        for (size_t r = 0; r < rounds.size(); r++) {
-          start[r] = pos;
-          std::memcpy(hr + pos, rounds[r].data(), rounds[r].size() * sizeof(int));
-          pos += rounds[r].size();
-          int* po = hr + pos;
-          for (int64_t i = 0; i < k; i++) po[i] = -1;
-          for (size_t a = 0; a < rounds[r].size() / 2; a++) {
-            po[rounds[r][2 * a]] = (int)a;
-            po[rounds[r][2 * a + 1]] = (int)a;
-          }
-          pos += k;
+      // device layout per round: pairs (2 np ints), then pair index per row (k ints)
+      int* hr = reinterpret_cast<int*>(hbuf);
+      size_t pos = 0;
+      std::vector<size_t> start(rounds.size());
+      for (size_t r = 0; r < rounds.size(); r++) {
+        start[r] = pos;
+        std::memcpy(hr + pos, rounds[r].data(), rounds[r].size() * sizeof(int));
+        pos += rounds[r].size();
+        int* po = hr + pos;
+        for (int64_t i = 0; i < k; i++) po[i] = -1;
+        for (size_t a = 0; a < rounds[r].size() / 2; a++) {
+          po[rounds[r][2 * a]] = (int)a;
+          po[rounds[r][2 * a + 1]] = (int)a;
         }
-        CHFSI_HIP(hipMemcpyAsync(rounds_d, hr, pos * sizeof(int), hipMemcpyHostToDevice, st));
-        fill_i32(flags.i() + 1, 1, 0, st);
-        for (size_t r = 0; r < rounds.size(); r++) {
-          const int np = (int)(rounds[r].size() / 2);
-          const int* pr = rounds_d + start[r];
-          jacobi_sparse_round(g0, z0, k, pr, np, pr + 2 * np, jrot.p, nr + 1, tau, flags.i() + 1, st);
-        }
-        continue;
+        pos += k;
       }
+      CHFSI_HIP(hipMemcpyAsync(rounds_d, hr, pos * sizeof(int), hipMemcpyHostToDevice, st));
+      fill_i32(flags.i() + 1, 1, 0, st);
+      for (size_t r = 0; r < rounds.size(); r++) {
+        const int np = (int)(rounds[r].size() / 2);
+        const int* pr = rounds_d + start[r];
+        jacobi_sparse_round(g0, z0, k, pr, np, pr + 2 * np, jrot.p, nr + 1, tau, flags.i() + 1, st);
+      }
+      return total;
+    };
+    for (int sweep = 0; sweep < 100; sweep++) {
+      if (refine(g0, sweep > 0 ? z0 : nullptr, k, w, Zo, ldz, tau)) return;
+      if (sparse_sweep(REF_ETA) > 0) continue;  // strong couplings only
+      const int64_t total = sparse_sweep(0.0);
+      if (total == 0) break;
+      if (total > 0) continue;
       // dense sweep
       fill_i32(flags.i() + 1, 1, 0, st);
       for (int64_t r = 0; r < K2 - 1; r++) {
@@ -441,12 +444,16 @@ struct chfsi_ctx_s {
   // iterative refinement of X = I (refine_coeffs).  Zpre (nullable, k x k)
   // holds rotations already applied to the caller's matrix; the result is
   // Zpre X.  Returns false, with w and Zo untouched, when some coupled pair's
-  // correction exceeds ETA (the matrix is not close enough to diagonal for
-  // the iteration to converge fast) or the corrections do not fall below
-  // DONE within MAX_STEPS steps; the caller then continues with Jacobi.
+  // first correction exceeds ETA (the matrix is not close enough to diagonal
+  // for the iteration to converge fast), a later one exceeds GROW, or the
+  // corrections do not fall below DONE within MAX_STEPS steps; the caller
+  // then continues with Jacobi.  The corrections shrink quadratically
+  // (e.g. 0.2, 9e-3, 7e-4, 1e-6, 1e-13), so after a step whose largest
+  // correction is below DONE the remaining error is at rounding level.
+  static constexpr double REF_ETA = 0.25;
   bool refine(const zc* Gm, const zc* Zpre, int64_t k, double* w, zc* Zo, int64_t ldz, double tau) {
-    const double ETA = 0.02, DONE = 1e-10;
-    const int MAX_STEPS = 8;
+    const double ETA = REF_ETA, GROW = 0.5, DONE = 1e-8;
+    const int MAX_STEPS = 10;
     const int64_t kk = k * k;
     zc* X = rf.z();
     zc* Xn = X + kk;
@@ -480,7 +487,7 @@ struct chfsi_ctx_s {
       gemm(OP_N, OP_N, k, k, k, 1.0, X, k, Eb, k, Xn, k, 1.0, X, k);  // X + X E
       std::swap(X, Xn);
       c = read_corr();
-      if (!(c <= ETA)) return false;
+      if (!(c <= GROW)) return false;
     }
     const zc* Zf = X;
     if (Zpre) {
@@ -573,17 +580,18 @@ struct chfsi_ctx_s {
   void* filter_any(int prec, const void* Ap, int64_t lda, void* Yp, int64_t ldy, void* Ybp, int64_t ldyb, int64_t ka, int m,
                    double a, double b, double a0) {
     const bool prof = opts.profile != 0;
-    if (prof && (int)fev.size() < m) {
-      for (int i = (int)fev.size(); i < m; i++) {
+    std::vector<EventPair>& ev = fev[prec];
+    if (prof && (int)ev.size() < m) {
+      for (int i = (int)ev.size(); i < m; i++) {
         EventPair ep;
         CHFSI_HIP(hipEventCreate(&ep.a));
         CHFSI_HIP(hipEventCreate(&ep.b));
-        fev.push_back(ep);
+        ev.push_back(ep);
       }
     }
     auto step = [&](int i, const void* cur, int64_t ldc, void* out, int64_t ldo, double al, double be, double ga,
                     const void* prev, int64_t ldp) {
-      if (prof) CHFSI_HIP(hipEventRecord(fev[i].a, st));
+      if (prof) CHFSI_HIP(hipEventRecord(ev[i].a, st));
       GemmOp g;
       g.prec = prec;
       g.M = n; g.N = ka; g.K = n;
@@ -594,7 +602,7 @@ struct chfsi_ctx_s {
       g.cfg = opts.filter_tile;
       g.splitk = opts.filter_splitk;
       zgemm(g, gw(), st);
-      if (prof) CHFSI_HIP(hipEventRecord(fev[i].b, st));
+      if (prof) CHFSI_HIP(hipEventRecord(ev[i].b, st));
     };
     const std::vector<ChebStep> cs = cheb_schedule(m, a, b, a0);
     // Y_1 = (sigma1/e)(A - cI) Y_0
@@ -609,16 +617,21 @@ struct chfsi_ctx_s {
     }
     filt_launches[prec] += m;
     filt_flops[prec] += 8.0 * (double)n * (double)n * (double)ka * (double)m;
-    last_filter_prec = prec;
+    if (prof) filt_pending[prec] = true;
     return cur;
   }
 
+  // Add the event times of the filters run since the last call (the
+  // stream must have passed them).
   void collect_filter_events(int m) {
-    if (!opts.profile) return;
-    for (int i = 0; i < m && i < (int)fev.size(); i++) {
-      float ms = 0.f;
-      CHFSI_HIP(hipEventElapsedTime(&ms, fev[i].a, fev[i].b));
-      filt_kernel_s[last_filter_prec] += ms * 1e-3;
+    for (int p = 0; p < 2; p++) {
+      if (!filt_pending[p]) continue;
+      for (int i = 0; i < m && i < (int)fev[p].size(); i++) {
+        float ms = 0.f;
+        CHFSI_HIP(hipEventElapsedTime(&ms, fev[p][i].a, fev[p][i].b));
+        filt_kernel_s[p] += ms * 1e-3;
+      }
+      filt_pending[p] = false;
     }
   }
 
@@ -759,21 +772,29 @@ struct SolveState {
   bool converged = false, done = false, mixed = false;
   std::vector<double> lam, rho_lock;
   std::vector<hipEvent_t> ev;
-  // mixed-precision bookkeeping
-  int64_t fp64_col = -1, prev_col = -1;
-  double prev_rho = INFINITY;
-  bool prev32 = false, use32 = false;
+  // mixed precision: this iteration's leading active columns filtered in
+  // FP64 (the rest in FP32), the columns below fp64_upto that stay FP64,
+  // the last residual of every column, and the first active column's
+  // previous residual for the stall test
+  int64_t split = 0, fp64_upto = 0;
+  std::vector<double> rho_last;
+  int64_t prev_first = -1;
+  double prev_first_rho = INFINITY;
+  bool prev_first32 = false;
 
   ~SolveState() {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
 
-// Mixed precision: the filter runs in complex FP32 while the first active
-// column's generalized residual is above MIXED_SWITCH * h_H and still
-// falling at least twofold per FP32 iteration; that column then gets FP64
-// filtering until it locks.  Everything else stays FP64, and locking uses
-// the FP64 residuals, so the accepted pairs meet the same tolerance.
+// Mixed precision, per column: the FP64 filter takes the leading active
+// columns whose generalized residuals have all reached MIXED_SWITCH * h_H
+// (two orders above where FP32 rounding in the filter would hold them); the
+// columns after the first one still above it are filtered in complex FP32.
+// The FP64 range only grows (a column stays FP64 until it locks), and the
+// first active column also turns FP64 if an FP32 iteration fails to halve
+// its residual.  QR, Rayleigh-Ritz, residuals and locking stay FP64, so
+// accepted pairs meet the same tolerance.
 constexpr double MIXED_SWITCH = 1e-5;
 
 double secs_since(std::chrono::steady_clock::time_point a) {
@@ -870,6 +891,7 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
   c->warm_valid = false;  // the block is being rewritten
   s.lam.assign(k, NAN);
   s.rho_lock.assign(k, 0.0);
+  s.rho_last.assign(k, INFINITY);
   s.cl = 0;
   s.it = 0;
   s.hs = s.tol * inf.h_H;
@@ -877,20 +899,19 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
   for (auto& e : s.ev) CHFSI_HIP(hipEventCreate(&e));
 }
 
-// Whether this iteration's filter runs in FP32 (mixed precision only).
-bool solve_wants_fp32(const SolveState& s) {
-  if (!s.mixed) return false;
-  if (s.fp64_col == s.cl) return false;
-  if (s.prev_col == s.cl && s.prev_rho <= MIXED_SWITCH * s.inf.h_H) return false;
-  return true;
-}
-
-// Host side of an outer iteration's start: count it and fix the precision
-// of its filter.
+// Host side of an outer iteration's start: count it and fix the split of
+// the active columns between the FP64 and FP32 filters.
 void solve_filter_begin(SolveState& s) {
   s.it++;
-  s.use32 = solve_wants_fp32(s);
-  if (s.mixed && !s.use32 && s.fp64_col != s.cl && s.prev_col == s.cl) s.fp64_col = s.cl;
+  const int64_t ka = s.k - s.cl;
+  if (!s.mixed) {
+    s.split = ka;
+    return;
+  }
+  int64_t j = std::max(s.cl, s.fp64_upto);
+  while (j < s.k && s.rho_last[j] <= MIXED_SWITCH * s.inf.h_H) j++;
+  s.fp64_upto = j;
+  s.split = std::min(ka, std::max<int64_t>(0, s.fp64_upto - s.cl));
 }
 
 // The filter of the active columns, result into F(:, cl:k).
@@ -901,16 +922,18 @@ void solve_filter(chfsi_ctx c, SolveState& s) {
   CHFSI_HIP(hipEventRecord(s.ev[0], st));
   zc* Y = c->Y.z();
   zc* F = c->F.z();
-  if (s.use32) {
+  const int64_t p = s.split, c32 = s.cl + p;
+  if (p > 0) {
+    zc* res = c->filter(c->A.z(), n, Y + s.cl * n, n, c->Yb.z() + s.cl * n, n, p, c->opts.degree, s.a, s.b, s.a0);
+    copy2d(res, n, F + s.cl * n, n, n, p, st);
+  }
+  if (p < ka) {
     cc* y32 = (cc*)c->Y32.p;
     cc* y32b = (cc*)c->Y32b.p;
-    to_f32(Y + s.cl * n, n, y32, n, n, ka, st);
-    void* r32 = c->filter_any(PREC_F32, c->A32.p, n, y32, n, y32b, n, ka, c->opts.degree, s.a, s.b, s.a0);
-    to_f64((const cc*)r32, n, F + s.cl * n, n, n, ka, st);
+    to_f32(Y + c32 * n, n, y32, n, n, ka - p, st);
+    void* r32 = c->filter_any(PREC_F32, c->A32.p, n, y32, n, y32b, n, ka - p, c->opts.degree, s.a, s.b, s.a0);
+    to_f64((const cc*)r32, n, F + c32 * n, n, n, ka - p, st);
     s.inf.iterations_fp32++;
-  } else {
-    zc* res = c->filter(c->A.z(), n, Y + s.cl * n, n, c->Yb.z() + s.cl * n, n, ka, c->opts.degree, s.a, s.b, s.a0);
-    copy2d(res, n, F + s.cl * n, n, n, ka, st);
   }
   CHFSI_HIP(hipEventRecord(s.ev[1], st));
 }
@@ -959,11 +982,13 @@ void solve_post(chfsi_ctx c, SolveState& s) {
     s.rho_lock[cl + j] = rho[j];
   }
   if (s.mixed) {
-    // stall of an FP32 iteration on the same first column
-    if (s.prev32 && s.prev_col == cl && rho[0] > 0.5 * s.prev_rho) s.fp64_col = cl;
-    s.prev32 = s.use32;
-    s.prev_col = cl + nl;
-    s.prev_rho = nl < ka ? rho[nl] : INFINITY;
+    for (int64_t j = 0; j < ka; j++) s.rho_last[cl + j] = rho[j];
+    // an FP32 iteration that did not halve the first column's residual
+    if (s.prev_first32 && s.prev_first == cl && rho[0] > 0.5 * s.prev_first_rho)
+      s.fp64_upto = std::max(s.fp64_upto, cl + 1);
+    s.prev_first = cl + nl;
+    s.prev_first_rho = nl < ka ? rho[nl] : INFINITY;
+    s.prev_first32 = nl < ka && nl >= s.split;  // that column's filter ran in FP32
   }
   s.cl += nl;
   s.a = mu[ka - 1];
@@ -1290,7 +1315,7 @@ struct chfsi_batch_s {
   hipEvent_t gt[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   // per precision: step parameters (degree x count, step-major) and tile
   // prefixes (count + 1) on the device, with pinned staging
-  DBuf gp[2], t0[2];
+  DBuf gp[2], t0[2], ctr[2];  // ctr: 8 tile counters per degree step, zeroed before the steps
   ZGemmParams* hgp[2] = {nullptr, nullptr};
   int64_t* ht0[2] = {nullptr, nullptr};
   // online tile choice: chosen configuration (0 while trying), next trial,
@@ -1314,6 +1339,7 @@ struct chfsi_batch_s {
       ht0[p] = nullptr;
       gp[p].release();
       t0[p].release();
+      ctr[p].release();
       for (int q = 0; q < 2; q++)
         if (gt[p][q]) (void)hipEventDestroy(gt[p][q]);
     }
@@ -1341,7 +1367,10 @@ struct chfsi_batch_s {
   void launch_steps(int prec, int c, int m) {
     const ZGemmParams* g = static_cast<const ZGemmParams*>(gp[prec].p);
     const int64_t* t = static_cast<const int64_t*>(t0[prec].p);
-    for (int i = 0; i < m; i++) zgemm_grouped_filter_step(prec, c, g + (int64_t)i * count, t, count, grid_of(prec, c), gst);
+    int* cn = ctr[prec].i();
+    fill_i32(cn, (int64_t)8 * m, 0, gst);  // a kernel, so it can sit in a captured graph
+    for (int i = 0; i < m; i++)
+      zgemm_grouped_filter_step(prec, c, g + (int64_t)i * count, t, count, cn + 8 * i, grid_of(prec, c), gst);
   }
 
   void capture(int prec, int c, int m) {
@@ -1375,7 +1404,7 @@ struct BatchMember {
   int status = CHFSI_OK;
   std::string err;
   bool active = false;     // taking part in the current iteration
-  double iter_flops = 0;   // its filter flops in the current iteration
+  double iter_flops[2] = {0, 0};  // its filter flops per precision in the current iteration
 };
 
 void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, const void* const* S,
@@ -1448,27 +1477,40 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
   });
 
   for (int it = 0;; it++) {
-    std::vector<int> act[2];
+    // active members; act[p]: those with columns filtered in precision p
+    // (FP64: the leading `split` active columns, FP32: the rest)
+    std::vector<int> all, act[2];
     for (int j = 0; j < G; j++) {
       mb[j]->active = !mb[j]->s.done;
       if (!mb[j]->active) continue;
-      solve_filter_begin(mb[j]->s);
-      act[mb[j]->s.use32 ? 1 : 0].push_back(j);
+      SolveState& s = mb[j]->s;
+      solve_filter_begin(s);
+      all.push_back(j);
+      if (s.split > 0) act[0].push_back(j);
+      if (s.split < s.k - s.cl) act[1].push_back(j);
     }
-    if (act[0].empty() && act[1].empty()) break;
+    if (all.empty()) break;
     rep.outer_iterations++;
+    // first column and width of member j's range in precision p
+    auto range = [&](int j, int p, int64_t& c0, int64_t& w) {
+      const SolveState& s = mb[j]->s;
+      c0 = p ? s.cl + s.split : s.cl;
+      w = p ? s.k - s.cl - s.split : s.split;
+    };
 
     // members' blocks ready for the grouped steps
-    for (int p = 0; p < 2; p++)
-      for (int j : act[p]) {
-        chfsi_ctx c = b->mem[j];
-        SolveState& s = mb[j]->s;
-        const int64_t n = c->n, ka = s.k - s.cl;
-        CHFSI_HIP(hipEventRecord(s.ev[0], c->st));
-        if (p == 1) to_f32(c->Y.z() + s.cl * n, n, (cc*)c->Y32.p, n, n, ka, c->st);
-        CHFSI_HIP(hipEventRecord(b->ready[j], c->st));
-        CHFSI_HIP(hipStreamWaitEvent(b->gst, b->ready[j], 0));
-      }
+    for (int j : all) {
+      chfsi_ctx c = b->mem[j];
+      SolveState& s = mb[j]->s;
+      const int64_t n = c->n;
+      int64_t c32, w32;
+      range(j, 1, c32, w32);
+      CHFSI_HIP(hipEventRecord(s.ev[0], c->st));
+      if (w32 > 0) to_f32(c->Y.z() + c32 * n, n, (cc*)c->Y32.p, n, n, w32, c->st);
+      CHFSI_HIP(hipEventRecord(b->ready[j], c->st));
+      CHFSI_HIP(hipStreamWaitEvent(b->gst, b->ready[j], 0));
+      mb[j]->iter_flops[0] = mb[j]->iter_flops[1] = 0.0;
+    }
 
     double flops[2] = {0, 0};
     int used_cfg[2] = {0, 0};
@@ -1488,16 +1530,18 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
         if (on[j]) {
           chfsi_ctx c = b->mem[j];
           const SolveState& s = mb[j]->s;
-          const int64_t n = c->n, ka = s.k - s.cl;
-          const int64_t tm = cdiv(n, (int64_t)bm), tn = cdiv(ka, (int64_t)bn);
+          const int64_t n = c->n;
+          int64_t c0, w;
+          range(j, p, c0, w);
+          const int64_t tm = cdiv(n, (int64_t)bm), tn = cdiv(w, (int64_t)bn);
           tiles = tm * tn;
-          char* y0 = p ? (char*)c->Y32.p : (char*)(c->Y.z() + s.cl * n);
-          char* y1 = p ? (char*)c->Y32b.p : (char*)(c->Yb.z() + s.cl * n);
+          char* y0 = p ? (char*)c->Y32.p : (char*)(c->Y.z() + c0 * n);
+          char* y1 = p ? (char*)c->Y32b.p : (char*)(c->Yb.z() + c0 * n);
           const std::vector<ChebStep> cs = cheb_schedule(m, s.a, s.b, s.a0);
           void *cur = y0, *out = y1;
           for (int i = 0; i < m; i++) {
             ZGemmParams q{};
-            q.M = n; q.N = ka; q.K = n;
+            q.M = n; q.N = w; q.K = n;
             q.A = p ? c->A32.p : (const void*)c->A.z(); q.lda = n;
             q.B = cur; q.ldb = n;
             q.C = out; q.ldc = n;
@@ -1509,10 +1553,11 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
             hp[(int64_t)i * G + j] = q;
             std::swap(cur, out);
           }
-          mb[j]->iter_flops = 8.0 * (double)n * (double)n * (double)ka * (double)m;
-          flops[p] += mb[j]->iter_flops;
+          const double f = 8.0 * (double)n * (double)n * (double)w * (double)m;
+          mb[j]->iter_flops[p] = f;
+          flops[p] += f;
           c->filt_launches[p] += m;
-          c->filt_flops[p] += mb[j]->iter_flops;
+          c->filt_flops[p] += f;
         } else {
           for (int i = 0; i < m; i++) hp[(int64_t)i * G + j] = ZGemmParams{};
         }
@@ -1535,25 +1580,25 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
     CHFSI_HIP(hipEventRecord(b->gdone, b->gst));
 
     // results into F(:, cl:k), then each member's QR / Rayleigh-Ritz / locking
-    for (int p = 0; p < 2; p++)
-      for (int j : act[p]) {
-        chfsi_ctx c = b->mem[j];
-        SolveState& s = mb[j]->s;
-        const int64_t n = c->n, ka = s.k - s.cl;
-        CHFSI_HIP(hipStreamWaitEvent(c->st, b->gdone, 0));
-        zc* F = c->F.z() + s.cl * n;
-        if (p == 1) {
-          const cc* r = (const cc*)((m & 1) ? c->Y32b.p : c->Y32.p);
-          to_f64(r, n, F, n, n, ka, c->st);
-          s.inf.iterations_fp32++;
-        } else {
-          const zc* r = (m & 1) ? c->Yb.z() + s.cl * n : c->Y.z() + s.cl * n;
-          copy2d(r, n, F, n, n, ka, c->st);
-        }
-        CHFSI_HIP(hipEventRecord(s.ev[1], c->st));
+    for (int j : all) {
+      chfsi_ctx c = b->mem[j];
+      SolveState& s = mb[j]->s;
+      const int64_t n = c->n;
+      CHFSI_HIP(hipStreamWaitEvent(c->st, b->gdone, 0));
+      int64_t c0, w;
+      range(j, 0, c0, w);
+      if (w > 0) {
+        const zc* r = (m & 1) ? c->Yb.z() + c0 * n : c->Y.z() + c0 * n;
+        copy2d(r, n, c->F.z() + c0 * n, n, n, w, c->st);
       }
-    std::vector<int> all(act[0]);
-    all.insert(all.end(), act[1].begin(), act[1].end());
+      range(j, 1, c0, w);
+      if (w > 0) {
+        const cc* r = (const cc*)((m & 1) ? c->Y32b.p : c->Y32.p);
+        to_f64(r, n, c->F.z() + c0 * n, n, n, w, c->st);
+        s.inf.iterations_fp32++;
+      }
+      CHFSI_HIP(hipEventRecord(s.ev[1], c->st));
+    }
     for_members((int)all.size(), b->threads, b->device, [&](int q) {
       const int j = all[q];
       member_guard(j, [&] { solve_post(b->mem[j], mb[j]->s); });
@@ -1570,7 +1615,7 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
       rep.filter_flops += flops[p];
       // members' share of the launch time, in proportion to their flops
       for (int j : act[p])
-        if (flops[p] > 0) b->mem[j]->filt_kernel_s[p] += sec * mb[j]->iter_flops / flops[p];
+        if (flops[p] > 0) b->mem[j]->filt_kernel_s[p] += sec * mb[j]->iter_flops[p] / flops[p];
       if (!b->cfg[p]) {
         const int cf = used_cfg[p];
         if (sec > 0) b->rate[p][cf] = flops[p] / sec * 1e-12;
@@ -2098,6 +2143,7 @@ chfsi_status chfsi_batch_create(chfsi_batch* out, int32_t count, const int64_t* 
     for (int p = 0; p < 2; p++) {
       b->gp[p].ensure(m * count * sizeof(ZGemmParams));
       b->t0[p].ensure((size_t)(count + 1) * sizeof(int64_t));
+      b->ctr[p].ensure((size_t)8 * m * sizeof(int));
       CHFSI_HIP(hipHostMalloc((void**)&b->hgp[p], m * count * sizeof(ZGemmParams), hipHostMallocDefault));
       CHFSI_HIP(hipHostMalloc((void**)&b->ht0[p], (size_t)(count + 1) * sizeof(int64_t), hipHostMallocDefault));
     }

@@ -75,10 +75,11 @@ int zgemm_num_configs();
 int zgemm_tile_shape(int cfg, int* bm, int* bn);
 // One grouped filter step over G problems in precision prec: gp (device, G
 // params with M, N, K, pointers, scalars and tiles_m / tiles_n filled,
-// splitk = 1, kchunk = K), tile0 (device, G + 1 prefix of tiles_m * tiles_n).
+// splitk = 1, kchunk = K), tile0 (device, G + 1 prefix of tiles_m * tiles_n),
+// ctr (device, 8 ints, zero at launch: the XCDs' tile counters).
 // Persistent grid of `grid` workgroups (multiple of 8).
-void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const int64_t* tile0, int G, int grid,
-                               hipStream_t st);
+void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const int64_t* tile0, int G, int* ctr,
+                               int grid, hipStream_t st);
 // Whether cfg can run the grouped step; the grid that fills the device with it.
 bool zgemm_grouped_config_ok(int cfg);
 int zgemm_grouped_grid(int prec, int cfg);

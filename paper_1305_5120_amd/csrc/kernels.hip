@@ -678,29 +678,54 @@ __global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout,
 
 // ---- sparse sweeps: only the pairs whose coupling is significant ----------
 // counts[j] = #{ i > j : |G(i, j)|^2 > thr_factor * fro2 }
-__global__ void k_jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau2, int* counts) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= k) return;
-  const double thr = fmax(thr_factor * fro2[0], tau2);
-  int c = 0;
-  for (int64_t i = j + 1; i < k; i++)
-    if (zabs2(G[i + j * k]) > thr) c++;
-  counts[j] = c;
+// Selected pairs (i, j), i > j, per column j: |G_ij|^2 above
+// max(thr_factor ||G||_F^2, tau^2) and, with ratio > 0, |G_ij| above ratio
+// times |G_ii - G_jj| (the couplings that keep the matrix from being nearly
+// diagonal).
+__device__ __forceinline__ bool jacobi_selected(const zc* G, int64_t k, int64_t i, int64_t j, double thr, double ratio) {
+  const double g2 = zabs2(G[i + j * k]);
+  if (!(g2 > thr)) return false;
+  if (ratio <= 0.0) return true;
+  const double d = G[i + i * k].x - G[j + j * k].x;
+  return g2 > ratio * ratio * d * d;
 }
 
-// pairs (j, i), i > j, of column j at offsets[j] (deterministic order)
-__global__ void k_jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau2,
-                              const int* offsets, int* pairs) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= k) return;
+// One wave (64 threads) per column j walks rows i > j in chunks of 64;
+// ballots give each selected pair its rank, so the list keeps the
+// ascending row order within a column.
+__global__ void __launch_bounds__(64) k_jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor,
+                                                     double tau2, double ratio, int* counts) {
+  const int64_t j = blockIdx.x;
+  const int lane = threadIdx.x;
   const double thr = fmax(thr_factor * fro2[0], tau2);
+  int c = 0;
+  for (int64_t i0 = j + 1; i0 < k; i0 += 64) {
+    const int64_t i = i0 + lane;
+    const bool sel = i < k && jacobi_selected(G, k, i, j, thr, ratio);
+    c += __popcll(__ballot(sel));
+  }
+  if (lane == 0) counts[j] = c;
+}
+
+// pairs (j, i), i > j, of column j at offsets[j] (ascending i)
+__global__ void __launch_bounds__(64) k_jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor,
+                                                    double tau2, double ratio, const int* offsets, int* pairs) {
+  const int64_t j = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double thr = fmax(thr_factor * fro2[0], tau2);
+  const unsigned long long below = (1ull << lane) - 1ull;
   int o = offsets[j];
-  for (int64_t i = j + 1; i < k; i++)
-    if (zabs2(G[i + j * k]) > thr) {
-      pairs[2 * o] = (int)j;
-      pairs[2 * o + 1] = (int)i;
-      o++;
+  for (int64_t i0 = j + 1; i0 < k; i0 += 64) {
+    const int64_t i = i0 + lane;
+    const bool sel = i < k && jacobi_selected(G, k, i, j, thr, ratio);
+    const unsigned long long m = __ballot(sel);
+    if (sel) {
+      const int pos = o + __popcll(m & below);
+      pairs[2 * pos] = (int)j;
+      pairs[2 * pos + 1] = (int)i;
     }
+    o += __popcll(m);
+  }
 }
 
 // rotation parameters of one round's disjoint pairs (read before any update)
@@ -1092,13 +1117,14 @@ void jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, i
          rotated);
 }
 
-void jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, int* counts, hipStream_t st) {
-  LAUNCH(k_jacobi_count, grid1(k, 64), dim3(64), 0, st, G, k, fro2, thr_factor, tau * tau, counts);
+void jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, double ratio, int* counts,
+                  hipStream_t st) {
+  LAUNCH(k_jacobi_count, dim3((unsigned)k), dim3(64), 0, st, G, k, fro2, thr_factor, tau * tau, ratio, counts);
 }
 
-void jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, const int* offsets,
-                 int* pairs, hipStream_t st) {
-  LAUNCH(k_jacobi_list, grid1(k, 64), dim3(64), 0, st, G, k, fro2, thr_factor, tau * tau, offsets, pairs);
+void jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, double ratio,
+                 const int* offsets, int* pairs, hipStream_t st) {
+  LAUNCH(k_jacobi_list, dim3((unsigned)k), dim3(64), 0, st, G, k, fro2, thr_factor, tau * tau, ratio, offsets, pairs);
 }
 
 void jacobi_sparse_round(zc* G, zc* Z, int64_t k, const int* pairs, int np, const int* pairof, void* prm_scratch,

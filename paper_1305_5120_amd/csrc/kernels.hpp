@@ -70,11 +70,13 @@ void jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, i
 // out[0] = sum |G_ij|^2 off the diagonal, out[1] = sum over all (two-stage)
 void jacobi_norms(const zc* G, int64_t k, double* part, double* out, hipStream_t st);
 void jacobi_sort(const zc* G, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz, hipStream_t st);
-// Sparse sweeps: count / list the pairs with |G(i,j)|^2 > thr_factor * fro2
-// (i > j, per column j), then apply one round of disjoint pairs in place.
-void jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, int* counts, hipStream_t st);
-void jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, const int* offsets,
-                 int* pairs, hipStream_t st);
+// Sparse sweeps: count / list the pairs with |G(i,j)|^2 > max(thr_factor *
+// fro2, tau^2) (i > j, per column j) and, when ratio > 0, |G(i,j)| > ratio *
+// |G(i,i) - G(j,j)|; then apply one round of disjoint pairs in place.
+void jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, double ratio, int* counts,
+                  hipStream_t st);
+void jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, double ratio,
+                 const int* offsets, int* pairs, hipStream_t st);
 // pairs: 2 np ints (p < q); pairof: k ints, the pair index of each row or -1
 void jacobi_sparse_round(zc* G, zc* Z, int64_t k, const int* pairs, int np, const int* pairof, void* prm_scratch,
                          const double* fro2, double tau, int* rotated, hipStream_t st);

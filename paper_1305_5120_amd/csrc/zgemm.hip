@@ -300,19 +300,32 @@ __global__ void __launch_bounds__(256, MINB) chebyshev_step_f32(ZGemmParams p) {
 // One degree step for a batch of problems of different sizes in one
 // persistent launch: gp[g] describes problem g's step (no split), tile0[g]
 // its first tile in the batch-wide tile range (tile0[G] = total; a problem
-// with no work this step has tile0[g] == tile0[g + 1]).  The grid is a fixed
-// multiple of 8 workgroups; workgroup i walks the tiles of XCD i % 8's
-// contiguous share, so the launch does not depend on the problems' sizes and
-// a captured graph of these launches stays valid while the active widths
-// shrink.
+// with no work this step has tile0[g] == tile0[g + 1]).  The tile range is
+// cut into blocks of GROUP_TILES consecutive tiles (tiles of one row panel
+// of A are consecutive) dealt round-robin to the 8 XCDs, so every XCD gets
+// a share of every problem (problems differ in K, so contiguous shares
+// would leave XCDs idle); within its XCD (workgroup i runs on XCD i % 8) a
+// workgroup takes the next tile of that XCD's sequence from a counter, so
+// workgroups that drew cheap tiles take more.  ctr (8 ints per launch) must
+// be zero at launch.  The grid is a fixed multiple of 8, so the launch does
+// not depend on the problems' sizes and a captured graph of these launches
+// stays valid while the active widths shrink.
+constexpr int GROUP_TILES = 16;
+
 template <class PT, int BM, int BN, int BK>
 __device__ __forceinline__ void grouped_body(const ZGemmParams* __restrict__ gp, const int64_t* __restrict__ tile0,
-                                             int G) {
+                                             int G, int* __restrict__ ctr) {
+  __shared__ int64_t next;
   const int64_t total = tile0[G];
-  const int64_t xcd = blockIdx.x % 8, slot = blockIdx.x / 8, nslot = gridDim.x / 8;
-  const int64_t chunk = (total + 7) / 8;
-  for (int64_t i = slot; i < chunk; i += nslot) {
-    const int64_t t = xcd * chunk + i;
+  const int xcd = blockIdx.x % 8;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const int64_t i = atomicAdd(ctr + xcd, 1);
+      next = ((i / GROUP_TILES) * 8 + xcd) * GROUP_TILES + i % GROUP_TILES;
+    }
+    __syncthreads();
+    const int64_t t = next;
+    __syncthreads();  // every thread has read `next` before it is rewritten
     if (t >= total) break;
     // last g with tile0[g] <= t (that problem has at least one tile)
     int lo = 0, hi = G - 1;
@@ -328,14 +341,16 @@ __device__ __forceinline__ void grouped_body(const ZGemmParams* __restrict__ gp,
 
 template <int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) chebyshev_step_grouped_f64(const ZGemmParams* __restrict__ gp,
-                                                                       const int64_t* __restrict__ tile0, int G) {
-  grouped_body<PF64, BM, BN, BK>(gp, tile0, G);
+                                                                       const int64_t* __restrict__ tile0, int G,
+                                                                       int* __restrict__ ctr) {
+  grouped_body<PF64, BM, BN, BK>(gp, tile0, G, ctr);
 }
 
 template <int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) chebyshev_step_grouped_f32(const ZGemmParams* __restrict__ gp,
-                                                                       const int64_t* __restrict__ tile0, int G) {
-  grouped_body<PF32, BM, BN, BK>(gp, tile0, G);
+                                                                       const int64_t* __restrict__ tile0, int G,
+                                                                       int* __restrict__ ctr) {
+  grouped_body<PF32, BM, BN, BK>(gp, tile0, G, ctr);
 }
 
 // Combine split-K partial tiles and apply the epilogue.
@@ -453,11 +468,11 @@ void launch_ops(int cfg, int opA, int opB, ZGemmParams& p, int batch, bool filte
 }
 
 template <int BM, int BN, int BK, int MINB>
-void launch_grouped(int prec, const ZGemmParams* gp, const int64_t* tile0, int G, int grid, hipStream_t st) {
+void launch_grouped(int prec, const ZGemmParams* gp, const int64_t* tile0, int G, int* ctr, int grid, hipStream_t st) {
   if (prec == PREC_F32)
-    hipLaunchKernelGGL((chebyshev_step_grouped_f32<BM, BN, BK, MINB>), dim3(grid), dim3(256), 0, st, gp, tile0, G);
+    hipLaunchKernelGGL((chebyshev_step_grouped_f32<BM, BN, BK, MINB>), dim3(grid), dim3(256), 0, st, gp, tile0, G, ctr);
   else
-    hipLaunchKernelGGL((chebyshev_step_grouped_f64<BM, BN, BK, MINB>), dim3(grid), dim3(256), 0, st, gp, tile0, G);
+    hipLaunchKernelGGL((chebyshev_step_grouped_f64<BM, BN, BK, MINB>), dim3(grid), dim3(256), 0, st, gp, tile0, G, ctr);
   CHFSI_CHECK_LAUNCH();
 }
 
@@ -503,17 +518,17 @@ int zgemm_grouped_grid(int prec, int cfg) {
   return std::max(8, grid / 8 * 8);
 }
 
-void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const int64_t* tile0, int G, int grid,
-                               hipStream_t st) {
+void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const int64_t* tile0, int G, int* ctr,
+                               int grid, hipStream_t st) {
   if (grid < 8 || grid % 8) throw Error(ST_EINVAL, "grouped filter: grid must be a positive multiple of 8");
-  if (G < 1) throw Error(ST_EINVAL, "grouped filter: no problems");
+  if (G < 1 || !ctr) throw Error(ST_EINVAL, "grouped filter: no problems or no counters");
   switch (cfg) {
-    case 1: launch_grouped<64, 64, 16, 2>(prec, gp, tile0, G, grid, st); break;
-    case 2: launch_grouped<32, 32, 16, 2>(prec, gp, tile0, G, grid, st); break;
-    case 3: launch_grouped<64, 64, 8, 2>(prec, gp, tile0, G, grid, st); break;
-    case 4: launch_grouped<128, 64, 8, 2>(prec, gp, tile0, G, grid, st); break;
-    case 5: launch_grouped<64, 128, 8, 2>(prec, gp, tile0, G, grid, st); break;
-    case 7: launch_grouped<64, 32, 16, 2>(prec, gp, tile0, G, grid, st); break;
+    case 1: launch_grouped<64, 64, 16, 2>(prec, gp, tile0, G, ctr, grid, st); break;
+    case 2: launch_grouped<32, 32, 16, 2>(prec, gp, tile0, G, ctr, grid, st); break;
+    case 3: launch_grouped<64, 64, 8, 2>(prec, gp, tile0, G, ctr, grid, st); break;
+    case 4: launch_grouped<128, 64, 8, 2>(prec, gp, tile0, G, ctr, grid, st); break;
+    case 5: launch_grouped<64, 128, 8, 2>(prec, gp, tile0, G, ctr, grid, st); break;
+    case 7: launch_grouped<64, 32, 16, 2>(prec, gp, tile0, G, ctr, grid, st); break;
     default: throw Error(ST_EINVAL, "grouped filter: bad tile configuration");
   }
 }
