@@ -63,11 +63,27 @@ def residual_check(p, evals, X):
     H, S = p["H"], p["S"]
     lam = torch.as_tensor(evals, dtype=torch.complex128, device=X.device)
     R = H @ X - (S @ X) * lam[None, :]
-    v = torch.ones(H.shape[0], dtype=torch.complex128, device=X.device)
-    for _ in range(30):
-        v = H @ v
-        v = v / torch.linalg.vector_norm(v)
-    hn = float(torch.linalg.vector_norm(H @ v))
+    # ||H||_2 from the Lanczos process of 40 steps (full re-orthogonalization),
+    # an estimate from below that is accurate to many digits
+    n = H.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(7)
+    v = torch.complex(torch.randn(n, generator=g, dtype=torch.float64),
+                      torch.randn(n, generator=g, dtype=torch.float64)).to(X.device)
+    V = [v / torch.linalg.vector_norm(v)]
+    alpha, beta = [], []
+    for j in range(min(40, n)):
+        w = H @ V[-1]
+        alpha.append(float(torch.vdot(V[-1], w).real))
+        for u in V:
+            w = w - torch.vdot(u, w) * u
+        b = float(torch.linalg.vector_norm(w))
+        if b == 0.0:
+            break
+        beta.append(b)
+        V.append(w / b)
+    import numpy as np
+    T = np.diag(alpha) + np.diag(beta[:len(alpha) - 1], 1) + np.diag(beta[:len(alpha) - 1], -1)
+    hn = float(np.abs(np.linalg.eigvalsh(T)).max())
     return float(torch.linalg.vector_norm(R, dim=0).max()) / hn
 
 

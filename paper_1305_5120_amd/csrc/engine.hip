@@ -789,13 +789,13 @@ struct SolveState {
 
 // Mixed precision, per column: the FP64 filter takes the leading active
 // columns whose generalized residuals have all reached MIXED_SWITCH * h_H
-// (two orders above where FP32 rounding in the filter would hold them); the
+// (an order above where FP32 rounding in the filter holds them); the
 // columns after the first one still above it are filtered in complex FP32.
 // The FP64 range only grows (a column stays FP64 until it locks), and the
 // first active column also turns FP64 if an FP32 iteration fails to halve
 // its residual.  QR, Rayleigh-Ritz, residuals and locking stay FP64, so
 // accepted pairs meet the same tolerance.
-constexpr double MIXED_SWITCH = 1e-5;
+constexpr double MIXED_SWITCH = 1e-6;
 
 double secs_since(std::chrono::steady_clock::time_point a) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();

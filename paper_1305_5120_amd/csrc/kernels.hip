@@ -138,105 +138,145 @@ __global__ void k_nonfinite(const zc* A, int64_t lda, int64_t n, int64_t k, int*
 }
 
 // --------------------------------------------------------------------------
-// Cholesky diagonal block (nb <= 64): right-looking factorization and the
-// inverse of the factor in one sweep over the columns, with the block held in
-// registers.  Thread (r, q) = (tid % 64, tid / 64) owns row r of columns
-// c = q + 4t (t < 16) of both the matrix being factored and of X = L^{-1}, so
-// wave q holds whole columns.  Step j: the wave owning column j takes the
-// pivot from lane j, scales the column and publishes it in LDS; after one
-// barrier every thread
-//   * updates its trailing entries  A(r, c) -= l(r, j) conj(l(c, j)),  c > j,
-//   * applies step j of the column-oriented forward substitution for L X = I:
-//     row j of X is divided by l(j, j) and l(r, j) times it is subtracted from
-//     rows r > j (lane j of each wave publishes its part of row j in LDS).
-// X(r, c) is zero for c > j until step c, and the trailing update only touches
-// c > j, so each thread has about 16 complex updates per step.
+// Cholesky diagonal block (nb <= 64) and the inverse of its factor, one
+// workgroup, the block in LDS (rows beyond nb padded with the identity).
+//
+// Factorization, right-looking in panels of CPW columns: wave 0 factors the
+// panel (lane r holds row r of it in registers; the pivot and the panel
+// entries a column update needs come from other lanes by readlane, the
+// pivot's inverse square root from the hardware estimate and two Newton
+// steps), then all waves apply the rank-CPW update to the trailing lower
+// triangle.  The sequential chain per pivot is a few register operations,
+// not a workgroup barrier.
+//
+// Inverse X = L^{-1} by recursive doubling: with X's diagonal blocks of size
+// s known, each pair of them gives the block below as -C^{-1} (B A^{-1}) for
+// L = [A 0; B C]; six levels s = 1, 2, ..., 32, each two small products
+// computed by all threads.
 // --------------------------------------------------------------------------
 constexpr int CNB = CHOL_NB;
+constexpr int CLD = CNB + 1;  // LDS row stride (complex); keeps 16-lane groups on distinct banks
+constexpr int CPW = 8;        // panel width
+
+__device__ __forceinline__ double lane_read(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
 
 __global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi,
                                                     int64_t j0, int nb, int* info) {
-  static_assert(CNB == 64, "one row per lane, four waves of columns");
-  __shared__ zc col[2][CNB];   // column j of L
-  __shared__ zc xrow[2][CNB];  // row j of X before its division by l(j, j)
+  static_assert(CNB == 64 && CNB % CPW == 0, "64 x 64 blocks, whole panels");
+  extern __shared__ zc smem[];
+  zc* S = smem;                // S[r * CLD + c]: the matrix, then L (lower triangle)
+  zc* X = smem + CNB * CLD;    // X[r * CLD + c]: L^{-1} (lower triangle)
+  zc* T = X + CNB * CLD;       // scratch of the inverse: up to CNB * CNB / 4 entries
   __shared__ int failed;
-  const int tid = threadIdx.x, r = tid & 63;
-  const int q = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index: uniform branches below
-  zc a[16], x[16];
+  const int tid = threadIdx.x;
+  const int r = tid & 63;
+  const int q = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
   for (int t = 0; t < 16; t++) {
     const int c = q + 4 * t;
-    a[t] = (r < nb && c < nb && r >= c) ? W[(j0 + r) + (j0 + c) * ldw] : zmk(0.0, 0.0);
-    x[t] = zmk(r == c ? 1.0 : 0.0, 0.0);
+    zc v = zmk(r == c ? 1.0 : 0.0, 0.0);
+    if (r < nb && c < nb) v = r >= c ? W[(j0 + r) + (j0 + c) * ldw] : zmk(0.0, 0.0);
+    S[r * CLD + c] = v;
+    X[r * CLD + c] = zmk(0.0, 0.0);
   }
   if (tid == 0) failed = -1;
   __syncthreads();
-  for (int j = 0; j < nb; j++) {
-    const int buf = j & 1, tj = j >> 2;
-    if (q == (j & 3)) {
-      zc v = zmk(0.0, 0.0);
+
+  for (int jb = 0; jb < CNB; jb += CPW) {
+    if (q == 0) {
+      zc p[CPW];
 #pragma unroll
-      for (int t = 0; t < 16; t++)
-        if (t == tj) v = a[t];
-      const double d = __shfl(v.x, j, 64);
-      if (!(d > 0.0)) {
-        if (r == 0) failed = j;
-      } else {
-        const double ljj = sqrt(d), inv = 1.0 / ljj;
-        const zc l = r > j ? zscale(inv, v) : (r == j ? zmk(ljj, 0.0) : zmk(0.0, 0.0));
+      for (int i = 0; i < CPW; i++) p[i] = S[r * CLD + jb + i];
+      int fail = -1;  // first column of the panel without a positive pivot (uniform)
 #pragma unroll
-        for (int t = 0; t < 16; t++)
-          if (t == tj) a[t] = l;
-        col[buf][r] = l;
+      for (int i = 0; i < CPW; i++) {
+        const int j = jb + i;
+        const double d = lane_read(p[i].x, j);
+        if (fail < 0 && !(d > 0.0)) fail = j;
+        if (fail < 0) {
+          double y = __builtin_amdgcn_rsq(d);
+          y = y * fma(-0.5 * d * y, y, 1.5);
+          y = y * fma(-0.5 * d * y, y, 1.5);
+          const double ljj = d * y;
+          p[i] = r > j ? zscale(y, p[i]) : (r == j ? zmk(ljj, 0.0) : zmk(0.0, 0.0));
+          if (r == j) X[j * CLD + j] = zmk(y, 0.0);  // X's diagonal: 1 / l(j, j)
+#pragma unroll
+          for (int ii = i + 1; ii < CPW; ii++) {
+            // p[ii] -= p[i] conj(l(jb + ii, j))
+            const double lx = lane_read(p[i].x, jb + ii), ly = lane_read(p[i].y, jb + ii);
+            p[ii] = zmk(fma(-p[i].x, lx, fma(-p[i].y, ly, p[ii].x)), fma(-p[i].y, lx, fma(p[i].x, ly, p[ii].y)));
+          }
+        }
       }
-    }
-    if (r == j) {
+      if (fail >= 0 && r == 0) failed = fail;
 #pragma unroll
-      for (int t = 0; t < 16; t++) xrow[buf][q + 4 * t] = x[t];
+      for (int i = 0; i < CPW; i++) S[r * CLD + jb + i] = p[i];
     }
     __syncthreads();
-    if (failed >= 0) break;  // uniform: read after the barrier
-    // every operand of this step first (broadcast LDS reads), then the updates
-    const zc lr = col[buf][r];
-    const double dinv = 1.0 / col[buf][j].x;
-    // slot t needs l(c, j) for c > j (trailing update) or X(j, c) for c <= j
-    zc o[16];
+    if (failed >= 0) break;
+    // trailing update: columns c >= jb + CPW, rows r >= c
+    zc lr[CPW];
+#pragma unroll
+    for (int i = 0; i < CPW; i++) lr[i] = S[r * CLD + jb + i];
 #pragma unroll
     for (int t = 0; t < 16; t++) {
       const int c = q + 4 * t;
-      o[t] = (c > j ? col[buf] : xrow[buf])[c];
-    }
-    // branch-free per lane: the slot's case is uniform over the wave, the
-    // row conditions are selects
+      if (c >= jb + CPW) {  // uniform over the wave
+        zc acc = S[r * CLD + c];
 #pragma unroll
-    for (int t = 0; t < 16; t++) {
-      const int c = q + 4 * t;
-      if (c > j) {
-        // a -= lr conj(o) on rows r >= c
-        const double ux = fma(-lr.x, o[t].x, fma(-lr.y, o[t].y, a[t].x));
-        const double uy = fma(-lr.y, o[t].x, fma(lr.x, o[t].y, a[t].y));
-        if (r >= c) a[t] = zmk(ux, uy);
-      } else {
-        const double vx = dinv * o[t].x, vy = dinv * o[t].y;
-        // rows below j: x -= lr v; row j: x = v
-        const double ux = fma(-lr.x, vx, fma(lr.y, vy, x[t].x));
-        const double uy = fma(-lr.x, vy, fma(-lr.y, vx, x[t].y));
-        x[t] = r == j ? zmk(vx, vy) : (r > j ? zmk(ux, uy) : x[t]);
+        for (int i = 0; i < CPW; i++) {
+          const zc lc = S[c * CLD + jb + i];
+          acc = zmk(fma(-lr[i].x, lc.x, fma(-lr[i].y, lc.y, acc.x)), fma(-lr[i].y, lc.x, fma(lr[i].x, lc.y, acc.y)));
+        }
+        if (r >= c) S[r * CLD + c] = acc;
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
   if (failed >= 0) {
     if (tid == 0) atomicMin(info, (int)(j0 + failed + 1));
     return;
   }
+  // L out (the matrix is final)
 #pragma unroll
   for (int t = 0; t < 16; t++) {
     const int c = q + 4 * t;
-    if (r < nb && c < nb) {
-      L[(j0 + r) + (j0 + c) * ldl] = r >= c ? a[t] : zmk(0.0, 0.0);
-      Linv[(j0 + r) + (j0 + c) * ldi] = r >= c ? x[t] : zmk(0.0, 0.0);
+    if (r < nb && c < nb) L[(j0 + r) + (j0 + c) * ldl] = r >= c ? S[r * CLD + c] : zmk(0.0, 0.0);
+  }
+  // inverse by recursive doubling
+  for (int sz = 1; sz < CNB; sz *= 2) {
+    const int per = sz * sz, total = (CNB / (2 * sz)) * per;
+    // T = B A^{-1} for every pair (B = L[o+sz.., o..], A^{-1} = X[o.., o..])
+    for (int e = tid; e < total; e += 256) {
+      const int pair = e / per, rem = e % per, i = rem / sz, j = rem % sz, o = 2 * sz * pair;
+      zc acc = zmk(0.0, 0.0);
+      for (int k = j; k < sz; k++) {
+        const zc bv = S[(o + sz + i) * CLD + o + k], av = X[(o + k) * CLD + o + j];
+        acc = zmk(fma(bv.x, av.x, fma(-bv.y, av.y, acc.x)), fma(bv.x, av.y, fma(bv.y, av.x, acc.y)));
+      }
+      T[e] = acc;
     }
+    __syncthreads();
+    // X[o+sz.., o..] = -C^{-1} T
+    for (int e = tid; e < total; e += 256) {
+      const int pair = e / per, rem = e % per, i = rem / sz, j = rem % sz, o = 2 * sz * pair;
+      zc acc = zmk(0.0, 0.0);
+      for (int k = 0; k <= i; k++) {
+        const zc cv = X[(o + sz + i) * CLD + o + sz + k], tv = T[pair * per + k * sz + j];
+        acc = zmk(fma(cv.x, tv.x, fma(-cv.y, tv.y, acc.x)), fma(cv.x, tv.y, fma(cv.y, tv.x, acc.y)));
+      }
+      X[(o + sz + i) * CLD + o + j] = zmk(-acc.x, -acc.y);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 16; t++) {
+    const int c = q + 4 * t;
+    if (r < nb && c < nb) Linv[(j0 + r) + (j0 + c) * ldi] = r >= c ? X[r * CLD + c] : zmk(0.0, 0.0);
   }
 }
 
@@ -1063,8 +1103,13 @@ void nonfinite_check(const zc* A, int64_t lda, int64_t n, int64_t k, int* flag, 
 
 void chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi, int64_t j0, int64_t nb, int* info,
                hipStream_t st) {
+  static std::once_flag attr;
+  const size_t shm = (size_t)(2 * CNB * CLD + CNB * CNB / 4) * sizeof(zc);
+  std::call_once(attr, [&] {
+    CHFSI_HIP(hipFuncSetAttribute((const void*)k_chol_diag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  });
   if (nb < 1 || nb > CNB) throw Error(ST_EINVAL, "chol_diag: block size out of range");
-  LAUNCH(k_chol_diag, dim3(1), dim3(256), 0, st, W, ldw, L, ldl, Linv, ldi, j0, (int)nb, info);
+  LAUNCH(k_chol_diag, dim3(1), dim3(256), shm, st, W, ldw, L, ldl, Linv, ldi, j0, (int)nb, info);
 }
 
 void hh_panel_setup(HHPanel& p) {

@@ -403,6 +403,8 @@ constexpr Cfg CFGS[] = {
     {64, 128, 8, 2, 1.05},    // 5
     {128, 128, 8, 1, 1.1},    // 6
     {64, 32, 16, 2, 0.8},     // 7
+    {64, 64, 8, 4, 1.0},      // 8: as 3 with room for four workgroups per CU
+    {64, 32, 16, 4, 0.8},     // 9: as 7 with room for four workgroups per CU
 };
 constexpr int NCFG = sizeof(CFGS) / sizeof(CFGS[0]);
 
@@ -436,6 +438,8 @@ void launch_f32(int cfg, ZGemmParams& p, int batch, hipStream_t st) {
     case 5: launch_one_f32<64, 128, 8, 2>(p, batch, st); break;
     case 6: launch_one_f32<128, 128, 8, 1>(p, batch, st); break;
     case 7: launch_one_f32<64, 32, 16, 2>(p, batch, st); break;
+    case 8: launch_one_f32<64, 64, 8, 4>(p, batch, st); break;
+    case 9: launch_one_f32<64, 32, 16, 4>(p, batch, st); break;
     default: throw Error(ST_EINVAL, "cgemm: bad tile configuration");
   }
 }
@@ -453,6 +457,8 @@ void launch_cfg(int cfg, ZGemmParams& p, int batch, bool filter_step, hipStream_
           case 4: launch_one<OPA, OPB, 128, 64, 8, 2>(p, batch, filter_step, st); return;
           case 5: launch_one<OPA, OPB, 64, 128, 8, 2>(p, batch, filter_step, st); return;
           case 6: launch_one<OPA, OPB, 128, 128, 8, 1>(p, batch, filter_step, st); return;
+          case 8: launch_one<OPA, OPB, 64, 64, 8, 4>(p, batch, filter_step, st); return;
+          case 9: launch_one<OPA, OPB, 64, 32, 16, 4>(p, batch, filter_step, st); return;
           default: break;
         }
       }
@@ -540,19 +546,26 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   const int batch = g.batch > 0 ? g.batch : 1;
   const bool nn = g.opA == OP_N && g.opB == OP_N;
   // Tall, deep products (the filter's A Y_i and the Rayleigh-Ritz A Q): rules
-  // read off a sweep of every configuration and split on MI355X (n = 4000 and
+  // read off sweeps of the configurations and splits on MI355X (n = 4000 and
   // 10000, k_a from 16 to 660).  The best choices keep each workgroup's K
   // range near 1000 (the A panels of the workgroups resident on one XCD then
-  // fit its 4 MB L2) and use the widest tile that still gives >= ~500
-  // workgroups.
+  // fit its 4 MB L2); in FP64 the 64 x 64 tile with room for four workgroups
+  // per CU leads from k_a = 256 up, the 64 x 32 tile between 160 and 256.
   if (nn && batch == 1 && g.M >= 1024 && g.K >= 1024 && !(g.flags & GEMM_OUT_LOWER)) {
     int c;
-    if (g.N >= 384) c = 3;        // 64 x 64 x 8
-    else if (g.N >= 160) c = 4;   // 128 x 64 x 8
-    else if (g.N >= 96) c = 5;    // 64 x 128 x 8
-    else c = 7;                   // 64 x 32 x 16
+    if (g.prec == PREC_F64) {
+      if (g.N >= 256) c = 8;        // 64 x 64 x 8, four workgroups per CU
+      else if (g.N >= 160) c = 7;   // 64 x 32 x 16
+      else if (g.N >= 96) c = 5;    // 64 x 128 x 8
+      else c = 7;
+    } else {
+      if (g.N >= 384) c = 3;
+      else if (g.N >= 160) c = 4;   // 128 x 64 x 8
+      else if (g.N >= 96) c = 5;
+      else c = 7;
+    }
     int sk = (int)std::min<int64_t>(8, std::max<int64_t>(1, (g.K + 500) / 1000));
-    if (g.N < 96) sk = 8;
+    if (g.N < 96 || (g.prec == PREC_F64 && g.N < 160)) sk = 8;
     // a triangular op(A) leaves the top row panels short: deeper splits
     // rebalance the workgroups
     if (g.flags & (GEMM_TRI_A_LOWER | GEMM_TRI_A_UPPER)) sk = std::min(16, 2 * sk);
