@@ -550,22 +550,30 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   // 10000, k_a from 16 to 660).  The best choices keep each workgroup's K
   // range near 1000 (the A panels of the workgroups resident on one XCD then
   // fit its 4 MB L2); in FP64 the 64 x 64 tile with room for four workgroups
-  // per CU leads from k_a = 256 up, the 64 x 32 tile between 160 and 256.
+  // per CU leads wherever N is close to a multiple of 64, the 64 x 32 tile
+  // elsewhere below N = 256 (the padding of the last column tile decides).
   if (nn && batch == 1 && g.M >= 1024 && g.K >= 1024 && !(g.flags & GEMM_OUT_LOWER)) {
     int c;
+    int sk = (int)std::min<int64_t>(8, std::max<int64_t>(1, (g.K + 500) / 1000));
     if (g.prec == PREC_F64) {
-      if (g.N >= 256) c = 8;        // 64 x 64 x 8, four workgroups per CU
-      else if (g.N >= 160) c = 7;   // 64 x 32 x 16
-      else if (g.N >= 96) c = 5;    // 64 x 128 x 8
-      else c = 7;
+      // 64-wide tiles unless they would pad N by more than 7 % (then the
+      // 32-wide tile); narrow blocks split K 8 ways
+      const double pad64 = (double)(cdiv(g.N, (int64_t)64) * 64) / (double)g.N;
+      if (g.N >= 256) {
+        c = 8;  // 64 x 64 x 8, four workgroups per CU
+      } else if (pad64 <= 1.07 || g.N < 56) {
+        c = 8;
+        sk = 8;
+      } else {
+        c = 7;  // 64 x 32 x 16
+      }
     } else {
       if (g.N >= 384) c = 3;
       else if (g.N >= 160) c = 4;   // 128 x 64 x 8
       else if (g.N >= 96) c = 5;
       else c = 7;
+      if (g.N < 96) sk = 8;
     }
-    int sk = (int)std::min<int64_t>(8, std::max<int64_t>(1, (g.K + 500) / 1000));
-    if (g.N < 96 || (g.prec == PREC_F64 && g.N < 160)) sk = 8;
     // a triangular op(A) leaves the top row panels short: deeper splits
     // rebalance the workgroups
     if (g.flags & (GEMM_TRI_A_LOWER | GEMM_TRI_A_UPPER)) sk = std::min(16, 2 * sk);

@@ -373,8 +373,11 @@ def test_solve_config0_matches_oracle(lib):
     p = workloads.make_problem(512, 0)
     ref = oracle.solve(p.H, p.S, 51, 13, tol=1e-10, degree=10, seed=0)
     ctx = lib.create(512, degree=10, seed=0)
-    ev, X, info, st = lib.solve(ctx, _t(p.H), _t(p.S), 51, 13, tol=1e-10)
+    Hd, Sd = _t(p.H), _t(p.S)
+    ev, X, info, st = lib.solve(ctx, Hd, Sd, 51, 13, tol=1e-10)
     assert st == 0 and info["converged"] >= 51
+    # the caller's matrices are read, never written
+    assert np.array_equal(_np(Hd), p.H) and np.array_equal(_np(Sd), p.S)
     assert np.abs(ev - ref["evals"]).max() <= 1e-12 * 100
     _check_solution(p, ev, _np(X), 51)
     assert info["b_upper"] >= p.lam.max()
