@@ -125,6 +125,7 @@ struct chfsi_ctx_s {
   int filt_launches[2] = {0, 0};
   double filt_flops[2] = {0, 0};
   bool filt_pending[2] = {false, false};  // events recorded since the last collection
+  int filt_first_product[2] = {0, 0};     // first degree step of the last filter that ran as a product
   void reset_filter_stats() {
     for (int i = 0; i < 2; i++) {
       filt_kernel_s[i] = 0;
@@ -571,14 +572,16 @@ struct chfsi_ctx_s {
   // Chebyshev filter on Y (n x ka); Yb same shape as work.  Returns the
   // buffer holding the result (Y or Yb).
   // ------------------------------------------------------------------------
+  // AY0 (optional, FP64): A Y_0 already at hand (the Rayleigh-Ritz step's
+  // W Z for the Ritz vectors in Y_0); the first step then needs no product.
   zc* filter(const zc* Ap, int64_t lda, zc* Yp, int64_t ldy, zc* Ybp, int64_t ldyb, int64_t ka, int m, double a, double b,
-             double a0) {
-    return static_cast<zc*>(filter_any(PREC_F64, Ap, lda, Yp, ldy, Ybp, ldyb, ka, m, a, b, a0));
+             double a0, const zc* AY0 = nullptr, int64_t lday = 0) {
+    return static_cast<zc*>(filter_any(PREC_F64, Ap, lda, Yp, ldy, Ybp, ldyb, ka, m, a, b, a0, AY0, lday));
   }
 
   // The filter in either precision: element type zc (FP64) or cc (FP32).
   void* filter_any(int prec, const void* Ap, int64_t lda, void* Yp, int64_t ldy, void* Ybp, int64_t ldyb, int64_t ka, int m,
-                   double a, double b, double a0) {
+                   double a, double b, double a0, const zc* AY0 = nullptr, int64_t lday = 0) {
     const bool prof = opts.profile != 0;
     std::vector<EventPair>& ev = fev[prec];
     if (prof && (int)ev.size() < m) {
@@ -606,7 +609,11 @@ struct chfsi_ctx_s {
     };
     const std::vector<ChebStep> cs = cheb_schedule(m, a, b, a0);
     // Y_1 = (sigma1/e)(A - cI) Y_0
-    step(0, Yp, ldy, Ybp, ldyb, cs[0].alpha, cs[0].beta, 0.0, nullptr, 0);
+    const bool reuse = AY0 && prec == PREC_F64;
+    if (reuse)
+      lincomb2d(cs[0].alpha, AY0, lday, cs[0].beta, static_cast<const zc*>(Yp), ldy, static_cast<zc*>(Ybp), ldyb, n, ka, st);
+    else
+      step(0, Yp, ldy, Ybp, ldyb, cs[0].alpha, cs[0].beta, 0.0, nullptr, 0);
     void *cur = Ybp, *prev = Yp;
     int64_t ldc = ldyb, ldp = ldy;
     for (int i = 1; i < m; i++) {
@@ -615,9 +622,11 @@ struct chfsi_ctx_s {
       std::swap(cur, prev);
       std::swap(ldc, ldp);
     }
-    filt_launches[prec] += m;
-    filt_flops[prec] += 8.0 * (double)n * (double)n * (double)ka * (double)m;
+    const int products = reuse ? m - 1 : m;
+    filt_launches[prec] += products;
+    filt_flops[prec] += 8.0 * (double)n * (double)n * (double)ka * (double)products;
     if (prof) filt_pending[prec] = true;
+    filt_first_product[prec] = reuse ? 1 : 0;
     return cur;
   }
 
@@ -626,7 +635,7 @@ struct chfsi_ctx_s {
   void collect_filter_events(int m) {
     for (int p = 0; p < 2; p++) {
       if (!filt_pending[p]) continue;
-      for (int i = 0; i < m && i < (int)fev[p].size(); i++) {
+      for (int i = filt_first_product[p]; i < m && i < (int)fev[p].size(); i++) {
         float ms = 0.f;
         CHFSI_HIP(hipEventElapsedTime(&ms, fev[p][i].a, fev[p][i].b));
         filt_kernel_s[p] += ms * 1e-3;
@@ -777,6 +786,8 @@ struct SolveState {
   // the last residual of every column, and the first active column's
   // previous residual for the stall test
   int64_t split = 0, fp64_upto = 0;
+  // first column whose A y is in Wz (the last Rayleigh-Ritz step's W Z), or -1
+  int64_t wz_first = -1;
   std::vector<double> rho_last;
   int64_t prev_first = -1;
   double prev_first_rho = INFINITY;
@@ -924,7 +935,9 @@ void solve_filter(chfsi_ctx c, SolveState& s) {
   zc* F = c->F.z();
   const int64_t p = s.split, c32 = s.cl + p;
   if (p > 0) {
-    zc* res = c->filter(c->A.z(), n, Y + s.cl * n, n, c->Yb.z() + s.cl * n, n, p, c->opts.degree, s.a, s.b, s.a0);
+    // A Y_0 of the active columns is the last Rayleigh-Ritz step's W Z
+    const zc* ay0 = s.wz_first >= 0 && s.cl >= s.wz_first ? c->Wz.z() + (s.cl - s.wz_first) * n : nullptr;
+    zc* res = c->filter(c->A.z(), n, Y + s.cl * n, n, c->Yb.z() + s.cl * n, n, p, c->opts.degree, s.a, s.b, s.a0, ay0, n);
     copy2d(res, n, F + s.cl * n, n, n, p, st);
   }
   if (p < ka) {
@@ -954,6 +967,7 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   c->rayleigh_ritz(c->A.z(), n, Qb + cl * n, n, ka, Y + cl * n, n, mu_d, c->Wk.z(), c->Wz.z(), 1e-3 * s.hs);
   CHFSI_HIP(hipEventRecord(s.ev[3], st));
   c->residual_norms(c->L.z(), n, c->Wz.z(), Y + cl * n, n, ka, mu_d, c->Wk.z(), F, rho_d);
+  s.wz_first = cl;  // Wz = A Y(:, cl:k) until the next Rayleigh-Ritz step
   double* hb = c->hbuf;
   CHFSI_HIP(hipMemcpyAsync(hb, mu_d, ka * sizeof(double), hipMemcpyDeviceToHost, st));
   CHFSI_HIP(hipMemcpyAsync(hb + ka, rho_d, ka * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -68,6 +68,16 @@ __global__ void k_copy2d(const zc* src, int64_t lds, zc* dst, int64_t ldd, int64
   dst[i + j * ldd] = src[i + j * lds];
 }
 
+// out = a X + b Y (real a, b; m x n blocks)
+__global__ void k_lincomb2d(double a, const zc* X, int64_t ldx, double b, const zc* Y, int64_t ldy, zc* out,
+                            int64_t ldo, int64_t m, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  const int64_t i = e % m, j = e / m;
+  const zc x = X[i + j * ldx], y = Y[i + j * ldy];
+  out[i + j * ldo] = zmk(fma(a, x.x, b * y.x), fma(a, x.y, b * y.y));
+}
+
 __global__ void k_z2c(const zc* src, int64_t lds, cc* dst, int64_t ldd, int64_t m, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * n) return;
@@ -1060,6 +1070,12 @@ void fill_i32(int* p, int64_t count, int v, hipStream_t st) {
 void copy2d(const zc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st) {
   if (m * n == 0) return;
   LAUNCH(k_copy2d, grid1(m * n), dim3(NT), 0, st, src, lds, dst, ldd, m, n);
+}
+
+void lincomb2d(double a, const zc* X, int64_t ldx, double b, const zc* Y, int64_t ldy, zc* out, int64_t ldo, int64_t m,
+               int64_t n, hipStream_t st) {
+  if (m * n == 0) return;
+  LAUNCH(k_lincomb2d, grid1(m * n), dim3(NT), 0, st, a, X, ldx, b, Y, ldy, out, ldo, m, n);
 }
 
 void to_f32(const zc* src, int64_t lds, cc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st) {

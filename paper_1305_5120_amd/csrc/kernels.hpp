@@ -15,6 +15,9 @@ void philox_raw(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t
 // ---- elementwise / layout --------------------------------------------------
 void fill_i32(int* p, int64_t count, int v, hipStream_t st);
 void copy2d(const zc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st);
+// out = a X + b Y (m x n, real a and b)
+void lincomb2d(double a, const zc* X, int64_t ldx, double b, const zc* Y, int64_t ldy, zc* out, int64_t ldo, int64_t m,
+               int64_t n, hipStream_t st);
 // precision conversions of an m x n block (round to nearest / exact widening)
 void to_f32(const zc* src, int64_t lds, cc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st);
 void to_f64(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st);
