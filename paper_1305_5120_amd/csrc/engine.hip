@@ -568,6 +568,37 @@ struct chfsi_ctx_s {
     return true;
   }
 
+  // Orthonormal basis of [Y_lock | F(:, cl:k)] with the locked columns
+  // Y_lock = Yl(:, :cl) (orthonormal) kept: two passes of block classical
+  // Gram-Schmidt of the active columns against Y_lock followed by CholeskyQR
+  // of the remainder -- CholeskyQR2 of the whole block with the locked
+  // block's Gram matrix and Cholesky factor (the identity) taken as known,
+  // so the factorization is k_a x k_a instead of k x k.  Result in
+  // Qo(:, cl:k).  When a Gram matrix is not positive definite, Householder
+  // QR of the whole block (F(:, :cl) gets Y_lock) writes all of Qo; returns
+  // true then.
+  bool orthonormalize_active(const zc* Yl, zc* Fp, int64_t cl, int64_t k, zc* Qo, int64_t ldq) {
+    const int64_t ka = k - cl;
+    if (opts.qr_mode == 0) {
+      zc* Fa = Fp + cl * n;
+      zc* mid = Wk.z();
+      zc* B = Z2.z();  // cl x ka coefficients (Z2 is free between the passes' factorizations)
+      auto project = [&](zc* X) {
+        if (cl == 0) return;
+        gemm(OP_C, OP_N, cl, ka, n, 1.0, Yl, n, X, n, B, cl);
+        gemm(OP_N, OP_N, n, ka, cl, -1.0, Yl, n, B, cl, X, n, 1.0, X, n);  // X -= Y_lock B
+      };
+      project(Fa);
+      if (cholqr_pass(Fa, n, ka, mid, n)) {
+        project(mid);
+        if (cholqr_pass(mid, n, ka, Qo + cl * ldq, ldq)) return false;
+      }
+    }
+    if (cl > 0) copy2d(Yl, n, Fp, n, n, cl, st);
+    qr(Fp, n, k, Qo, ldq);
+    return true;
+  }
+
   // ------------------------------------------------------------------------
   // Chebyshev filter on Y (n x ka); Yb same shape as work.  Returns the
   // buffer holding the result (Y or Yb).
@@ -961,8 +992,7 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   zc* Qb = c->Qb.z();
   double* mu_d = c->mu.d();
   double* rho_d = c->rho.d();
-  if (cl > 0) copy2d(Y, n, F, n, n, cl, st);
-  inf.qr_householder += c->orthonormalize(F, k, Qb, n) ? 1 : 0;
+  inf.qr_householder += c->orthonormalize_active(Y, F, cl, k, Qb, n) ? 1 : 0;
   CHFSI_HIP(hipEventRecord(s.ev[2], st));
   c->rayleigh_ritz(c->A.z(), n, Qb + cl * n, n, ka, Y + cl * n, n, mu_d, c->Wk.z(), c->Wz.z(), 1e-3 * s.hs);
   CHFSI_HIP(hipEventRecord(s.ev[3], st));
@@ -1328,7 +1358,7 @@ struct chfsi_batch_s {
   hipEvent_t gdone = nullptr;
   hipEvent_t gt[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   // per precision: step parameters (degree x count, step-major) and tile
-  // prefixes (count + 1) on the device, with pinned staging
+  // prefixes (degree x (count + 1)) on the device, with pinned staging
   DBuf gp[2], t0[2], ctr[2];  // ctr: 8 tile counters per degree step, zeroed before the steps
   ZGemmParams* hgp[2] = {nullptr, nullptr};
   int64_t* ht0[2] = {nullptr, nullptr};
@@ -1384,7 +1414,8 @@ struct chfsi_batch_s {
     int* cn = ctr[prec].i();
     fill_i32(cn, (int64_t)8 * m, 0, gst);  // a kernel, so it can sit in a captured graph
     for (int i = 0; i < m; i++)
-      zgemm_grouped_filter_step(prec, c, g + (int64_t)i * count, t, count, cn + 8 * i, grid_of(prec, c), gst);
+      zgemm_grouped_filter_step(prec, c, g + (int64_t)i * count, t + (int64_t)i * (count + 1), count, cn + 8 * i,
+                                grid_of(prec, c), gst);
   }
 
   void capture(int prec, int c, int m) {
@@ -1419,6 +1450,7 @@ struct BatchMember {
   std::string err;
   bool active = false;     // taking part in the current iteration
   double iter_flops[2] = {0, 0};  // its filter flops per precision in the current iteration
+  bool reuse = false;             // its FP64 first step came from W Z this iteration
 };
 
 void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, const void* const* S,
@@ -1521,6 +1553,13 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
       range(j, 1, c32, w32);
       CHFSI_HIP(hipEventRecord(s.ev[0], c->st));
       if (w32 > 0) to_f32(c->Y.z() + c32 * n, n, (cc*)c->Y32.p, n, n, w32, c->st);
+      // the FP64 range's first step from the last Rayleigh-Ritz product W Z = A Y
+      mb[j]->reuse = s.split > 0 && s.wz_first >= 0 && s.cl >= s.wz_first;
+      if (mb[j]->reuse) {
+        const ChebStep c0 = cheb_schedule(1, s.a, s.b, s.a0)[0];
+        lincomb2d(c0.alpha, c->Wz.z() + (s.cl - s.wz_first) * n, n, c0.beta, c->Y.z() + s.cl * n, n,
+                  c->Yb.z() + s.cl * n, n, n, s.split, c->st);
+      }
       CHFSI_HIP(hipEventRecord(b->ready[j], c->st));
       CHFSI_HIP(hipStreamWaitEvent(b->gst, b->ready[j], 0));
       mb[j]->iter_flops[0] = mb[j]->iter_flops[1] = 0.0;
@@ -1538,9 +1577,10 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
       int64_t* ht = b->ht0[p];
       std::vector<char> on(G, 0);
       for (int j : act[p]) on[j] = 1;
-      ht[0] = 0;
+      for (int i = 0; i < m; i++) ht[(int64_t)i * (G + 1)] = 0;
       for (int j = 0; j < G; j++) {
         int64_t tiles = 0;
+        bool skip0 = false;  // step 0 done without a product (reuse of W Z)
         if (on[j]) {
           chfsi_ctx c = b->mem[j];
           const SolveState& s = mb[j]->s;
@@ -1567,18 +1607,23 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
             hp[(int64_t)i * G + j] = q;
             std::swap(cur, out);
           }
-          const double f = 8.0 * (double)n * (double)n * (double)w * (double)m;
+          skip0 = p == 0 && mb[j]->reuse;
+          const int products = skip0 ? m - 1 : m;
+          const double f = 8.0 * (double)n * (double)n * (double)w * (double)products;
           mb[j]->iter_flops[p] = f;
           flops[p] += f;
-          c->filt_launches[p] += m;
+          c->filt_launches[p] += products;
           c->filt_flops[p] += f;
         } else {
           for (int i = 0; i < m; i++) hp[(int64_t)i * G + j] = ZGemmParams{};
         }
-        ht[j + 1] = ht[j] + tiles;
+        for (int i = 0; i < m; i++) {
+          int64_t* hi = ht + (int64_t)i * (G + 1);
+          hi[j + 1] = hi[j] + ((i == 0 && skip0) ? 0 : tiles);
+        }
       }
       CHFSI_HIP(hipMemcpyAsync(b->gp[p].p, hp, (size_t)m * G * sizeof(ZGemmParams), hipMemcpyHostToDevice, b->gst));
-      CHFSI_HIP(hipMemcpyAsync(b->t0[p].p, ht, (size_t)(G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->gst));
+      CHFSI_HIP(hipMemcpyAsync(b->t0[p].p, ht, (size_t)m * (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->gst));
       CHFSI_HIP(hipEventRecord(b->gt[p][0], b->gst));
       const bool graph = b->use_graph && b->cfg[p] != 0;
       if (graph) {
@@ -2156,10 +2201,10 @@ chfsi_status chfsi_batch_create(chfsi_batch* out, int32_t count, const int64_t* 
     const size_t m = (size_t)o.degree;
     for (int p = 0; p < 2; p++) {
       b->gp[p].ensure(m * count * sizeof(ZGemmParams));
-      b->t0[p].ensure((size_t)(count + 1) * sizeof(int64_t));
+      b->t0[p].ensure(m * (size_t)(count + 1) * sizeof(int64_t));
       b->ctr[p].ensure((size_t)8 * m * sizeof(int));
       CHFSI_HIP(hipHostMalloc((void**)&b->hgp[p], m * count * sizeof(ZGemmParams), hipHostMallocDefault));
-      CHFSI_HIP(hipHostMalloc((void**)&b->ht0[p], (size_t)(count + 1) * sizeof(int64_t), hipHostMallocDefault));
+      CHFSI_HIP(hipHostMalloc((void**)&b->ht0[p], m * (size_t)(count + 1) * sizeof(int64_t), hipHostMallocDefault));
     }
     if (o.filter_tile) b->cfg[0] = b->cfg[1] = o.filter_tile;
   } catch (const Error& e) {

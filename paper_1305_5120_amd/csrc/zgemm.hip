@@ -568,10 +568,7 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
         c = 7;  // 64 x 32 x 16
       }
     } else {
-      if (g.N >= 384) c = 3;
-      else if (g.N >= 160) c = 4;   // 128 x 64 x 8
-      else if (g.N >= 96) c = 5;
-      else c = 7;
+      c = 3;  // FP32: 64 x 64 x 8 at every width in the sweep (within 5 % of the best)
       if (g.N < 96) sk = 8;
     }
     // a triangular op(A) leaves the top row panels short: deeper splits
