@@ -156,10 +156,14 @@ def cpu_baseline(cfg, gpu_filter_flops_per_solve, target_seconds=12.0):
     oracle.chebyshev_filter(A, Y, m, lo, hi, float(lam.min()))
     dt = time.perf_counter() - t0
     rate = 8.0 * n * n * k * m / dt
-    # scale the sample (columns first, then degree) to about target_seconds
-    k2 = int(max(8, min(cfg["nev"] + cfg["nex"], rate * target_seconds / (8.0 * n * n * m))))
-    m2 = int(max(2, min(cfg["degree"], round(rate * target_seconds / (8.0 * n * n * k2)))))
-    if k2 > k or m2 > m:
+    # scale the sample (columns first, then degree) to about target_seconds;
+    # the rate grows with the column count, so rescale once more from the
+    # second measurement
+    for _ in range(2):
+        k2 = int(max(8, min(cfg["nev"] + cfg["nex"], rate * target_seconds / (8.0 * n * n * m))))
+        m2 = int(max(2, min(cfg["degree"], round(rate * target_seconds / (8.0 * n * n * k2)))))
+        if (k2 <= k and m2 <= m) or dt >= 0.5 * target_seconds:
+            break
         Y = oracle.gauss_block(1, 3, n, k2)
         t0 = time.perf_counter()
         oracle.chebyshev_filter(A, Y, m2, lo, hi, float(lam.min()))
