@@ -1360,8 +1360,10 @@ struct chfsi_batch_s {
   // per precision: step parameters (degree x count, step-major) and tile
   // prefixes (degree x (count + 1)) on the device, with pinned staging
   DBuf gp[2], t0[2], ctr[2];  // ctr: 8 tile counters per degree step, zeroed before the steps
+  DBuf e0[2];                 // per step, (count + 1) prefixes of the split members' elements
   ZGemmParams* hgp[2] = {nullptr, nullptr};
   int64_t* ht0[2] = {nullptr, nullptr};
+  int64_t* he0[2] = {nullptr, nullptr};
   // online tile choice: chosen configuration (0 while trying), next trial,
   // measured rates
   int cfg[2] = {0, 0};
@@ -1379,6 +1381,9 @@ struct chfsi_batch_s {
       gexec[p] = nullptr;
       if (hgp[p]) (void)hipHostFree(hgp[p]);
       if (ht0[p]) (void)hipHostFree(ht0[p]);
+      if (he0[p]) (void)hipHostFree(he0[p]);
+      he0[p] = nullptr;
+      e0[p].release();
       hgp[p] = nullptr;
       ht0[p] = nullptr;
       gp[p].release();
@@ -1413,9 +1418,13 @@ struct chfsi_batch_s {
     const int64_t* t = static_cast<const int64_t*>(t0[prec].p);
     int* cn = ctr[prec].i();
     fill_i32(cn, (int64_t)8 * m, 0, gst);  // a kernel, so it can sit in a captured graph
-    for (int i = 0; i < m; i++)
+    const int64_t* el = static_cast<const int64_t*>(e0[prec].p);
+    for (int i = 0; i < m; i++) {
       zgemm_grouped_filter_step(prec, c, g + (int64_t)i * count, t + (int64_t)i * (count + 1), count, cn + 8 * i,
                                 grid_of(prec, c), gst);
+      // split members' combination (no work when nothing was split)
+      zgemm_grouped_reduce(prec, g + (int64_t)i * count, el + (int64_t)i * (count + 1), count, 1024, gst);
+    }
   }
 
   void capture(int prec, int c, int m) {
@@ -1577,9 +1586,11 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
       int64_t* ht = b->ht0[p];
       std::vector<char> on(G, 0);
       for (int j : act[p]) on[j] = 1;
-      for (int i = 0; i < m; i++) ht[(int64_t)i * (G + 1)] = 0;
+      int64_t* he = b->he0[p];
+      for (int i = 0; i < m; i++) ht[(int64_t)i * (G + 1)] = he[(int64_t)i * (G + 1)] = 0;
+      const int bk = zgemm_config_bk(cf);
       for (int j = 0; j < G; j++) {
-        int64_t tiles = 0;
+        int64_t tiles = 0, elems = 0;
         bool skip0 = false;  // step 0 done without a product (reuse of W Z)
         if (on[j]) {
           chfsi_ctx c = b->mem[j];
@@ -1588,7 +1599,15 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
           int64_t c0, w;
           range(j, p, c0, w);
           const int64_t tm = cdiv(n, (int64_t)bm), tn = cdiv(w, (int64_t)bn);
-          tiles = tm * tn;
+          // K split as in single solves (chunks near 1000 deep), within the
+          // member's partial-tile buffer
+          int sk = (int)std::min<int64_t>(4, std::max<int64_t>(1, (n + 500) / 1000));
+          const size_t cap = c->P_elems * (p ? 2 : 1);
+          while (sk > 1 && ((size_t)sk * n * w > cap || n < (int64_t)sk * 4 * bk)) sk--;
+          const int64_t kchunk = cdiv(cdiv(n, (int64_t)sk), (int64_t)bk) * bk;
+          sk = (int)cdiv(n, kchunk);
+          tiles = tm * tn * sk;
+          elems = sk > 1 ? n * w : 0;
           char* y0 = p ? (char*)c->Y32.p : (char*)(c->Y.z() + c0 * n);
           char* y1 = p ? (char*)c->Y32b.p : (char*)(c->Yb.z() + c0 * n);
           const std::vector<ChebStep> cs = cheb_schedule(m, s.a, s.b, s.a0);
@@ -1602,7 +1621,7 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
             q.X = cur; q.ldx = n;
             q.Z = i ? out : nullptr; q.ldz = n;
             q.alpha = cs[i].alpha; q.beta = cs[i].beta; q.gamma = cs[i].gamma;
-            q.flags = 0; q.splitk = 1; q.kchunk = n; q.P = nullptr;
+            q.flags = 0; q.splitk = sk; q.kchunk = sk > 1 ? kchunk : n; q.P = sk > 1 ? c->P.p : nullptr;
             q.tiles_m = (int)tm; q.tiles_n = (int)tn;
             hp[(int64_t)i * G + j] = q;
             std::swap(cur, out);
@@ -1619,11 +1638,15 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
         }
         for (int i = 0; i < m; i++) {
           int64_t* hi = ht + (int64_t)i * (G + 1);
-          hi[j + 1] = hi[j] + ((i == 0 && skip0) ? 0 : tiles);
+          int64_t* hq = he + (int64_t)i * (G + 1);
+          const bool none = i == 0 && skip0;
+          hi[j + 1] = hi[j] + (none ? 0 : tiles);
+          hq[j + 1] = hq[j] + (none ? 0 : elems);
         }
       }
       CHFSI_HIP(hipMemcpyAsync(b->gp[p].p, hp, (size_t)m * G * sizeof(ZGemmParams), hipMemcpyHostToDevice, b->gst));
       CHFSI_HIP(hipMemcpyAsync(b->t0[p].p, ht, (size_t)m * (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->gst));
+      CHFSI_HIP(hipMemcpyAsync(b->e0[p].p, he, (size_t)m * (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->gst));
       CHFSI_HIP(hipEventRecord(b->gt[p][0], b->gst));
       const bool graph = b->use_graph && b->cfg[p] != 0;
       if (graph) {
@@ -2203,6 +2226,8 @@ chfsi_status chfsi_batch_create(chfsi_batch* out, int32_t count, const int64_t* 
       b->gp[p].ensure(m * count * sizeof(ZGemmParams));
       b->t0[p].ensure(m * (size_t)(count + 1) * sizeof(int64_t));
       b->ctr[p].ensure((size_t)8 * m * sizeof(int));
+      b->e0[p].ensure(m * (size_t)(count + 1) * sizeof(int64_t));
+      CHFSI_HIP(hipHostMalloc((void**)&b->he0[p], m * (size_t)(count + 1) * sizeof(int64_t), hipHostMallocDefault));
       CHFSI_HIP(hipHostMalloc((void**)&b->hgp[p], m * count * sizeof(ZGemmParams), hipHostMallocDefault));
       CHFSI_HIP(hipHostMalloc((void**)&b->ht0[p], m * (size_t)(count + 1) * sizeof(int64_t), hipHostMallocDefault));
     }

@@ -80,6 +80,14 @@ int zgemm_tile_shape(int cfg, int* bm, int* bn);
 // Persistent grid of `grid` workgroups (multiple of 8).
 void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const int64_t* tile0, int G, int* ctr,
                                int grid, hipStream_t st);
+// The split-K combination of one grouped step: elem0 (device, G + 1 prefix
+// of M * N over the problems whose params have splitk > 1, 0 elements for
+// the others); grid-stride launch of `grid` workgroups.  The problems' split
+// work items are counted in tile0 as tiles_m * tiles_n * splitk, with
+// kchunk the K range of one split.
+void zgemm_grouped_reduce(int prec, const ZGemmParams* gp, const int64_t* elem0, int G, int grid, hipStream_t st);
+// K slab depth of a tile configuration (0 if cfg is not one).
+int zgemm_config_bk(int cfg);
 // Whether cfg can run the grouped step; the grid that fills the device with it.
 bool zgemm_grouped_config_ok(int cfg);
 int zgemm_grouped_grid(int prec, int cfg);

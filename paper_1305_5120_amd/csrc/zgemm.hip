@@ -334,7 +334,14 @@ __device__ __forceinline__ void grouped_body(const ZGemmParams* __restrict__ gp,
       if (tile0[mid] <= t) lo = mid;
       else hi = mid - 1;
     }
-    zgemm_body<PT, OP_N, OP_N, BM, BN, BK>(gp[lo], t - tile0[lo], 0, 0);
+    // work item -> (row panel, K chunk, column tile): consecutive items share
+    // the A sub-panel of one row panel and K chunk
+    const ZGemmParams& p = gp[lo];
+    const int64_t w = t - tile0[lo];
+    const int64_t nt = w % p.tiles_n, rest = w / p.tiles_n;
+    const int split = (int)(rest % p.splitk);
+    const int64_t mt = rest / p.splitk;
+    zgemm_body<PT, OP_N, OP_N, BM, BN, BK>(p, mt * p.tiles_n + nt, 0, split);
     __syncthreads();  // LDS of this tile fully consumed before the next one
   }
 }
@@ -353,14 +360,12 @@ __global__ void __launch_bounds__(256, MINB) chebyshev_step_grouped_f32(const ZG
   grouped_body<PF32, BM, BN, BK>(gp, tile0, G, ctr);
 }
 
-// Combine split-K partial tiles and apply the epilogue.
+// Combine split-K partial tiles and apply the epilogue (element e of batch
+// entry `batch`).
 template <class PT>
-__device__ __forceinline__ void splitk_reduce_body(const ZGemmParams& p) {
+__device__ __forceinline__ void splitk_reduce_elem(const ZGemmParams& p, int64_t e, int batch) {
   using E = typename PT::E;
   using R = typename PT::R;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int batch = blockIdx.y;
-  if (e >= p.M * p.N) return;
   const int64_t m = e % p.M, n = e / p.M;
   const E* P = static_cast<const E*>(p.P) + (int64_t)batch * p.splitk * p.M * p.N;
   R re = 0, im = 0;
@@ -381,6 +386,41 @@ __device__ __forceinline__ void splitk_reduce_body(const ZGemmParams& p) {
     vy += (R)p.gamma * z.y;
   }
   static_cast<E*>(p.C)[(int64_t)batch * p.sC + m + n * p.ldc] = PT::mk(vx, vy);
+}
+
+template <class PT>
+__device__ __forceinline__ void splitk_reduce_body(const ZGemmParams& p) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p.M * p.N) return;
+  splitk_reduce_elem<PT>(p, e, blockIdx.y);
+}
+
+// The combination of a grouped step's split problems: elem0 is the
+// (G + 1)-prefix of the elements M * N of the problems that were split
+// (0 for the others); grid-stride over the total.
+template <class PT>
+__device__ __forceinline__ void grouped_reduce_body(const ZGemmParams* __restrict__ gp,
+                                                    const int64_t* __restrict__ elem0, int G) {
+  const int64_t total = elem0[G];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (elem0[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    splitk_reduce_elem<PT>(gp[lo], e - elem0[lo], 0);
+  }
+}
+
+__global__ void __launch_bounds__(256) chebyshev_step_grouped_reduce_f64(const ZGemmParams* __restrict__ gp,
+                                                                         const int64_t* __restrict__ elem0, int G) {
+  grouped_reduce_body<PF64>(gp, elem0, G);
+}
+
+__global__ void __launch_bounds__(256) chebyshev_step_grouped_reduce_f32(const ZGemmParams* __restrict__ gp,
+                                                                         const int64_t* __restrict__ elem0, int G) {
+  grouped_reduce_body<PF32>(gp, elem0, G);
 }
 
 __global__ void zgemm_splitk_reduce(ZGemmParams p) { splitk_reduce_body<PF64>(p); }
@@ -503,6 +543,17 @@ int zgemm_tile_shape(int cfg, int* bm, int* bn) {
   *bn = CFGS[cfg].bn;
   return 0;
 }
+
+void zgemm_grouped_reduce(int prec, const ZGemmParams* gp, const int64_t* elem0, int G, int grid, hipStream_t st) {
+  if (grid < 1 || G < 1) throw Error(ST_EINVAL, "grouped reduce: bad grid or no problems");
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(chebyshev_step_grouped_reduce_f32, dim3(grid), dim3(256), 0, st, gp, elem0, G);
+  else
+    hipLaunchKernelGGL(chebyshev_step_grouped_reduce_f64, dim3(grid), dim3(256), 0, st, gp, elem0, G);
+  CHFSI_CHECK_LAUNCH();
+}
+
+int zgemm_config_bk(int cfg) { return (cfg >= 1 && cfg < NCFG) ? CFGS[cfg].bk : 0; }
 
 bool zgemm_grouped_config_ok(int cfg) { return cfg == 1 || cfg == 2 || cfg == 3 || cfg == 4 || cfg == 5 || cfg == 7; }
 
