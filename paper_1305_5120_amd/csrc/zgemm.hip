@@ -86,8 +86,13 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
   using E = typename PT::E;
   using R = typename PT::R;
   using Acc = typename PT::Acc;
+  // B slabs are stored k-fastest (consecutive threads take consecutive k of
+  // one column, which keeps the global loads in contiguous runs); the row
+  // padding spreads the BK rows of a 16-lane (FP64) or 32-lane (FP32) store
+  // group over distinct LDS banks
+  constexpr int LDB = BN + (sizeof(E) == 16 ? (BK == 8 ? 2 : 1) : (BK == 8 ? 4 : 2));
   __shared__ E As[2][BK][T::LDA_S];
-  __shared__ E Bs[2][BK][T::LDB_S];
+  __shared__ E Bs[2][BK][LDB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
