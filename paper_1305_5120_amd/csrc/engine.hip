@@ -58,6 +58,13 @@ struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
+// Columns of split-K partial tiles a context keeps for a block of k columns
+// (times n elements): four splits of the whole block, and up to eight for
+// narrow blocks, where the filter's products split K eight ways.
+size_t splitk_columns(int64_t k) {
+  return std::max((size_t)4 * k, std::min((size_t)8 * k, (size_t)2560));
+}
+
 // Coefficients of the m degree steps of the scaled Chebyshev filter
 // (eq. (3) on (A - cI)/e, normalized at a0): step i computes
 //   Y_{i+1} = alpha_i A Y_i + beta_i Y_i + gamma_i Y_{i-1}   (gamma_0 = 0).
@@ -181,7 +188,8 @@ struct chfsi_ctx_s {
     mu.release(); mu.ensure((size_t)kk * sizeof(double));
     rho.release(); rho.ensure((size_t)kk * sizeof(double));
     rank.release(); rank.ensure((size_t)kk * sizeof(int));
-    P_elems = 8 * (size_t)kk * kk + (size_t)std::max(4, opts.filter_splitk) * n * kk + ((size_t)1 << 16);
+    P_elems = 8 * (size_t)kk * kk + (size_t)n * std::max((size_t)opts.filter_splitk * kk, splitk_columns(kk)) +
+              ((size_t)1 << 16);
     P.release();
     P.ensure(P_elems * sizeof(zc));
     const int64_t npan = cdiv(kk, HH_NB);
@@ -1144,7 +1152,8 @@ struct Worker {
 // Device bytes of a solver context for problems of size n with block k.
 size_t ctx_footprint(int64_t n, int64_t k, int precision) {
   size_t z = sizeof(zc);
-  size_t b = z * ((size_t)4 * n * n + (size_t)6 * n * k + (size_t)13 * k * k + (size_t)4 * n * k + (size_t)64 * n);
+  size_t b = z * ((size_t)4 * n * n + (size_t)6 * n * k + (size_t)13 * k * k + (size_t)n * splitk_columns(k) +
+                  (size_t)64 * n);
   if (precision == 1) b += sizeof(cc) * ((size_t)n * n + (size_t)2 * n * k);
   return b;
 }

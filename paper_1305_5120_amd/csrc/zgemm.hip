@@ -13,8 +13,14 @@
 // Design (CDNA4):
 //   * 256 threads = 4 waves in a 2x2 arrangement; a workgroup owns a BM x BN
 //     complex output tile, each wave (BM/2) x (BN/2) of it as 16x16 blocks;
-//   * complex products as four real v_mfma_f64_16x16x4f64 per 16x16x4 block
-//     into separate real / imaginary accumulators;
+//   * complex products as real v_mfma_f64_16x16x4f64 per 16x16x4 block:
+//     four of them into separate real / imaginary accumulators, or, in the
+//     filter steps, three (Gauss's 3M form: the sums of operand parts are
+//     formed in registers and three accumulator sets combined at the end),
+//     which removes a quarter of the matrix-core work; the rounding error
+//     stays within a small constant of the four-product form's normwise
+//     bound (Higham, "Stability of a method for multiplying complex
+//     matrices with three real matrix multiplications", SIMAX 1992);
 //   * K is walked in slabs of BK complex elements staged through LDS, double
 //     buffered: the next slab's global loads are in flight while the current
 //     slab feeds the matrix cores; one barrier per slab;
@@ -80,7 +86,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles) {
   return bid < full ? (bid % 8) * (ntiles / 8) + bid / 8 : bid;
 }
 
-template <class PT, int OPA, int OPB, int BM, int BN, int BK>
+template <class PT, int OPA, int OPB, int BM, int BN, int BK, bool G3 = false>
 __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int batch, int split) {
   using T = ZTile<BM, BN, BK>;
   using E = typename PT::E;
@@ -118,7 +124,14 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
   }
   const int64_t nslab = kend > kbeg ? cdiv(kend - kbeg, (int64_t)BK) : 0;
 
-  Acc accR[T::MI][T::NJ], accI[T::MI][T::NJ];
+  // Four real products per complex product: accR, accI hold the real and
+  // imaginary parts.  Three (G3): with a = ar + i ai, b = br + i bi,
+  //   t1 = br (ar + ai), t2 = ar (bi - br), t3 = ai (br + bi),
+  //   re = t1 - t3, im = t1 + t2,
+  // accumulated in accR (t1), accI (t2) and acc3 (t3) and combined once at
+  // the end; the sums of operand parts are formed in registers per step.
+  constexpr int MI3 = G3 ? T::MI : 1, NJ3 = G3 ? T::NJ : 1;
+  Acc accR[T::MI][T::NJ], accI[T::MI][T::NJ], acc3[MI3][NJ3];
 #pragma unroll
   for (int i = 0; i < T::MI; i++)
 #pragma unroll
@@ -126,6 +139,10 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
       accR[i][j] = Acc{0, 0, 0, 0};
       accI[i][j] = Acc{0, 0, 0, 0};
     }
+#pragma unroll
+  for (int i = 0; i < MI3; i++)
+#pragma unroll
+    for (int j = 0; j < NJ3; j++) acc3[i][j] = Acc{0, 0, 0, 0};
 
   E ra[T::EA], rb[T::EB];
 
@@ -200,40 +217,89 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
       for (int j = 0; j < T::NJ; j++) b[0][j] = Bs[buf][lk][wn0 + j * 16 + lr];
 #pragma unroll
       for (int ks = 0; ks < T::KS; ks++) {
-        const int c = ks & 1;
-        if (ks + 1 < T::KS) {
+        // with three accumulator sets the registers for a second set of
+        // fragments are not there: read each step's fragments when it starts
+        // (the other resident waves cover the LDS latency)
+        const int c = G3 ? 0 : (ks & 1);
+        if (G3) {
+          if (ks > 0) {
+#pragma unroll
+            for (int i = 0; i < T::MI; i++) a[0][i] = As[buf][ks * 4 + lk][wm0 + i * 16 + lr];
+#pragma unroll
+            for (int j = 0; j < T::NJ; j++) b[0][j] = Bs[buf][ks * 4 + lk][wn0 + j * 16 + lr];
+          }
+        } else if (ks + 1 < T::KS) {
 #pragma unroll
           for (int i = 0; i < T::MI; i++) a[c ^ 1][i] = As[buf][(ks + 1) * 4 + lk][wm0 + i * 16 + lr];
 #pragma unroll
           for (int j = 0; j < T::NJ; j++) b[c ^ 1][j] = Bs[buf][(ks + 1) * 4 + lk][wn0 + j * 16 + lr];
         }
         // D[n][m] += B[k][n] A[m][k]  (transposed product: result lanes run
-        // down columns).  The four real products are issued type by type so
-        // that dependent accumulations are MI*NJ instructions apart.
+        // down columns).  The real products are issued type by type so that
+        // dependent accumulations are MI*NJ instructions apart.
+        if constexpr (G3) {
+          R sa[T::MI], db[T::NJ], sb[T::NJ];
 #pragma unroll
-        for (int i = 0; i < T::MI; i++)
+          for (int i = 0; i < T::MI; i++) sa[i] = a[c][i].x + a[c][i].y;
 #pragma unroll
-          for (int j = 0; j < T::NJ; j++)
-            accR[i][j] = PT::mfma(b[c][j].x, a[c][i].x, accR[i][j]);
+          for (int j = 0; j < T::NJ; j++) {
+            db[j] = b[c][j].y - b[c][j].x;
+            sb[j] = b[c][j].x + b[c][j].y;
+          }
 #pragma unroll
-        for (int i = 0; i < T::MI; i++)
+          for (int i = 0; i < T::MI; i++)
 #pragma unroll
-          for (int j = 0; j < T::NJ; j++)
-            accI[i][j] = PT::mfma(b[c][j].y, a[c][i].x, accI[i][j]);
+            for (int j = 0; j < T::NJ; j++)
+              accR[i][j] = PT::mfma(b[c][j].x, sa[i], accR[i][j]);
 #pragma unroll
-        for (int i = 0; i < T::MI; i++)
+          for (int i = 0; i < T::MI; i++)
 #pragma unroll
-          for (int j = 0; j < T::NJ; j++)
-            accR[i][j] = PT::mfma(-b[c][j].y, a[c][i].y, accR[i][j]);
+            for (int j = 0; j < T::NJ; j++)
+              accI[i][j] = PT::mfma(db[j], a[c][i].x, accI[i][j]);
 #pragma unroll
-        for (int i = 0; i < T::MI; i++)
+          for (int i = 0; i < MI3; i++)
 #pragma unroll
-          for (int j = 0; j < T::NJ; j++)
-            accI[i][j] = PT::mfma(b[c][j].x, a[c][i].y, accI[i][j]);
+            for (int j = 0; j < NJ3; j++)
+              acc3[i][j] = PT::mfma(sb[j], a[c][i].y, acc3[i][j]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < T::MI; i++)
+#pragma unroll
+            for (int j = 0; j < T::NJ; j++)
+              accR[i][j] = PT::mfma(b[c][j].x, a[c][i].x, accR[i][j]);
+#pragma unroll
+          for (int i = 0; i < T::MI; i++)
+#pragma unroll
+            for (int j = 0; j < T::NJ; j++)
+              accI[i][j] = PT::mfma(b[c][j].y, a[c][i].x, accI[i][j]);
+#pragma unroll
+          for (int i = 0; i < T::MI; i++)
+#pragma unroll
+            for (int j = 0; j < T::NJ; j++)
+              accR[i][j] = PT::mfma(-b[c][j].y, a[c][i].y, accR[i][j]);
+#pragma unroll
+          for (int i = 0; i < T::MI; i++)
+#pragma unroll
+            for (int j = 0; j < T::NJ; j++)
+              accI[i][j] = PT::mfma(b[c][j].x, a[c][i].y, accI[i][j]);
+        }
       }
       if (s + 1 < nslab) store_slab(buf ^ 1);
       __syncthreads();
     }
+  }
+
+  if constexpr (G3) {
+#pragma unroll
+    for (int i = 0; i < MI3; i++)
+#pragma unroll
+      for (int j = 0; j < NJ3; j++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const R t1 = accR[i][j][r];
+          accR[i][j][r] = t1 - acc3[i][j][r];
+          accI[i][j][r] = t1 + accI[i][j][r];
+        }
   }
 
   // Epilogue.  D's row is the output column n, its column the output row m.
@@ -280,6 +346,15 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
       }
 }
 
+// Whether a filter tile configuration forms its complex products with three
+// real products: wherever the third accumulator set fits the registers the
+// configuration's occupancy leaves (FP64: tiles up to 64 x 64 at two
+// workgroups per CU; FP32 accumulators take half the registers).
+template <class PT, int BM, int BN, int MINB>
+constexpr bool gauss3() {
+  return sizeof(typename PT::E) == 8 || (BM * BN <= 64 * 64 && MINB <= 2);
+}
+
 #define ZGEMM_TILE_ARGS(p) xcd_tile(blockIdx.x, (int64_t)(p).tiles_m * (p).tiles_n), \
                                  (int)(blockIdx.y / (p).splitk), (int)(blockIdx.y % (p).splitk)
 
@@ -292,14 +367,14 @@ __global__ void __launch_bounds__(256, MINB) zgemm_kernel(ZGemmParams p) {
 // own symbol so that profiles separate the filter from the other products.
 template <int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) chebyshev_step_f64(ZGemmParams p) {
-  zgemm_body<PF64, OP_N, OP_N, BM, BN, BK>(p, ZGEMM_TILE_ARGS(p));
+  zgemm_body<PF64, OP_N, OP_N, BM, BN, BK, gauss3<PF64, BM, BN, MINB>()>(p, ZGEMM_TILE_ARGS(p));
 }
 
 // The mixed-precision filter step: complex FP32 operands on the FP32 matrix
 // cores with FP32 accumulation.
 template <int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) chebyshev_step_f32(ZGemmParams p) {
-  zgemm_body<PF32, OP_N, OP_N, BM, BN, BK>(p, ZGEMM_TILE_ARGS(p));
+  zgemm_body<PF32, OP_N, OP_N, BM, BN, BK, gauss3<PF32, BM, BN, MINB>()>(p, ZGEMM_TILE_ARGS(p));
 }
 
 // One degree step for a batch of problems of different sizes in one
@@ -317,7 +392,7 @@ __global__ void __launch_bounds__(256, MINB) chebyshev_step_f32(ZGemmParams p) {
 // stays valid while the active widths shrink.
 constexpr int GROUP_TILES = 16;
 
-template <class PT, int BM, int BN, int BK>
+template <class PT, int BM, int BN, int BK, int MINB>
 __device__ __forceinline__ void grouped_body(const ZGemmParams* __restrict__ gp, const int64_t* __restrict__ tile0,
                                              int G, int* __restrict__ ctr) {
   __shared__ int64_t next;
@@ -346,7 +421,7 @@ __device__ __forceinline__ void grouped_body(const ZGemmParams* __restrict__ gp,
     const int64_t nt = w % p.tiles_n, rest = w / p.tiles_n;
     const int split = (int)(rest % p.splitk);
     const int64_t mt = rest / p.splitk;
-    zgemm_body<PT, OP_N, OP_N, BM, BN, BK>(p, mt * p.tiles_n + nt, 0, split);
+    zgemm_body<PT, OP_N, OP_N, BM, BN, BK, gauss3<PT, BM, BN, MINB>()>(p, mt * p.tiles_n + nt, 0, split);
     __syncthreads();  // LDS of this tile fully consumed before the next one
   }
 }
@@ -355,14 +430,14 @@ template <int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) chebyshev_step_grouped_f64(const ZGemmParams* __restrict__ gp,
                                                                        const int64_t* __restrict__ tile0, int G,
                                                                        int* __restrict__ ctr) {
-  grouped_body<PF64, BM, BN, BK>(gp, tile0, G, ctr);
+  grouped_body<PF64, BM, BN, BK, MINB>(gp, tile0, G, ctr);
 }
 
 template <int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) chebyshev_step_grouped_f32(const ZGemmParams* __restrict__ gp,
                                                                        const int64_t* __restrict__ tile0, int G,
                                                                        int* __restrict__ ctr) {
-  grouped_body<PF32, BM, BN, BK>(gp, tile0, G, ctr);
+  grouped_body<PF32, BM, BN, BK, MINB>(gp, tile0, G, ctr);
 }
 
 // Combine split-K partial tiles and apply the epilogue (element e of batch
@@ -602,35 +677,27 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   const int batch = g.batch > 0 ? g.batch : 1;
   const bool nn = g.opA == OP_N && g.opB == OP_N;
   // Tall, deep products (the filter's A Y_i and the Rayleigh-Ritz A Q): rules
-  // read off sweeps of the configurations and splits on MI355X (n = 4000 and
-  // 10000, k_a from 16 to 660).  The best choices keep each workgroup's K
-  // range near 1000 (the A panels of the workgroups resident on one XCD then
-  // fit its 4 MB L2); in FP64 the 64 x 64 tile with room for four workgroups
-  // per CU leads wherever N is close to a multiple of 64, the 64 x 32 tile
-  // elsewhere below N = 256 (the padding of the last column tile decides).
+  // read off sweeps of the configurations and splits on MI355X (n = 2000,
+  // 4000 and 10000, k_a from 24 to 660).  The 64 x 64 x 16 tile leads unless
+  // its last column tile pads N clearly more than the 64 x 32 x 16 tile's
+  // does.  K is split so that each workgroup's range stays near 1000 (the A
+  // panels of the workgroups resident on one XCD then fit its 4 MB L2), and
+  // further where the tiles alone would leave the CUs short of work (FP32
+  // steps are shorter and want about twice as many workgroups).
   if (nn && batch == 1 && g.M >= 1024 && g.K >= 1024 && !(g.flags & GEMM_OUT_LOWER)) {
-    int c;
-    int sk = (int)std::min<int64_t>(8, std::max<int64_t>(1, (g.K + 500) / 1000));
-    if (g.prec == PREC_F64) {
-      // 64-wide tiles unless they would pad N by more than 7 % (then the
-      // 32-wide tile); narrow blocks split K 8 ways
-      const double pad64 = (double)(cdiv(g.N, (int64_t)64) * 64) / (double)g.N;
-      if (g.N >= 256) {
-        c = 8;  // 64 x 64 x 8, four workgroups per CU
-      } else if (pad64 <= 1.07 || g.N < 56) {
-        c = 8;
-        sk = 8;
-      } else {
-        c = 7;  // 64 x 32 x 16
-      }
-    } else {
-      c = 3;  // FP32: 64 x 64 x 8 at every width in the sweep (within 5 % of the best)
-      if (g.N < 96) sk = 8;
-    }
+    const bool f32 = g.prec == PREC_F32;
+    const double pad64 = (double)(cdiv(g.N, (int64_t)64) * 64) / (double)g.N;
+    const double pad32 = (double)(cdiv(g.N, (int64_t)32) * 32) / (double)g.N;
+    const int c = pad64 <= 1.08 * pad32 ? 1 : 7;
+    int sk = g.K < 1500 ? 1 : g.K < 3000 ? 2 : g.K < 7000 ? 4 : 8;
+    if (f32) sk = std::min(8, 2 * sk);
+    const int64_t tiles = cdiv(g.M, (int64_t)CFGS[c].bm) * cdiv(g.N, (int64_t)CFGS[c].bn);
+    const int64_t want = f32 ? 1000 : 480;
+    while (sk < 8 && tiles * sk < want && g.K >= (int64_t)2 * sk * (f32 ? 200 : 250)) sk *= 2;
     // a triangular op(A) leaves the top row panels short: deeper splits
     // rebalance the workgroups
     if (g.flags & (GEMM_TRI_A_LOWER | GEMM_TRI_A_UPPER)) sk = std::min(16, 2 * sk);
-    const size_t cap = (size_t)P_elems * (g.prec == PREC_F32 ? 2 : 1);
+    const size_t cap = (size_t)P_elems * (f32 ? 2 : 1);
     while (sk > 1 && (!g.allow_splitk || !P_elems || (size_t)sk * g.M * g.N > cap ||
                       g.K < (int64_t)sk * 4 * CFGS[c].bk))
       sk /= 2;

@@ -143,6 +143,48 @@ def test_filter_matches_oracle(lib, n, k, m):
     assert _rel(_np(Yt), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 8, 9])
+def test_filter_every_tile_shape_matches_oracle(lib, tile):
+    """Every tile configuration of the filter step, those forming complex
+    products with three real products (64 x 64 and smaller at two
+    workgroups per CU) and those with four, with and without a K split."""
+    n, k, m = 300, 37, 5
+    p = workloads.make_problem(n, 11)
+    Y = _cg(_rng(12), (n, k))
+    lam = np.sort(p.lam)
+    a, b, a0 = float(lam[k]), float(lam[-1] * 1.05), float(lam[0])
+    ref = oracle.chebyshev_filter(p.A, Y, m, a, b, a0)
+    for sk in (1, 4):
+        ctx = lib.create(n, filter_tile=tile, filter_splitk=sk)
+        Yt = _t(Y)
+        lib.filter(ctx, _t(p.A), Yt, m, a, b, a0)
+        assert _rel(_np(Yt), ref) <= 1e-12, (tile, sk)
+        ctx.release()
+
+
+def test_filter_three_product_form_with_unbalanced_parts(lib):
+    """The three-product form cancels in the imaginary part when real parts
+    dominate (t1 + t2 = b_r a_i + a_r b_i is formed from two terms of size
+    |a_r b_r|).  Its error must still be normwise: relative to the largest
+    entry, like the four-product form's.  n = 1100 takes the tall product
+    rules (64-wide tiles, K split)."""
+    n, k, m = 1100, 70, 3
+    rng = _rng(21)
+    R = rng.standard_normal((n, n))
+    I = rng.standard_normal((n, n))
+    A = (R + R.T) / 2 + 1e-6j * (I - I.T) / 2
+    A /= np.abs(np.linalg.eigvalsh(A)).max()
+    Y = rng.standard_normal((n, k)) + 1e-6j * rng.standard_normal((n, k))
+    a, b, a0 = 0.2, 1.05, -1.0
+    ref = oracle.chebyshev_filter(A, Y, m, a, b, a0)
+    ctx = lib.create(n)
+    Yt = _t(Y)
+    lib.filter(ctx, _t(A), Yt, m, a, b, a0)
+    got = _np(Yt)
+    assert _rel(got, ref) <= 1e-12
+    assert np.abs((got - ref).imag).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("n,k,m", [(300, 37, 7), (1000, 130, 20)])
 def test_filter_fp32_against_oracle(lib, n, k, m):
     """Mixed precision: the recurrence in complex FP32 with FP32 accumulation
