@@ -14,8 +14,8 @@
 //   * 256 threads = 4 waves in a 2x2 arrangement; a workgroup owns a BM x BN
 //     complex output tile, each wave (BM/2) x (BN/2) of it as 16x16 blocks;
 //   * complex products as real v_mfma_f64_16x16x4f64 per 16x16x4 block:
-//     four of them into separate real / imaginary accumulators, or, in the
-//     filter steps, three (Gauss's 3M form: the sums of operand parts are
+//     four of them into separate real / imaginary accumulators, or, where
+//     the registers allow, three (Gauss's 3M form: the sums of operand parts are
 //     formed in registers and three accumulator sets combined at the end),
 //     which removes a quarter of the matrix-core work; the rounding error
 //     stays within a small constant of the four-product form's normwise
@@ -346,8 +346,8 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
       }
 }
 
-// Whether a filter tile configuration forms its complex products with three
-// real products: wherever the third accumulator set fits the registers the
+// Whether a tile configuration forms its complex products with three real
+// products: wherever the third accumulator set fits the registers the
 // configuration's occupancy leaves (FP64: tiles up to 64 x 64 at two
 // workgroups per CU; FP32 accumulators take half the registers).
 template <class PT, int BM, int BN, int MINB>
@@ -360,7 +360,7 @@ constexpr bool gauss3() {
 
 template <int OPA, int OPB, int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) zgemm_kernel(ZGemmParams p) {
-  zgemm_body<PF64, OPA, OPB, BM, BN, BK>(p, ZGEMM_TILE_ARGS(p));
+  zgemm_body<PF64, OPA, OPB, BM, BN, BK, gauss3<PF64, BM, BN, MINB>()>(p, ZGEMM_TILE_ARGS(p));
 }
 
 // One degree step of the Chebyshev filter: the same body, launched under its
