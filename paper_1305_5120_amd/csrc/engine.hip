@@ -328,10 +328,12 @@ struct chfsi_ctx_s {
     ensure_small();
     if (S) cholesky(S, lds);
     else if (!have_factors) throw Error(ST_EINVAL, "no cached factor of S: pass S");
-    // A = Linv H Linv^H
+    // A = Linv H Linv^H; A is Hermitian, so the second product forms only
+    // the tiles that touch its lower triangle and the upper one is mirrored
     gemm(OP_N, OP_N, n, n, n, 1.0, Linv.z(), n, H, ldh, W.z(), n, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_A_LOWER);
-    gemm(OP_N, OP_C, n, n, n, 1.0, W.z(), n, Linv.z(), n, A.z(), n, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER);
-    hermitize(A.z(), n, n, st);
+    gemm(OP_N, OP_C, n, n, n, 1.0, W.z(), n, Linv.z(), n, A.z(), n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+         GEMM_TRI_B_UPPER | GEMM_OUT_LOWER);
+    hermitian_from_lower(A.z(), n, n, st);
   }
 
   // ------------------------------------------------------------------------

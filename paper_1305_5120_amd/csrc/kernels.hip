@@ -108,6 +108,15 @@ __global__ void k_zero_strict_upper(zc* A, int64_t lda, int64_t n) {
   if (i < j) A[i + j * lda] = zmk(0.0, 0.0);
 }
 
+__global__ void k_hermitian_from_lower(zc* A, int64_t lda, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e % n, j = e / n;
+  if (i < j) return;
+  if (i == j) A[i + i * lda].y = 0.0;
+  else A[j + i * lda] = zconj(A[i + j * lda]);
+}
+
 __global__ void k_hermitize(zc* A, int64_t lda, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * n) return;
@@ -1095,6 +1104,10 @@ void set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st) {
 
 void zero_strict_upper(zc* A, int64_t lda, int64_t n, hipStream_t st) {
   LAUNCH(k_zero_strict_upper, grid1(n * n), dim3(NT), 0, st, A, lda, n);
+}
+
+void hermitian_from_lower(zc* A, int64_t lda, int64_t n, hipStream_t st) {
+  LAUNCH(k_hermitian_from_lower, grid1(n * n), dim3(NT), 0, st, A, lda, n);
 }
 
 void hermitize(zc* A, int64_t lda, int64_t n, hipStream_t st) {

@@ -24,6 +24,9 @@ void to_f64(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t
 void set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st);
 void zero_strict_upper(zc* A, int64_t lda, int64_t n, hipStream_t st);
 void hermitize(zc* A, int64_t lda, int64_t n, hipStream_t st);  // A <- (A + A^H)/2, in place
+// A <- the Hermitian matrix whose lower triangle A holds (upper triangle
+// overwritten by the conjugate transpose, diagonal made real)
+void hermitian_from_lower(zc* A, int64_t lda, int64_t n, hipStream_t st);
 // R(:, j) = W(:, j) - mu[j] Y(:, j)
 void residual_block(const zc* W, int64_t ldw, const zc* Y, int64_t ldy, const double* mu, zc* R, int64_t ldr, int64_t n,
                     int64_t k, hipStream_t st);

@@ -358,9 +358,32 @@ constexpr bool gauss3() {
 #define ZGEMM_TILE_ARGS(p) xcd_tile(blockIdx.x, (int64_t)(p).tiles_m * (p).tiles_n), \
                                  (int)(blockIdx.y / (p).splitk), (int)(blockIdx.y % (p).splitk)
 
+// Products whose tile rows carry unequal work: a triangular op(A) gives
+// row panel i a K range proportional to i + 1 (lower) or to the rows below
+// it (upper), and a product restricted to the lower output tiles gives the
+// bottom rows the most tiles (with an upper-triangular op(B), also the
+// longest).  Their rows are
+// taken in the order heaviest, lightest, second heaviest, second lightest,
+// ..., so that each XCD's contiguous range of the order holds balanced work
+// (in row order the XCD holding the heavy rows would finish last, alone);
+// inside an XCD the workgroups resident on one CU are spread over the range
+// (consecutive workgroups of an XCD go to different CUs), so a row-major
+// walk gives every CU a share of heavy and light rows.
+__device__ __forceinline__ int64_t balanced_rows(const ZGemmParams& p, int64_t t) {
+  const bool lower_heavy = (p.flags & (GEMM_TRI_A_LOWER | GEMM_OUT_LOWER)) != 0;
+  const bool upper_heavy = (p.flags & GEMM_TRI_A_UPPER) != 0;
+  if (!lower_heavy && !upper_heavy) return t;
+  const int64_t i = t / p.tiles_n, c = t - i * p.tiles_n;
+  const int64_t heavy = lower_heavy ? p.tiles_m - 1 - (i >> 1) : (i >> 1);
+  const int64_t light = lower_heavy ? (i >> 1) : p.tiles_m - 1 - (i >> 1);
+  return ((i & 1) ? light : heavy) * p.tiles_n + c;
+}
+
 template <int OPA, int OPB, int BM, int BN, int BK, int MINB>
 __global__ void __launch_bounds__(256, MINB) zgemm_kernel(ZGemmParams p) {
-  zgemm_body<PF64, OPA, OPB, BM, BN, BK, gauss3<PF64, BM, BN, MINB>()>(p, ZGEMM_TILE_ARGS(p));
+  const int64_t t = balanced_rows(p, xcd_tile(blockIdx.x, (int64_t)p.tiles_m * p.tiles_n));
+  zgemm_body<PF64, OPA, OPB, BM, BN, BK, gauss3<PF64, BM, BN, MINB>()>(p, t, (int)(blockIdx.y / p.splitk),
+                                                                       (int)(blockIdx.y % p.splitk));
 }
 
 // One degree step of the Chebyshev filter: the same body, launched under its
