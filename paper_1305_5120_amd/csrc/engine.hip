@@ -344,6 +344,13 @@ struct chfsi_ctx_s {
   // less than their residual tolerance); tau = 0 iterates to working accuracy.
   void eigh(const zc* Gp, int64_t ldg, int64_t k, double* w, zc* Zo, int64_t ldz, double tau = 0.0) {
     if (k <= JACOBI_LDS_MAX) {
+      // nearly diagonal (the projected matrices of warm iterations): the
+      // refinement's few small products beat the sweeps of one workgroup;
+      // otherwise Jacobi in one workgroup
+      if (k >= SMALL_REFINE_MIN) {
+        jacobi_init(Gp, ldg, k, G2.z(), Ztmp.z(), st);
+        if (refine(G2.z(), nullptr, k, w, Zo, ldz, tau)) return;
+      }
       jacobi_small(Gp, ldg, k, w, Zo, ldz, Ztmp.z(), nullptr, st, tau);
       return;
     }
@@ -462,6 +469,7 @@ struct chfsi_ctx_s {
   // (e.g. 0.2, 9e-3, 7e-4, 1e-6, 1e-13), so after a step whose largest
   // correction is below DONE the remaining error is at rounding level.
   static constexpr double REF_ETA = 0.25;
+  static constexpr int64_t SMALL_REFINE_MIN = 24;
   bool refine(const zc* Gm, const zc* Zpre, int64_t k, double* w, zc* Zo, int64_t ldz, double tau) {
     const double ETA = REF_ETA, GROW = 0.5, DONE = 1e-8;
     const int MAX_STEPS = 10;

@@ -305,11 +305,12 @@ def test_eigh_clustered_spectrum(lib):
     assert np.abs(w - lam).max() <= 1e-14 * k
 
 
-@pytest.mark.parametrize("k,eps", [(300, 1e-6), (200, 1e-3), (130, 0.0)])
+@pytest.mark.parametrize("k,eps", [(300, 1e-6), (200, 1e-3), (130, 0.0), (64, 1e-6), (96, 1e-4), (24, 1e-8)])
 def test_eigh_nearly_diagonal_matches_oracle(lib, k, eps):
     """The projected matrices of late iterations are nearly diagonal: a
     spread diagonal with a tight pair and a Hermitian perturbation of
-    relative size eps (the refinement path), against the oracle's Jacobi."""
+    relative size eps (the refinement path, for small blocks too), against
+    the oracle's Jacobi."""
     rng = _rng(k + 7)
     d = np.sort(rng.uniform(-1, 1, k))
     d[k // 2 + 1] = d[k // 2] + 3e-4  # close pair, still resolved by the coupling ratio
