@@ -273,29 +273,47 @@ struct chfsi_ctx_s {
   // into Lb (strict upper triangle zero) and Lib = Lb^{-1}; Wb is m x m work;
   // all with leading dimension ld.  Returns 0, or the 1-based column of the
   // first pivot that is not positive (then Lb / Lib are incomplete).
-  int chol_factor(int64_t m, const zc* src, int64_t lds, zc* Wb, zc* Lb, zc* Lib, int64_t ld) {
+  // Blocked Cholesky of the m x m Hermitian matrix whose lower triangle src
+  // holds (the upper triangle is not read): Lb = L, Lib = L^{-1} (both with
+  // zero strict upper triangles), Wb scratch.  With info_d null the host
+  // waits and the first non-positive pivot's column + 1 is returned (0 when
+  // positive definite).  With info_d (device int) nothing waits: the column
+  // + 1 lands there (INT_MAX when positive definite) and Lb, Lib are
+  // meaningless when it is not; the caller reads it when convenient.
+  int chol_factor(int64_t m, const zc* src, int64_t lds, zc* Wb, zc* Lb, zc* Lib, int64_t ld, int* info_d = nullptr) {
     const int64_t NB = CHOL_NB;
-    copy2d(src, lds, Wb, ld, m, m, st);
-    fill_i32(flags.i(), 1, INT_MAX, st);
-    for (int64_t j0 = 0; j0 < m; j0 += NB) {
-      const int64_t nb = std::min(NB, m - j0), r = m - j0 - nb;
-      chol_diag(Wb, ld, Lb, ld, Lib, ld, j0, nb, flags.i(), st);
-      if (r > 0) {
-        // L21 = W21 L11^{-H}
-        gemm(OP_N, OP_C, r, nb, nb, 1.0, Wb + (j0 + nb) + j0 * ld, ld, Lib + j0 + j0 * ld, ld, Lb + (j0 + nb) + j0 * ld,
-             ld, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER, false);
-        // W22 -= L21 L21^H (lower tiles)
-        zc* W22 = Wb + (j0 + nb) + (j0 + nb) * ld;
-        const zc* L21 = Lb + (j0 + nb) + j0 * ld;
-        gemm(OP_N, OP_C, r, r, nb, -1.0, L21, ld, L21, ld, W22, ld, 1.0, W22, ld, 0.0, nullptr, 0, GEMM_OUT_LOWER, false);
+    int* info = info_d ? info_d : flags.i();
+    fill_i32(info, 1, INT_MAX, st);
+    if (m <= NB) {
+      // one diagonal block: factor and inverse in one launch, straight from
+      // src (no trailing updates touch it); the kernel writes the zeros
+      chol_diag(src, lds, Lb, ld, Lib, ld, 0, m, info, st);
+    } else {
+      copy2d(src, lds, Wb, ld, m, m, st);
+      for (int64_t j0 = 0; j0 < m; j0 += NB) {
+        const int64_t nb = std::min(NB, m - j0), r = m - j0 - nb;
+        chol_diag(Wb, ld, Lb, ld, Lib, ld, j0, nb, info, st);
+        if (r > 0) {
+          // L21 = W21 L11^{-H}
+          gemm(OP_N, OP_C, r, nb, nb, 1.0, Wb + (j0 + nb) + j0 * ld, ld, Lib + j0 + j0 * ld, ld,
+               Lb + (j0 + nb) + j0 * ld, ld, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER, false);
+          // W22 -= L21 L21^H (lower tiles)
+          zc* W22 = Wb + (j0 + nb) + (j0 + nb) * ld;
+          const zc* L21 = Lb + (j0 + nb) + j0 * ld;
+          gemm(OP_N, OP_C, r, r, nb, -1.0, L21, ld, L21, ld, W22, ld, 1.0, W22, ld, 0.0, nullptr, 0, GEMM_OUT_LOWER,
+               false);
+        }
       }
+      zero_strict_upper(Lb, ld, m, st);
     }
-    zero_strict_upper(Lb, ld, m, st);
-    CHFSI_HIP(hipMemcpyAsync(hbuf, flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    sync();
-    int info;
-    std::memcpy(&info, hbuf, sizeof(int));
-    if (info != INT_MAX) return info;
+    if (!info_d) {
+      CHFSI_HIP(hipMemcpyAsync(hbuf, flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
+      sync();
+      int hinfo;
+      std::memcpy(&hinfo, hbuf, sizeof(int));
+      if (hinfo != INT_MAX) return hinfo;
+    }
+    if (m <= NB) return 0;
     // Lib: off-diagonal blocks by recursive doubling,
     //   inv([[L11, 0], [L21, L22]]) = [[X11, 0], [-X22 L21 X11, X22]]
     for (int64_t s = NB; s < m; s *= 2) {
@@ -481,9 +499,11 @@ struct chfsi_ctx_s {
     zc* Pb = Sb + kk;
     zc* Eb = Pb + kk;
     double* lam = rfl.d();
+    // step s accumulates its largest correction in slot s % 2 and clears the
+    // other slot for step s + 1 (the host has read it by then)
     auto* corr = static_cast<unsigned long long*>(rfc.p);
-    auto read_corr = [&]() {
-      CHFSI_HIP(hipMemcpyAsync(hbuf, corr, sizeof(double), hipMemcpyDeviceToHost, st));
+    auto read_corr = [&](int step) {
+      CHFSI_HIP(hipMemcpyAsync(hbuf, corr + (step & 1), sizeof(double), hipMemcpyDeviceToHost, st));
       sync();
       double c;
       std::memcpy(&c, hbuf, sizeof(double));
@@ -491,21 +511,18 @@ struct chfsi_ctx_s {
     };
     // step 0: X = I, S = Gm, P = I
     CHFSI_HIP(hipMemsetAsync(corr, 0, sizeof(unsigned long long), st));
-    refine_coeffs(Gm, nullptr, k, tau, Eb, X, lam, corr, st);
-    double c = read_corr();
+    refine_coeffs(Gm, nullptr, k, tau, Eb, X, lam, corr, corr + 1, st);
+    double c = read_corr(0);
     if (!(c <= ETA)) return false;
     for (int step = 1; !(c < DONE); step++) {
       if (step > MAX_STEPS) return false;
       gemm(OP_N, OP_N, k, k, k, 1.0, Gm, k, X, k, Wb, k);
       gemm(OP_C, OP_N, k, k, k, 1.0, X, k, Wb, k, Sb, k);
       gemm(OP_C, OP_N, k, k, k, 1.0, X, k, X, k, Pb, k);
-      hermitize(Sb, k, k, st);
-      hermitize(Pb, k, k, st);
-      CHFSI_HIP(hipMemsetAsync(corr, 0, sizeof(unsigned long long), st));
-      refine_coeffs(Sb, Pb, k, tau, Eb, nullptr, lam, corr, st);
+      refine_coeffs(Sb, Pb, k, tau, Eb, nullptr, lam, corr + (step & 1), corr + ((step + 1) & 1), st);
       gemm(OP_N, OP_N, k, k, k, 1.0, X, k, Eb, k, Xn, k, 1.0, X, k);  // X + X E
       std::swap(X, Xn);
-      c = read_corr();
+      c = read_corr(step);
       if (!(c <= GROW)) return false;
     }
     const zc* Zf = X;
@@ -560,12 +577,22 @@ struct chfsi_ctx_s {
   // One CholeskyQR pass: G = Yin^H Yin = Lg Lg^H, Qo = Yin Lg^{-H}.  False
   // when the Gram matrix is not numerically positive definite.
   // ------------------------------------------------------------------------
-  bool cholqr_pass(const zc* Yin, int64_t ldy, int64_t k, zc* Qo, int64_t ldq) {
+  // (The Cholesky reads only the Gram matrix's lower triangle.)  The pass's
+  // success lands in info_d (INT_MAX: positive definite) without a wait;
+  // Qo is meaningless when it failed.
+  void cholqr_pass(const zc* Yin, int64_t ldy, int64_t k, zc* Qo, int64_t ldq, int* info_d) {
     gemm(OP_C, OP_N, k, k, n, 1.0, Yin, ldy, Yin, ldy, G.z(), k);
-    hermitize(G.z(), k, k, st);
-    if (chol_factor(k, G.z(), k, G2.z(), Z2.z(), Ztmp.z(), k) != 0) return false;
+    chol_factor(k, G.z(), k, G2.z(), Z2.z(), Ztmp.z(), k, info_d);
     gemm(OP_N, OP_C, n, k, k, 1.0, Yin, ldy, Ztmp.z(), k, Qo, ldq, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER);
-    return true;
+  }
+
+  // Both passes' outcomes (infos at flags[2], flags[3]) with one wait.
+  std::pair<bool, bool> cholqr_outcome() {
+    CHFSI_HIP(hipMemcpyAsync(hbuf, flags.i() + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    sync();
+    int h[2];
+    std::memcpy(h, hbuf, sizeof(h));
+    return {h[0] == INT_MAX, h[1] == INT_MAX};
   }
 
   // Orthonormal basis of span(F) (F: n x k, ld n, destroyed) into Qo.
@@ -576,8 +603,11 @@ struct chfsi_ctx_s {
   bool orthonormalize(zc* Fp, int64_t k, zc* Qo, int64_t ldq) {
     if (opts.qr_mode == 0) {
       zc* mid = Wk.z();
-      if (cholqr_pass(Fp, n, k, mid, n)) {
-        if (cholqr_pass(mid, n, k, Qo, ldq)) return false;
+      cholqr_pass(Fp, n, k, mid, n, flags.i() + 2);
+      cholqr_pass(mid, n, k, Qo, ldq, flags.i() + 3);
+      const auto ok = cholqr_outcome();
+      if (ok.first && ok.second) return false;
+      if (ok.first) {
         qr(mid, n, k, Qo, ldq);
         return true;
       }
@@ -607,10 +637,11 @@ struct chfsi_ctx_s {
         gemm(OP_N, OP_N, n, ka, cl, -1.0, Yl, n, B, cl, X, n, 1.0, X, n);  // X -= Y_lock B
       };
       project(Fa);
-      if (cholqr_pass(Fa, n, ka, mid, n)) {
-        project(mid);
-        if (cholqr_pass(mid, n, ka, Qo + cl * ldq, ldq)) return false;
-      }
+      cholqr_pass(Fa, n, ka, mid, n, flags.i() + 2);
+      project(mid);
+      cholqr_pass(mid, n, ka, Qo + cl * ldq, ldq, flags.i() + 3);
+      const auto ok = cholqr_outcome();
+      if (ok.first && ok.second) return false;
     }
     if (cl > 0) copy2d(Yl, n, Fp, n, n, cl, st);
     qr(Fp, n, k, Qo, ldq);

@@ -925,10 +925,14 @@ __global__ void k_jacobi_permute(const zc* Z, int64_t k, const int* rank, zc* Zo
 // corr (bit pattern of a non-negative double) receives max |E_ij| over i != j,
 // +inf for a non-finite value.
 // --------------------------------------------------------------------------
+// (S, P are read as their Hermitian parts (M + M^H)/2: the products that
+// form them are Hermitian only up to rounding.)  corr_next (nullable) is
+// zeroed for the next step's maximum.
 __global__ void k_refine_coeffs(const zc* S, const zc* P, int64_t k, double tau, zc* E, zc* Xout, double* lam,
-                                unsigned long long* corr) {
+                                unsigned long long* corr, unsigned long long* corr_next) {
   __shared__ double red[NT / 64];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (corr_next && e == 0) *corr_next = 0ull;
   double c = 0.0;
   if (e < k * k) {
     const int64_t i = e % k, j = e / k;
@@ -939,8 +943,14 @@ __global__ void k_refine_coeffs(const zc* S, const zc* P, int64_t k, double tau,
       ev = zmk(0.5 * (1.0 - pii), 0.0);
       if (lam) lam[i] = li;
     } else {
-      const zc r = P ? zmk(-P[e].x, -P[e].y) : zmk(0.0, 0.0);
-      const zc sij = S[e];
+      const int64_t et = j + i * k;
+      zc r = zmk(0.0, 0.0);
+      if (P) {
+        const zc a = P[e], b = P[et];
+        r = zmk(-(0.5 * (a.x + b.x)), -(0.5 * (a.y - b.y)));
+      }
+      const zc s0 = S[e], s1 = S[et];
+      const zc sij = zmk(0.5 * (s0.x + s1.x), 0.5 * (s0.y - s1.y));
       const zc n1 = zadd(sij, zscale(lj, r)), n2 = zadd(sij, zscale(li, r));
       const double m2 = fmax(zabs2(n1), zabs2(n2));
       if (m2 > tau * tau) ev = zscale(1.0 / (lj - li), n1);
@@ -1223,8 +1233,8 @@ void jacobi_sort(const zc* G, const zc* Z, int64_t k, double* w, int* rank, zc* 
 }
 
 void refine_coeffs(const zc* S, const zc* P, int64_t k, double tau, zc* E, zc* Xout, double* lam,
-                   unsigned long long* corr, hipStream_t st) {
-  LAUNCH(k_refine_coeffs, grid1(k * k), dim3(NT), 0, st, S, P, k, tau, E, Xout, lam, corr);
+                   unsigned long long* corr, unsigned long long* corr_next, hipStream_t st) {
+  LAUNCH(k_refine_coeffs, grid1(k * k), dim3(NT), 0, st, S, P, k, tau, E, Xout, lam, corr, corr_next);
 }
 
 void sort_by_values(const double* lam, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz,

@@ -89,11 +89,12 @@ void jacobi_sparse_round(zc* G, zc* Z, int64_t k, const int* pairs, int np, cons
 size_t jacobi_rot_bytes();
 
 // ---- Eigenvector refinement for nearly diagonal Hermitian k x k -------------
-// One step's coefficients E (k x k) from S = X^H G X and P = X^H X (P null:
-// X = I, then also Xout = I + E); lam = Rayleigh quotients; *corr (zeroed by
-// the caller) = max off-diagonal |E| as double bits.
+// One step's coefficients E (k x k) from S = X^H G X and P = X^H X, both
+// read as their Hermitian parts (P null: X = I, then also Xout = I + E);
+// lam = Rayleigh quotients; *corr (zero at launch) = max off-diagonal |E| as
+// double bits; *corr_next (nullable) is zeroed for the next step.
 void refine_coeffs(const zc* S, const zc* P, int64_t k, double tau, zc* E, zc* Xout, double* lam,
-                   unsigned long long* corr, hipStream_t st);
+                   unsigned long long* corr, unsigned long long* corr_next, hipStream_t st);
 // w ascending = lam sorted; Zout (ld ldz) = Z's columns in that order
 void sort_by_values(const double* lam, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz,
                     hipStream_t st);

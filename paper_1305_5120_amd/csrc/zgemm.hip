@@ -472,6 +472,9 @@ __device__ __forceinline__ void splitk_reduce_elem(const ZGemmParams& p, int64_t
   const int64_t m = e % p.M, n = e / p.M;
   const E* P = static_cast<const E*>(p.P) + (int64_t)batch * p.splitk * p.M * p.N;
   R re = 0, im = 0;
+  // unrolled so that several partial loads are in flight; the sum is still
+  // taken in split order
+#pragma unroll 8
   for (int s = 0; s < p.splitk; s++) {
     const E v = P[(int64_t)s * p.M * p.N + e];
     re += v.x;
@@ -729,12 +732,17 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
     return;
   }
   // Small outputs of deep products (Gram matrices Y^H Y, Q^H W): 32 x 32
-  // tiles split 16 ways; tall products with a short K (n x k times k x k):
-  // 32 x 32 tiles, no split (both read off the same sweep).
+  // tiles split 16 ways, and further (up to 64, each split at least two
+  // slabs deep) while the tiles and splits give fewer than 256 workgroups;
+  // tall products with a short K (n x k times k x k): 32 x 32 tiles, no
+  // split (both read off the same sweep).
   if (batch == 1 && g.M * g.N <= 512 * 512 && g.K >= 2048 && g.allow_splitk && P_elems &&
       !(g.flags & GEMM_OUT_LOWER) && g.prec == PREC_F64) {
+    const int64_t tiles = cdiv(g.M, (int64_t)32) * cdiv(g.N, (int64_t)32);
     int sk = 16;
-    while (sk > 1 && ((size_t)sk * g.M * g.N > (size_t)P_elems || g.K < (int64_t)sk * 4 * CFGS[2].bk)) sk /= 2;
+    while (sk < 64 && tiles * sk < 256 && g.K >= (int64_t)2 * sk * 2 * CFGS[2].bk) sk *= 2;
+    const int min_slabs = sk > 16 ? 2 : 4;
+    while (sk > 1 && ((size_t)sk * g.M * g.N > (size_t)P_elems || g.K < (int64_t)sk * min_slabs * CFGS[2].bk)) sk /= 2;
     cfg = 2;
     splitk = sk;
     return;
