@@ -485,6 +485,48 @@ def run_warmcold(args):
     print(json.dumps(out), flush=True)
 
 
+def run_mixed_same_workload(args, cfg, probs, fp64_rate):
+    """After the FP64 timed region: the same problems, in the same order and
+    with the same warm starts, solved with the mixed-precision filter (complex
+    FP32 degree steps for columns whose residual is above the switch, FP64
+    final sweeps to the same tolerance), timed the same way."""
+    import torch
+    from paper_1305_5120_amd import chfsi
+    n, nev, nex = cfg["n"], cfg["nev"], cfg["nex"]
+    ctx = chfsi.create(n, degree=cfg["degree"], seed=0, precision=1, profile=0 if args.no_profile else 1)
+    S0 = probs[0]["S"]
+    total = args.warmup + args.steps
+
+    def one(i):
+        p = probs[i]
+        S = S0 if i == 0 else (None if cfg["sequence"] else p["S"])
+        if not cfg["sequence"]:
+            ctx.reset()
+        return chfsi.solve(ctx, p["H"], S, nev, nex, tol=1e-10)
+
+    for i in range(args.warmup):
+        one(i)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.warmup, total):
+        ev, X, info, st = one(i)
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    rel_res = residual_check(probs[total - 1], ev, X)
+    ctx.release()
+    f32s = sum(i["filter_kernel_seconds_fp32"] for i in infos)
+    f32f = sum(i["filter_flops_fp32"] for i in infos)
+    rate = args.steps / elapsed
+    log(f"[bench] mixed precision, same problems: {rate:.3f} solves/s ({rate / fp64_rate:.2f}x FP64), "
+        f"iterations {[i['iterations'] for i in infos]}, residual {rel_res:.2e}")
+    return {"solves_per_s": rate, "speedup_vs_fp64": rate / fp64_rate, "ms_per_step": 1e3 * elapsed / args.steps,
+            "iterations": [i["iterations"] for i in infos], "iterations_fp32": [i["iterations_fp32"] for i in infos],
+            "max_rel_residual": rel_res, "filter_tflops_fp32": f32f / f32s / 1e12 if f32s else None,
+            "filter_flops_fp32_share": f32f / max(1.0, sum(i["filter_flops"] for i in infos))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,6 +542,8 @@ def main():
     ap.add_argument("--wc-n", type=int, default=4000, help="problem size of the warm/cold study")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not time filter launches with events")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision pass over the same problems (after the timed region)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, run a device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -590,6 +634,8 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "algorithmic_flops_per_launch": flops / launches if launches else None},
     }
+    if not args.no_mixed:
+        out["mixed_precision"] = run_mixed_same_workload(args, cfg, probs, out["value"])
     if args.calibrate_copy:
         calibrate_copy()
     if not args.no_cpu_baseline:

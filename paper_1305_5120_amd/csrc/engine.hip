@@ -887,6 +887,7 @@ struct SolveState {
 // its residual.  QR, Rayleigh-Ritz, residuals and locking stay FP64, so
 // accepted pairs meet the same tolerance.
 constexpr double MIXED_SWITCH = 1e-6;
+constexpr int64_t MIXED_MIN_COLS = 64;
 
 double secs_since(std::chrono::steady_clock::time_point a) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
@@ -1003,6 +1004,10 @@ void solve_filter_begin(SolveState& s) {
   while (j < s.k && s.rho_last[j] <= MIXED_SWITCH * s.inf.h_H) j++;
   s.fp64_upto = j;
   s.split = std::min(ka, std::max<int64_t>(0, s.fp64_upto - s.cl));
+  // a narrow FP32 part does not pay for its own launches and conversions
+  // beside an FP64 one (measured: a warm n = 4000 sequence ran slower in
+  // mixed precision than in FP64): filter everything in FP64 then
+  if (s.split > 0 && ka - s.split < std::max<int64_t>(MIXED_MIN_COLS, ka / 8)) s.split = ka;
 }
 
 // The filter of the active columns, result into F(:, cl:k).
