@@ -714,7 +714,8 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
     const bool f32 = g.prec == PREC_F32;
     const double pad64 = (double)(cdiv(g.N, (int64_t)64) * 64) / (double)g.N;
     const double pad32 = (double)(cdiv(g.N, (int64_t)32) * 32) / (double)g.N;
-    const int c = pad64 <= 1.08 * pad32 ? 1 : 7;
+    // (FP32 blocks of 97-128 columns: the 64 x 128 x 8 tile, one column tile)
+    const int c = (f32 && g.N > 96 && g.N <= 128) ? 5 : (pad64 <= 1.08 * pad32 ? 1 : 7);
     int sk = g.K < 1500 ? 1 : g.K < 3000 ? 2 : g.K < 7000 ? 4 : 8;
     if (f32) sk = std::min(8, 2 * sk);
     const int64_t tiles = cdiv(g.M, (int64_t)CFGS[c].bm) * cdiv(g.N, (int64_t)CFGS[c].bn);
