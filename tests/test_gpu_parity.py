@@ -112,6 +112,41 @@ def test_zgemm_triangular_structure_flags(lib):
     assert _rel(_np(C), Am @ Bl.conj().T) <= 1e-13
 
 
+@pytest.mark.parametrize("flag", [1, 2, 16, 8 | 16])
+@pytest.mark.parametrize("tile,split", [(0, 0), (1, 4), (7, 1), (2, 8)])
+def test_zgemm_structured_products_many_tile_rows(lib, flag, tile, split):
+    """Triangular op(A) (lower, upper), lower-only output, and upper op(B)
+    with lower-only output over 18 tile rows (an odd count: the products
+    deal their rows heaviest / lightest alternately), several column tiles,
+    automatic and explicit tiles and K splits (none with a lower-only
+    output, which takes no split)."""
+    rng = _rng(100 + flag)
+    n, w = 1100, 300
+    ctx = lib.create(8)
+    if flag & 16 and split > 1:
+        split = 1
+    bits = flag | (tile << 8) | (split << 16)
+    if flag in (1, 2):
+        Am = np.tril(_cg(rng, (n, n))) if flag == 1 else np.triu(_cg(rng, (n, n)))
+        B = _cg(rng, (n, w))
+        C = lib.zgemm(ctx, 0, 0, _t(Am), _t(B), flags=bits)
+        assert _rel(_np(C), Am @ B) <= 1e-13
+    elif flag == 16:
+        Am = _cg(rng, (n, 500))
+        B = _cg(rng, (500, n))
+        C = _np(lib.zgemm(ctx, 0, 0, _t(Am), _t(B), flags=bits))
+        ref = Am @ B
+        low = np.tril_indices(n)
+        assert np.linalg.norm(C[low] - ref[low]) <= 1e-13 * np.linalg.norm(ref[low])
+    else:
+        Am = _cg(rng, (n, n))
+        Bl = np.tril(_cg(rng, (n, n)))
+        C = _np(lib.zgemm(ctx, 0, 1, _t(Am), _t(Bl), flags=bits))
+        ref = Am @ Bl.conj().T
+        low = np.tril_indices(n)
+        assert np.linalg.norm(C[low] - ref[low]) <= 1e-13 * np.linalg.norm(ref[low])
+
+
 def test_zgemm_in_place_epilogue(lib):
     """out aliasing Z (the filter writes Y_{i+1} over Y_{i-1})."""
     import torch
