@@ -59,16 +59,20 @@ typedef struct {
   int32_t max_iter;      /* outer iterations before CHFSI_ENOCONV (default 1000) */
   int32_t lanczos_steps; /* Lanczos steps for the spectral bound (default 10, at most 96) */
   int32_t precision;     /* 0: FP64 throughout; 1: mixed - the Chebyshev filter in complex FP32
-                            (FP32 matrix cores, FP32 accumulation) while the leading unconverged
-                            residual is above 1e-5 h_H and falling, FP64 for everything else and
-                            for the final sweeps; accepted pairs meet the same FP64 tolerance */
+                            (FP32 matrix cores, FP32 accumulation) for the active columns after the
+                            leading ones whose generalized residuals are below the switch (see
+                            mixed_switch_digits), FP64 for those, for everything else and for the
+                            final sweeps; accepted pairs meet the same FP64 tolerance */
   uint64_t seed;         /* Philox4x32-10 seed of the random start vectors (default 0) */
   int32_t profile;       /* 1: time every filter kernel launch with device events */
   int32_t qr_mode;       /* re-orthonormalization: 0 = CholeskyQR2, Householder when a Gram
                             matrix is not positive definite (default); 1 = Householder always */
   int32_t filter_tile;   /* filter kernel tile configuration (chfsi_zgemm's numbering; 0 = automatic) */
   int32_t filter_splitk; /* filter K split (0 = automatic, 1 = none, up to 16) */
-  int32_t reserved[4];
+  int32_t mixed_switch_digits; /* mixed precision: a column's filter turns FP64 once its generalized
+                                  residual is below 10^-digits h_H (0 = default 6; 1 to 12); a switch
+                                  below the FP32 filter's rounding floor costs iterations, not accuracy */
+  int32_t reserved[3];
 } chfsi_opts;
 
 typedef struct {

@@ -37,7 +37,8 @@ class ChfsiError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("degree", c_i32), ("max_iter", c_i32), ("lanczos_steps", c_i32), ("precision", c_i32),
                 ("seed", c_u64), ("profile", c_i32), ("qr_mode", c_i32),
-                ("filter_tile", c_i32), ("filter_splitk", c_i32), ("reserved", c_i32 * 4)]
+                ("filter_tile", c_i32), ("filter_splitk", c_i32), ("mixed_switch_digits", c_i32),
+                ("reserved", c_i32 * 3)]
 
 
 class Info(ctypes.Structure):

@@ -859,6 +859,7 @@ struct SolveState {
   int64_t cl = 0;
   int it = 0;
   bool converged = false, done = false, mixed = false;
+  double mixed_switch = 0.0;  // relative residual below which a column's filter is FP64
   std::vector<double> lam, rho_lock;
   std::vector<hipEvent_t> ev;
   // mixed precision: this iteration's leading active columns filtered in
@@ -879,7 +880,8 @@ struct SolveState {
 };
 
 // Mixed precision, per column: the FP64 filter takes the leading active
-// columns whose generalized residuals have all reached MIXED_SWITCH * h_H
+// columns whose generalized residuals have all reached the switch (MIXED_SWITCH
+// unless the options set another) times h_H
 // (an order above where FP32 rounding in the filter holds them); the
 // columns after the first one still above it are filtered in complex FP32.
 // The FP64 range only grows (a column stays FP64 until it locks), and the
@@ -926,6 +928,7 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
   auto t0 = std::chrono::steady_clock::now();
   c->reduce(s.H, s.ldh, s.S, s.lds);
   s.mixed = o.precision == 1;
+  s.mixed_switch = o.mixed_switch_digits > 0 ? std::pow(10.0, -o.mixed_switch_digits) : MIXED_SWITCH;
   if (s.mixed) {
     c->A32.ensure((size_t)n * n * sizeof(cc));
     c->Y32.ensure((size_t)n * k * sizeof(cc));
@@ -1001,7 +1004,7 @@ void solve_filter_begin(SolveState& s) {
     return;
   }
   int64_t j = std::max(s.cl, s.fp64_upto);
-  while (j < s.k && s.rho_last[j] <= MIXED_SWITCH * s.inf.h_H) j++;
+  while (j < s.k && s.rho_last[j] <= s.mixed_switch * s.inf.h_H) j++;
   s.fp64_upto = j;
   s.split = std::min(ka, std::max<int64_t>(0, s.fp64_upto - s.cl));
   // a narrow FP32 part does not pay for its own launches and conversions
@@ -1081,9 +1084,17 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   }
   if (s.mixed) {
     for (int64_t j = 0; j < ka; j++) s.rho_last[cl + j] = rho[j];
-    // an FP32 iteration that did not halve the first column's residual
-    if (s.prev_first32 && s.prev_first == cl && rho[0] > 0.5 * s.prev_first_rho)
-      s.fp64_upto = std::max(s.fp64_upto, cl + 1);
+    // an FP32 iteration that did not halve the first column's residual: the
+    // FP32 filter has reached its rounding floor there, and the columns after
+    // it whose residuals are within an order of that one (or two orders of
+    // the switch) are near the same floor, so they turn FP64 together (one
+    // per iteration would cost an iteration each)
+    if (s.prev_first32 && s.prev_first == cl && rho[0] > 0.5 * s.prev_first_rho) {
+      const double floor_level = std::max(100.0 * s.mixed_switch * inf.h_H, 10.0 * rho[0]);
+      int64_t j = cl + 1;
+      while (j < s.k && s.rho_last[j] <= floor_level) j++;
+      s.fp64_upto = std::max(s.fp64_upto, j);
+    }
     s.prev_first = cl + nl;
     s.prev_first_rho = nl < ka ? rho[nl] : INFINITY;
     s.prev_first32 = nl < ka && nl >= s.split;  // that column's filter ran in FP32
@@ -1833,7 +1844,7 @@ chfsi_status chfsi_create(chfsi_ctx* out, int64_t n, const chfsi_opts* opts, voi
   if (opts) o = *opts;
   if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX || (o.precision != 0 && o.precision != 1) ||
       (o.qr_mode != 0 && o.qr_mode != 1) || o.filter_tile < 0 || o.filter_tile >= zgemm_num_configs() ||
-      o.filter_splitk < 0 || o.filter_splitk > 16)
+      o.filter_splitk < 0 || o.filter_splitk > 16 || o.mixed_switch_digits < 0 || o.mixed_switch_digits > 12)
     return CHFSI_EINVAL;
   chfsi_ctx c = new (std::nothrow) chfsi_ctx_s();
   if (!c) return CHFSI_ENOMEM;

@@ -52,6 +52,9 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     assert lib.chfsi_create(ctypes.byref(h), 10, ctypes.byref(o), None) == -1
     o = chfsi.default_opts(lanczos_steps=500)
     assert lib.chfsi_create(ctypes.byref(h), 10, ctypes.byref(o), None) == -1
+    for bad in (-1, 13):
+        o = chfsi.default_opts(mixed_switch_digits=bad)
+        assert lib.chfsi_create(ctypes.byref(h), 10, ctypes.byref(o), None) == -1
     assert lib.chfsi_create(None, 10, None, None) == -1
     lib.chfsi_release(None)  # NULL-safe
 

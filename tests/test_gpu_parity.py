@@ -484,6 +484,25 @@ def test_solve_config0_mixed_precision_matches_oracle(lib):
     _check_solution(p, ev, _np(X), 51)
 
 
+@pytest.mark.parametrize("digits", [8, 10])
+def test_solve_mixed_precision_switch_below_fp32_floor(lib, digits):
+    """A switch below what the FP32 filter can reach (10^-8, 10^-10 h_H):
+    the columns stuck at the FP32 rounding floor must turn FP64 together and
+    the solve still converge to the FP64 tolerance, in a bounded number of
+    iterations (the rule that once moved them one per iteration stalled)."""
+    p = workloads.make_problem(512, 0)
+    ref = oracle.solve(p.H, p.S, 51, 13, tol=1e-10, degree=10, seed=0)
+    ctx64 = lib.create(512, degree=10, seed=0)
+    _, _, info64, st64 = lib.solve(ctx64, _t(p.H), _t(p.S), 51, 13, tol=1e-10)
+    ctx = lib.create(512, degree=10, seed=0, precision=1, mixed_switch_digits=digits)
+    ev, X, info, st = lib.solve(ctx, _t(p.H), _t(p.S), 51, 13, tol=1e-10)
+    assert st == 0 and st64 == 0
+    assert info["iterations_fp32"] > 0
+    assert info["iterations"] <= 2 * info64["iterations"] + 10, (info["iterations"], info64["iterations"])
+    assert np.abs(ev - ref["evals"]).max() <= 1e-12 * 100
+    _check_solution(p, ev, _np(X), 51)
+
+
 def test_solve_ragged_sizes_against_brute_force(lib):
     n, nev, nex = 333, 17, 6
     p = workloads.make_problem(n, 41)
