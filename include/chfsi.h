@@ -123,7 +123,10 @@ chfsi_status chfsi_reset(chfsi_ctx ctx);
 chfsi_status chfsi_reduce(chfsi_ctx ctx, const void* H, int64_t ldh, const void* S, int64_t lds);
 
 /* Solve H x = lambda S x for the nev smallest eigenpairs with a search block
- * of k = nev + nex vectors (Algorithm 1 with locking).
+ * of k = nev + nex vectors (Algorithm 1 with locking).  Sizes: 1 <= nev,
+ * nev + nex <= n, and nex >= 1 unless nev = n (CHFSI_EINVAL otherwise): the
+ * filter damps the interval that starts at the block's largest Ritz value,
+ * which must not be a wanted one.
  *   H, S    device n x n; S == NULL reuses the cached factor of S (sequences
  *           with a fixed overlap matrix);
  *   V_warm  device n x kw approximate eigenvectors of the generalized problem

@@ -65,6 +65,16 @@ size_t splitk_columns(int64_t k) {
   return std::max((size_t)4 * k, std::min((size_t)8 * k, (size_t)2560));
 }
 
+// Block sizes of a solve: 1 <= nev, nev + nex <= n, and at least one extra
+// column unless the block is the whole space: the filter damps [a, b] with
+// a the largest Ritz value of the block, which must not be a wanted one (with
+// nex = 0 the nev-th wanted value sits on the damped interval's edge and its
+// convergence stalls).
+bool block_sizes_ok(int64_t n, int64_t nev, int64_t nex) {
+  return nev >= 1 && nex >= 0 && nev + nex <= n && (nex >= 1 || nev == n);
+}
+constexpr const char* BLOCK_SIZES_RULE = "need 1 <= nev, nev + nex <= n and nex >= 1 unless nev = n";
+
 // Coefficients of the m degree steps of the scaled Chebyshev filter
 // (eq. (3) on (A - cI)/e, normalized at a0): step i computes
 //   Y_{i+1} = alpha_i A Y_i + beta_i Y_i + gamma_i Y_{i-1}   (gamma_0 = 0).
@@ -899,7 +909,7 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
   const int64_t n = c->n;
   s.k = s.nev + s.nex;
   const int64_t k = s.k;
-  if (s.nev < 1 || s.nex < 0 || k > n) throw Error(ST_EINVAL, "need 1 <= nev and nev + nex <= n");
+  if (!block_sizes_ok(n, s.nev, s.nex)) throw Error(ST_EINVAL, BLOCK_SIZES_RULE);
   if (!(s.tol > 0.0)) throw Error(ST_EINVAL, "tol must be positive");
   if (s.kw < 0 || s.kw > k) throw Error(ST_EINVAL, "kw out of range");
   check_ptr(s.H, "H");
@@ -999,6 +1009,12 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
 void solve_filter_begin(SolveState& s) {
   s.it++;
   const int64_t ka = s.k - s.cl;
+  // The damped interval [a, b] must not be empty: when the Lanczos bound is
+  // exact (n at most the Lanczos steps) and the block spans the whole space,
+  // b equals the largest Ritz value a and the scaled recurrence would divide
+  // zero by zero.  Raising b by a relative 1e-8 changes nothing elsewhere.
+  s.b = std::max(s.b, s.a + 1e-8 * std::max(std::max(std::fabs(s.a), std::fabs(s.b)),
+                                             std::max(s.inf.h_H, 1e-300)));
   if (!s.mixed) {
     s.split = ka;
     return;
@@ -1548,7 +1564,7 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
     const std::string w = " (member " + std::to_string(j) + ")";
     if (!H[j]) throw Error(ST_EINVAL, "null H" + w);
     if (!evals[j]) throw Error(ST_EINVAL, "null evals" + w);
-    if (nev[j] < 1 || nex[j] < 0 || nev[j] + nex[j] > n) throw Error(ST_EINVAL, "need 1 <= nev and nev + nex <= n" + w);
+    if (!block_sizes_ok(n, nev[j], nex[j])) throw Error(ST_EINVAL, BLOCK_SIZES_RULE + w);
     if (ldh[j] < n) throw Error(ST_EINVAL, "ldh smaller than n" + w);
     if (S && S[j] && lds[j] < n) throw Error(ST_EINVAL, "lds smaller than n" + w);
     if (X && X[j] && ldx[j] < n) throw Error(ST_EINVAL, "ldx smaller than n" + w);
@@ -2129,7 +2145,7 @@ chfsi_status chfsi_server_submit(chfsi_server s, int64_t seq, int64_t n, const v
                                  int64_t lds, int64_t nev, int64_t nex, double tol, double* evals, void* X, int64_t ldx,
                                  int64_t* ticket) {
   if (!s || !ticket) return CHFSI_EINVAL;
-  if (n < 1 || nev < 1 || nex < 0 || nev + nex > n || !(tol > 0.0) || !H || !S || !evals || ldh < n || lds < n ||
+  if (n < 1 || !block_sizes_ok(n, nev, nex) || !(tol > 0.0) || !H || !S || !evals || ldh < n || lds < n ||
       (X && ldx < n))
     return CHFSI_EINVAL;
   std::unique_ptr<Req> r(new Req());

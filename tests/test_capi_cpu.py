@@ -77,6 +77,9 @@ def test_solve_argument_validation_without_device_work():
         # nev + nex > n
         assert lib.chfsi_solve(h, fake, 16, fake, 16, 10, 10, None, 16, 0, 1e-10, ev, None, 16, None) == -1
         assert b"nev" in lib.chfsi_last_error(h)
+        # no extra column while the block is not the whole space
+        assert lib.chfsi_solve(h, fake, 16, fake, 16, 4, 0, None, 16, 0, 1e-10, ev, None, 16, None) == -1
+        assert b"nex >= 1" in lib.chfsi_last_error(h)
         # tol <= 0
         assert lib.chfsi_solve(h, fake, 16, fake, 16, 4, 2, None, 16, 0, 0.0, ev, None, 16, None) == -1
         # leading dimension too small

@@ -503,6 +503,44 @@ def test_solve_mixed_precision_switch_below_fp32_floor(lib, digits):
     _check_solution(p, ev, _np(X), 51)
 
 
+@pytest.mark.parametrize("case", ["block is the space", "all eigenpairs", "n = 1", "n = 2", "S = I",
+                                  "diagonal H, S = I"])
+def test_solve_degenerate_cases_against_dense_solver(lib, case):
+    """The block spans the whole space (the Lanczos bound is exact for
+    n <= its steps, so the damped interval would be empty without its
+    guard), the smallest sizes, S = I and an already diagonal H."""
+    if case in ("block is the space", "all eigenpairs"):
+        p = workloads.make_problem(40, 5)
+        H, S = p.H, p.S
+        nev, nex = (30, 10) if case == "block is the space" else (40, 0)
+    elif case == "n = 1":
+        H, S, nev, nex = np.array([[2.5 + 0j]]), np.array([[2.0 + 0j]]), 1, 0
+    elif case == "n = 2":
+        H, S, nev, nex = np.array([[2.0, 1j], [-1j, 3.0]]), np.eye(2, dtype=complex), 1, 1
+    elif case == "S = I":
+        p = workloads.make_problem(100, 6)
+        H, S, nev, nex = p.A, np.eye(100, dtype=complex), 10, 4
+    else:
+        H, S, nev, nex = np.diag(np.linspace(-1, 5, 100)).astype(complex), np.eye(100, dtype=complex), 10, 4
+    n = H.shape[0]
+    ctx = lib.create(n, degree=10, seed=0)
+    ev, X, info, st = lib.solve(ctx, _t(H), _t(S), nev, nex, tol=1e-10)
+    assert st == 0
+    ref = sl.eigh(H, S, eigvals_only=True)[:nev]
+    hn = np.linalg.norm(H, 2)
+    assert np.abs(ev - ref).max() <= 1e-12 * hn
+    Xn = _np(X)
+    assert np.linalg.norm(H @ Xn - (S @ Xn) * ev[None, :], axis=0).max() <= 1e-10 * hn
+
+
+def test_solve_rejects_missing_extra_column(lib):
+    p = workloads.make_problem(100, 6)
+    ctx = lib.create(100)
+    with pytest.raises(lib.ChfsiError) as e:
+        lib.solve(ctx, _t(p.H), _t(p.S), 1, 0, tol=1e-10)
+    assert e.value.status == -1
+
+
 def test_solve_ragged_sizes_against_brute_force(lib):
     n, nev, nex = 333, 17, 6
     p = workloads.make_problem(n, 41)
