@@ -582,7 +582,11 @@ int32_t orc_solve(int64_t n, const cplx* H, int64_t ldh, const cplx* S, int64_t 
                   double* evals, cplx* X, int64_t ldx, cplx* Y_state, orc_info* info) {
   memset(info, 0, sizeof(*info));
   int64_t k = nev + nex;
-  if (n < 1 || nev < 1 || nex < 0 || k > n || !(tol > 0.0) || kw < 0 || kw > k) return info->status = -1;
+  /* sizes: at least one extra column unless the block is the whole space
+     (the damped interval starts at the block's largest Ritz value, which
+     must not be a wanted one) */
+  if (n < 1 || nev < 1 || nex < 0 || k > n || (nex == 0 && nev < n) || !(tol > 0.0) || kw < 0 || kw > k)
+    return info->status = -1;
   cplx* L = (cplx*)malloc(sizeof(cplx) * (size_t)n * (size_t)n);
   cplx* A = (cplx*)malloc(sizeof(cplx) * (size_t)n * (size_t)n);
   cplx* Y = (cplx*)malloc(sizeof(cplx) * (size_t)n * (size_t)k);
@@ -629,6 +633,14 @@ int32_t orc_solve(int64_t n, const cplx* H, int64_t ldh, const cplx* S, int64_t 
   info->status = -3;
   for (it = 1; it <= opt->max_iter; it++) {
     int64_t ka = k - c;
+    /* the damped interval [a, b] must not be empty: with the block spanning
+       the space and an exact Lanczos bound (n at most its steps) b equals a */
+    {
+      double scale = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+      if (info->h_H > scale) scale = info->h_H;
+      if (scale < 1e-300) scale = 1e-300;
+      if (b < a + 1e-8 * scale) b = a + 1e-8 * scale;
+    }
     orc_filter(n, A, n, &Y[(size_t)c * n], n, ka, opt->degree, a, b, a0);
     info->filter_flops += 8.0 * (double)n * (double)n * (double)ka * (double)opt->degree;
     /* QR of [Y_lock | Y_active] on a copy (the factorization overwrites its

@@ -392,3 +392,26 @@ def test_solve_rejects_bad_arguments():
     assert oracle.solve(p.H, p.S, 10, 10)["info"]["status"] == -1
     assert oracle.solve(p.H, p.S, 0, 2)["info"]["status"] == -1
     assert oracle.solve(p.H, p.S, 2, 2, tol=0.0)["info"]["status"] == -1
+    # no extra column while the block is not the whole space
+    assert oracle.solve(p.H, p.S, 2, 0)["info"]["status"] == -1
+
+
+@pytest.mark.parametrize("case", ["n = 1", "n = 2", "block is the space"])
+def test_solve_degenerate_sizes_against_dense_solver(case):
+    """The Lanczos bound is exact for n at most its steps, so with the block
+    spanning the space the damped interval would be empty; the solve must
+    still give the dense solver's eigenpairs."""
+    if case == "n = 1":
+        H, S, nev, nex = np.array([[2.5 + 0j]]), np.array([[2.0 + 0j]]), 1, 0
+    elif case == "n = 2":
+        H, S, nev, nex = np.array([[2.0, 1j], [-1j, 3.0]]), np.eye(2, dtype=complex), 1, 1
+    else:
+        p = workloads.make_problem(40, 5)
+        H, S, nev, nex = p.H, p.S, 30, 10
+    res = oracle.solve(H, S, nev, nex, tol=1e-10, degree=10, seed=0)
+    assert res["info"]["status"] == 0
+    ref = sl.eigh(H, S, eigvals_only=True)[:nev]
+    hn = np.linalg.norm(H, 2)
+    assert np.abs(res["evals"] - ref).max() <= 1e-12 * hn
+    X = res["X"]
+    assert np.linalg.norm(H @ X - (S @ X) * res["evals"][None, :], axis=0).max() <= 1e-10 * hn
