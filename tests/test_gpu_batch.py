@@ -141,6 +141,9 @@ def test_batch_rejects_bad_arguments(lib):
     with pytest.raises(lib.ChfsiError) as e:
         b.solve([_t(p0.H), _t(p1.H)], [_t(p0.S), _t(p1.S)], [10, 90], [2, 2], tol=1e-10)
     assert e.value.status == -1
+    with pytest.raises(lib.ChfsiError) as e:
+        b.solve([_t(p0.H), _t(p1.H)], [_t(p0.S), _t(p1.S)], [10, 10], [2, 0], tol=1e-10)  # no extra column
+    assert e.value.status == -1
     with pytest.raises(ValueError):
         b.solve([_t(p0.H)], [_t(p0.S)], [10], [2])
     with pytest.raises(lib.ChfsiError):

@@ -100,3 +100,15 @@ def test_server_rejects_request_larger_than_budget(lib, sequences):
     ev, X, info, lat, st = srv.wait(t, raise_on_error=False)
     assert st == -5
     srv.close()
+
+
+def test_server_rejects_invalid_block_sizes(lib, sequences):
+    """nev + nex above n, and no extra column while the block is not the
+    whole space, are refused at submission."""
+    p, H, S = sequences[0][0]
+    srv = lib.Server(workers=1, degree=10)
+    for nev, nex in ((p.n, 1), (10, 0)):
+        with pytest.raises(lib.ChfsiError) as e:
+            srv.submit(0, H, S, nev, nex)
+        assert e.value.status == -1
+    srv.close()
