@@ -416,15 +416,21 @@ def run_serve(args):
 
 
 def run_warmcold(args):
-    """Warm versus cold starts along a correlated sequence (fixed S and a
-    varying-S variant that goes through the generalized-space map of the
-    block), with the eigenvector correlation between consecutive problems."""
+    """Warm versus cold starts along correlated sequences: a fixed
+    perturbation with fixed S, the same with S varying (through the
+    generalized-space map of the block), and a converging cycle (fixed S,
+    perturbation 1e-2 shrinking tenfold per step).  Per step: iterations and
+    times of both starts and the angle theta between consecutive eigenvectors
+    in the S inner product (median over the wanted ones; sin(theta) from the
+    S-norm of the part of x_l orthogonal to x_(l-1), accurate for small
+    angles)."""
     import numpy as np
     import torch
     from paper_1305_5120_amd import chfsi
     import workloads
     n, nev, nex, steps = args.wc_n, args.wc_n // 10, max(1, args.wc_n // 100), args.seq_steps
     seq = list(workloads.make_sequence_torch(n, steps, 5, device="cuda"))
+    seq_c = list(workloads.make_sequence_torch(n, steps, 5, eps=1e-2, eps_decay=0.1, device="cuda"))
     S0 = seq[0]["S"]
     # varying-S variant: S_l = L_l L_l^H with L_l = L_0 + 1e-4 (strict lower Gaussian)/sqrt(n) per step
     gen = torch.Generator(device="cpu").manual_seed(55)
@@ -438,17 +444,27 @@ def run_warmcold(args):
     Hs_v = [((h + h.conj().T) / 2).mT.contiguous().mT for h in Hs_v]
     Ss_v = [((L @ L.conj().T + (L @ L.conj().T).conj().T) / 2).mT.contiguous().mT for L in Ls]
     torch.cuda.synchronize()
+
+    def theta_median(prevX, X, S):
+        c = torch.sum(prevX.conj() * (S @ X), dim=0)           # <x_(l-1), x_l>_S
+        R = X - prevX * c[None, :]                             # part orthogonal to x_(l-1)
+        sin = torch.sqrt(torch.clamp(torch.real(torch.sum(R.conj() * (S @ R), dim=0)), min=0.0))
+        th = torch.atan2(sin, torch.abs(c)).cpu().numpy()
+        return float(np.median(th))
+
     rows = {}
-    for variant in ("fixed_S", "varying_S"):
+    for variant in ("fixed_S", "varying_S", "converging"):
         warm = chfsi.create(n, degree=20, seed=0)
         cold = chfsi.create(n, degree=20, seed=0)
         prevX = None
         recs = []
         for ell in range(steps):
             if variant == "fixed_S":
-                H, S_w, S_c = seq[ell]["H"], (S0 if ell == 0 else None), S0
+                H, S_w, S_c, Sm = seq[ell]["H"], (S0 if ell == 0 else None), S0, S0
+            elif variant == "varying_S":
+                H, S_w, S_c, Sm = Hs_v[ell], Ss_v[ell], Ss_v[ell], Ss_v[ell]
             else:
-                H, S_w, S_c = Hs_v[ell], Ss_v[ell], Ss_v[ell]
+                H, S_w, S_c, Sm = seq_c[ell]["H"], (S0 if ell == 0 else None), S0, S0
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ev, X, iw, _ = chfsi.solve(warm, H, S_w, nev, nex, tol=1e-10)
@@ -459,16 +475,12 @@ def run_warmcold(args):
             evc, Xc, ic, _ = chfsi.solve(cold, H, S_c, nev, nex, tol=1e-10, want_vectors=False)
             torch.cuda.synchronize()
             tc = time.perf_counter() - t0
-            theta = None
-            if prevX is not None:
-                Sm = S0 if variant == "fixed_S" else Ss_v[ell]
-                c = torch.abs(torch.sum(prevX.conj() * (Sm @ X), dim=0)).cpu().numpy()
-                theta = float(np.median(1.0 - np.minimum(c, 1.0)))
+            theta = theta_median(prevX, X, Sm) if prevX is not None else None
             prevX = X
             recs.append({"step": ell, "warm_iterations": iw["iterations"], "cold_iterations": ic["iterations"],
-                         "warm_s": tw, "cold_s": tc, "warm_start": iw["warm_start"], "median_1_minus_corr": theta})
+                         "warm_s": tw, "cold_s": tc, "warm_start": iw["warm_start"], "median_theta": theta})
             log(f"[bench] {variant} step {ell}: warm {iw['iterations']} it {tw:.3f} s, cold {ic['iterations']} it "
-                f"{tc:.3f} s, 1-corr {theta}")
+                f"{tc:.3f} s, median theta {theta}")
         warm.release()
         cold.release()
         rows[variant] = recs
@@ -478,10 +490,12 @@ def run_warmcold(args):
                 steps - 1, 1, 1e3 * sum(x["warm_s"] for x in r) / len(r), "complex128 (f64)",
                 {"workload": "sequence of correlated complex Hermitian DGEVPs, FLAPW-shaped synthetic spectrum",
                  "n": n, "nev": nev, "nex": nex, "degree": 20, "tol": 1e-10, "steps": steps,
-                 "perturbation": 1e-4})
+                 "perturbation": 1e-4, "converging_perturbation": "1e-2 * 0.1**(step - 1)"})
     out["per_step"] = rows
     out["speedup_varying_S"] = (sum(x["cold_s"] for x in rows["varying_S"][1:]) /
                                 sum(x["warm_s"] for x in rows["varying_S"][1:]))
+    out["speedup_converging"] = (sum(x["cold_s"] for x in rows["converging"][1:]) /
+                                 sum(x["warm_s"] for x in rows["converging"][1:]))
     print(json.dumps(out), flush=True)
 
 

@@ -171,16 +171,17 @@ def make_problem_torch(n: int, seed: int, device="cuda"):
     return {"H": _colmajor(H), "S": _colmajor(S), "L": L, "A": A, "Q": Q, "lam": lam}
 
 
-def make_sequence_torch(n: int, steps: int, seed: int, eps: float = 1e-4, device="cuda"):
+def make_sequence_torch(n: int, steps: int, seed: int, eps: float = 1e-4, device="cuda", eps_decay: float = 1.0):
     """Device variant of make_sequence; yields dicts with H (and S, L for the
-    first problem)."""
+    first problem).  Step l (l >= 1) perturbs by eps * eps_decay**(l - 1)
+    (eps_decay < 1: a converging self-consistent cycle)."""
     import torch
     p0 = make_problem_torch(n, seed, device)
     yield p0
     rng = np.random.default_rng(seed + 1_000_003)
     A = p0["A"]
     L = p0["L"]
-    for _ in range(1, steps):
+    for step in range(1, steps):
         v = torch.from_numpy(_cgauss(np.random.default_rng(12345), (n,))).to(device)
         v = v / torch.linalg.vector_norm(v)
         s = 1.0
@@ -199,7 +200,7 @@ def make_sequence_torch(n: int, steps: int, seed: int, eps: float = 1e-4, device
             u = w / se
         E = E / math.sqrt(float(se))
         P = (E + E.conj().T) / 2
-        A = A + eps * nrm * P
+        A = A + eps * eps_decay ** (step - 1) * nrm * P
         A = (A + A.conj().T) / 2
         H = L @ A @ L.conj().T
         H = (H + H.conj().T) / 2
