@@ -171,11 +171,15 @@ __global__ void k_nonfinite(const zc* A, int64_t lda, int64_t n, int64_t k, int*
 // Inverse X = L^{-1} by recursive doubling: with X's diagonal blocks of size
 // s known, each pair of them gives the block below as -C^{-1} (B A^{-1}) for
 // L = [A 0; B C]; six levels s = 1, 2, ..., 32, each two small products
-// computed by all threads.
+// computed by all threads.  The sums run over whole blocks (the strictly
+// upper parts of A^{-1} and C^{-1} are zero), so every loop has a fixed trip
+// count and unrolls: 16 waves, four per SIMD, keep the LDS loads in flight.
 // --------------------------------------------------------------------------
 constexpr int CNB = CHOL_NB;
 constexpr int CLD = CNB + 1;  // LDS row stride (complex); keeps 16-lane groups on distinct banks
 constexpr int CPW = 8;        // panel width
+constexpr int CNT = 1024;     // threads of the diagonal-block kernel
+constexpr int CWV = CNT / 64; // its waves
 
 __device__ __forceinline__ double lane_read(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -183,20 +187,55 @@ __device__ __forceinline__ double lane_read(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-__global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi,
+// One doubling level of the inverse (block size SZ): for each of the
+// CNB / (2 SZ) pairs at origin o, X(o+SZ.., o..) = -C^{-1} (B A^{-1}) with
+// B = L(o+SZ.., o..), A^{-1} = X(o.., o..), C^{-1} = X(o+SZ.., o+SZ..).
+template <int SZ>
+__device__ __forceinline__ void chol_inv_level(const zc* S, zc* X, zc* T, int tid) {
+  constexpr int PER = SZ * SZ, TOTAL = (CNB / (2 * SZ)) * PER;
+  for (int e = tid; e < TOTAL; e += CNT) {
+    const int pair = e / PER, rem = e % PER, i = rem / SZ, j = rem % SZ, o = 2 * SZ * pair;
+    const zc* brow = S + (o + SZ + i) * CLD + o;
+    const zc* acol = X + o * CLD + o + j;
+    zc acc = zmk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < SZ; k++) {
+      const zc bv = brow[k], av = acol[k * CLD];
+      acc = zmk(fma(bv.x, av.x, fma(-bv.y, av.y, acc.x)), fma(bv.x, av.y, fma(bv.y, av.x, acc.y)));
+    }
+    T[e] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < TOTAL; e += CNT) {
+    const int pair = e / PER, rem = e % PER, i = rem / SZ, j = rem % SZ, o = 2 * SZ * pair;
+    const zc* crow = X + (o + SZ + i) * CLD + o + SZ;
+    const zc* tcol = T + pair * PER + j;
+    zc acc = zmk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < SZ; k++) {
+      const zc cv = crow[k], tv = tcol[k * SZ];
+      acc = zmk(fma(cv.x, tv.x, fma(-cv.y, tv.y, acc.x)), fma(cv.x, tv.y, fma(cv.y, tv.x, acc.y)));
+    }
+    X[(o + SZ + i) * CLD + o + j] = zmk(-acc.x, -acc.y);
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(CNT) k_chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi,
                                                     int64_t j0, int nb, int* info) {
-  static_assert(CNB == 64 && CNB % CPW == 0, "64 x 64 blocks, whole panels");
+  static_assert(CNB == 64 && CNB % CPW == 0 && CNB % CWV == 0, "64 x 64 blocks, whole panels");
+  constexpr int CPT = CNB / CWV;  // columns per thread in the element-wise loops
   extern __shared__ zc smem[];
   zc* S = smem;                // S[r * CLD + c]: the matrix, then L (lower triangle)
-  zc* X = smem + CNB * CLD;    // X[r * CLD + c]: L^{-1} (lower triangle)
+  zc* X = smem + CNB * CLD;    // X[r * CLD + c]: L^{-1} (lower triangle, zero above)
   zc* T = X + CNB * CLD;       // scratch of the inverse: up to CNB * CNB / 4 entries
   __shared__ int failed;
   const int tid = threadIdx.x;
   const int r = tid & 63;
   const int q = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
-  for (int t = 0; t < 16; t++) {
-    const int c = q + 4 * t;
+  for (int t = 0; t < CPT; t++) {
+    const int c = q + CWV * t;
     zc v = zmk(r == c ? 1.0 : 0.0, 0.0);
     if (r < nb && c < nb) v = r >= c ? W[(j0 + r) + (j0 + c) * ldw] : zmk(0.0, 0.0);
     S[r * CLD + c] = v;
@@ -238,20 +277,22 @@ __global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc*
     __syncthreads();
     if (failed >= 0) break;
     // trailing update: columns c >= jb + CPW, rows r >= c
-    zc lr[CPW];
+    if (q + CWV * (CPT - 1) >= jb + CPW) {  // this wave owns a trailing column (uniform)
+      zc lr[CPW];
 #pragma unroll
-    for (int i = 0; i < CPW; i++) lr[i] = S[r * CLD + jb + i];
+      for (int i = 0; i < CPW; i++) lr[i] = S[r * CLD + jb + i];
 #pragma unroll
-    for (int t = 0; t < 16; t++) {
-      const int c = q + 4 * t;
-      if (c >= jb + CPW) {  // uniform over the wave
-        zc acc = S[r * CLD + c];
+      for (int t = 0; t < CPT; t++) {
+        const int c = q + CWV * t;
+        if (c >= jb + CPW) {  // uniform over the wave
+          zc acc = S[r * CLD + c];
 #pragma unroll
-        for (int i = 0; i < CPW; i++) {
-          const zc lc = S[c * CLD + jb + i];
-          acc = zmk(fma(-lr[i].x, lc.x, fma(-lr[i].y, lc.y, acc.x)), fma(-lr[i].y, lc.x, fma(lr[i].x, lc.y, acc.y)));
+          for (int i = 0; i < CPW; i++) {
+            const zc lc = S[c * CLD + jb + i];
+            acc = zmk(fma(-lr[i].x, lc.x, fma(-lr[i].y, lc.y, acc.x)), fma(-lr[i].y, lc.x, fma(lr[i].x, lc.y, acc.y)));
+          }
+          if (r >= c) S[r * CLD + c] = acc;
         }
-        if (r >= c) S[r * CLD + c] = acc;
       }
     }
     __syncthreads();
@@ -262,39 +303,19 @@ __global__ void __launch_bounds__(256) k_chol_diag(const zc* W, int64_t ldw, zc*
   }
   // L out (the matrix is final)
 #pragma unroll
-  for (int t = 0; t < 16; t++) {
-    const int c = q + 4 * t;
+  for (int t = 0; t < CPT; t++) {
+    const int c = q + CWV * t;
     if (r < nb && c < nb) L[(j0 + r) + (j0 + c) * ldl] = r >= c ? S[r * CLD + c] : zmk(0.0, 0.0);
   }
-  // inverse by recursive doubling
-  for (int sz = 1; sz < CNB; sz *= 2) {
-    const int per = sz * sz, total = (CNB / (2 * sz)) * per;
-    // T = B A^{-1} for every pair (B = L[o+sz.., o..], A^{-1} = X[o.., o..])
-    for (int e = tid; e < total; e += 256) {
-      const int pair = e / per, rem = e % per, i = rem / sz, j = rem % sz, o = 2 * sz * pair;
-      zc acc = zmk(0.0, 0.0);
-      for (int k = j; k < sz; k++) {
-        const zc bv = S[(o + sz + i) * CLD + o + k], av = X[(o + k) * CLD + o + j];
-        acc = zmk(fma(bv.x, av.x, fma(-bv.y, av.y, acc.x)), fma(bv.x, av.y, fma(bv.y, av.x, acc.y)));
-      }
-      T[e] = acc;
-    }
-    __syncthreads();
-    // X[o+sz.., o..] = -C^{-1} T
-    for (int e = tid; e < total; e += 256) {
-      const int pair = e / per, rem = e % per, i = rem / sz, j = rem % sz, o = 2 * sz * pair;
-      zc acc = zmk(0.0, 0.0);
-      for (int k = 0; k <= i; k++) {
-        const zc cv = X[(o + sz + i) * CLD + o + sz + k], tv = T[pair * per + k * sz + j];
-        acc = zmk(fma(cv.x, tv.x, fma(-cv.y, tv.y, acc.x)), fma(cv.x, tv.y, fma(cv.y, tv.x, acc.y)));
-      }
-      X[(o + sz + i) * CLD + o + j] = zmk(-acc.x, -acc.y);
-    }
-    __syncthreads();
-  }
+  chol_inv_level<1>(S, X, T, tid);
+  chol_inv_level<2>(S, X, T, tid);
+  chol_inv_level<4>(S, X, T, tid);
+  chol_inv_level<8>(S, X, T, tid);
+  chol_inv_level<16>(S, X, T, tid);
+  chol_inv_level<32>(S, X, T, tid);
 #pragma unroll
-  for (int t = 0; t < 16; t++) {
-    const int c = q + 4 * t;
+  for (int t = 0; t < CPT; t++) {
+    const int c = q + CWV * t;
     if (r < nb && c < nb) Linv[(j0 + r) + (j0 + c) * ldi] = r >= c ? X[r * CLD + c] : zmk(0.0, 0.0);
   }
 }
@@ -1148,7 +1169,7 @@ void chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t l
     CHFSI_HIP(hipFuncSetAttribute((const void*)k_chol_diag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   });
   if (nb < 1 || nb > CNB) throw Error(ST_EINVAL, "chol_diag: block size out of range");
-  LAUNCH(k_chol_diag, dim3(1), dim3(256), shm, st, W, ldw, L, ldl, Linv, ldi, j0, (int)nb, info);
+  LAUNCH(k_chol_diag, dim3(1), dim3(CNT), shm, st, W, ldw, L, ldl, Linv, ldi, j0, (int)nb, info);
 }
 
 void hh_panel_setup(HHPanel& p) {
