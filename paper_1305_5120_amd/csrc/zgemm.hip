@@ -11,8 +11,9 @@
 // form, Householder block updates, Rayleigh-Ritz, back-transform).
 //
 // Design (CDNA4):
-//   * 256 threads = 4 waves in a 2x2 arrangement; a workgroup owns a BM x BN
-//     complex output tile, each wave (BM/2) x (BN/2) of it as 16x16 blocks;
+//   * 256 threads = 4 waves in a 2x2 arrangement (4x1 for tiles 48 columns
+//     wide); a workgroup owns a BM x BN complex output tile, each wave
+//     (BM/2) x (BN/2) (or (BM/4) x BN) of it as 16x16 blocks;
 //   * complex products as real v_mfma_f64_16x16x4f64 per 16x16x4 block:
 //     four of them into separate real / imaginary accumulators, or, where
 //     the registers allow, three (Gauss's 3M form: the sums of operand parts are
@@ -70,12 +71,16 @@ struct ZTile {
   static constexpr int LDB_S = BN + PAD;
   static constexpr int EA = BM * BK / NT;  // A elements per thread per slab
   static constexpr int EB = BK * BN / NT;  // B elements per thread per slab
-  static constexpr int MI = BM / 32;       // 16-row fragments per wave (2x2 waves)
-  static constexpr int NJ = BN / 32;       // 16-col fragments per wave
+  // waves along M: 2 (2x2 waves) where half the tile width is a whole
+  // number of 16-column fragments, else 4 (4x1, e.g. 48 columns)
+  static constexpr int WMW = (BN % 32 == 0) ? 2 : 4;
+  static constexpr int MI = BM / (16 * WMW);       // 16-row fragments per wave
+  static constexpr int NJ = BN / (16 * (4 / WMW)); // 16-col fragments per wave
   static constexpr int KS = BK / 4;        // MFMA depth steps per slab
   static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
   static_assert(BM * BK % NT == 0 && BK * BN % NT == 0, "tile/thread mismatch");
   static_assert(BK % 4 == 0, "BK multiple of the MFMA depth");
+  static_assert(MI >= 1 && NJ >= 1 && BM % (16 * WMW) == 0 && BN % (16 * (4 / WMW)) == 0, "wave fragments");
 };
 
 // Workgroup -> tile order with the XCD-aware remap (workgroup i runs on XCD
@@ -103,8 +108,8 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int wm0 = (wave & 1) * (BM / 2);
-  const int wn0 = (wave >> 1) * (BN / 2);
+  const int wm0 = (wave % T::WMW) * (BM / T::WMW);
+  const int wn0 = (wave / T::WMW) * (BN / (4 / T::WMW));
 
   const int64_t mt = t / p.tiles_n, nt = t % p.tiles_n;
   const int64_t m0 = mt * BM, n0 = nt * BN;
@@ -535,7 +540,7 @@ __global__ void zgemm_splitk_reduce(ZGemmParams p) { splitk_reduce_body<PF64>(p)
 __global__ void chebyshev_step_reduce_f64(ZGemmParams p) { splitk_reduce_body<PF64>(p); }
 __global__ void chebyshev_step_reduce_f32(ZGemmParams p) { splitk_reduce_body<PF32>(p); }
 
-// Tile configurations.  All use 256 threads (2x2 waves).
+// Tile configurations.  All use 256 threads (2x2 waves; 4x1 for 48 columns).
 struct Cfg {
   int bm, bn, bk, minb;
   double eff;  // relative per-tile efficiency used by the chooser
@@ -551,6 +556,7 @@ constexpr Cfg CFGS[] = {
     {64, 32, 16, 2, 0.8},     // 7
     {64, 64, 8, 4, 1.0},      // 8: as 3 with room for four workgroups per CU
     {64, 32, 16, 4, 0.8},     // 9: as 7 with room for four workgroups per CU
+    {64, 48, 16, 2, 0.9},     // 10: 48 columns (4x1 waves) for active widths that pad 64 / 32
 };
 constexpr int NCFG = sizeof(CFGS) / sizeof(CFGS[0]);
 
@@ -586,6 +592,7 @@ void launch_f32(int cfg, ZGemmParams& p, int batch, hipStream_t st) {
     case 7: launch_one_f32<64, 32, 16, 2>(p, batch, st); break;
     case 8: launch_one_f32<64, 64, 8, 4>(p, batch, st); break;
     case 9: launch_one_f32<64, 32, 16, 4>(p, batch, st); break;
+    case 10: launch_one_f32<64, 48, 16, 2>(p, batch, st); break;
     default: throw Error(ST_EINVAL, "cgemm: bad tile configuration");
   }
 }
@@ -605,6 +612,7 @@ void launch_cfg(int cfg, ZGemmParams& p, int batch, bool filter_step, hipStream_
           case 6: launch_one<OPA, OPB, 128, 128, 8, 1>(p, batch, filter_step, st); return;
           case 8: launch_one<OPA, OPB, 64, 64, 8, 4>(p, batch, filter_step, st); return;
           case 9: launch_one<OPA, OPB, 64, 32, 16, 4>(p, batch, filter_step, st); return;
+          case 10: launch_one<OPA, OPB, 64, 48, 16, 2>(p, batch, filter_step, st); return;
           default: break;
         }
       }
@@ -699,6 +707,13 @@ void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const i
 // Choose the tile configuration and the K split: maximise the estimated
 // throughput = per-tile efficiency x occupancy of the chip's workgroup slots
 // (256 CUs x workgroups per CU), charging split-K for its partial-tile traffic.
+// Cost per computed column of the 48- and 32-wide filter tiles relative to
+// the 64-wide tile's (FP64, tall deep products; a sweep of active widths 24
+// to 440 at n = 4000 on MI355X: the 48-wide tile's 4x1 waves read more LDS
+// per matrix-core product).  With these weights the rule picks the fastest
+// of the three at every width of the sweep.
+constexpr double W48_COST = 1.10, W32_COST = 1.08;
+
 void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   const int batch = g.batch > 0 ? g.batch : 1;
   const bool nn = g.opA == OP_N && g.opB == OP_N;
@@ -709,13 +724,23 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   // does.  K is split so that each workgroup's range stays near 1000 (the A
   // panels of the workgroups resident on one XCD then fit its 4 MB L2), and
   // further where the tiles alone would leave the CUs short of work (FP32
-  // steps are shorter and want about twice as many workgroups).
+  // steps are shorter and want about twice as many workgroups).  FP64: the
+  // tile width (64, 48 or 32 columns) that computes the fewest padded
+  // columns, each width's columns weighted by its measured cost relative
+  // to the 64-wide tile's.
   if (nn && batch == 1 && g.M >= 1024 && g.K >= 1024 && !(g.flags & GEMM_OUT_LOWER)) {
     const bool f32 = g.prec == PREC_F32;
     const double pad64 = (double)(cdiv(g.N, (int64_t)64) * 64) / (double)g.N;
     const double pad32 = (double)(cdiv(g.N, (int64_t)32) * 32) / (double)g.N;
-    // (FP32 blocks of 97-128 columns: the 64 x 128 x 8 tile, one column tile)
-    const int c = (f32 && g.N > 96 && g.N <= 128) ? 5 : (pad64 <= 1.08 * pad32 ? 1 : 7);
+    int c;
+    if (f32) {
+      // (blocks of 97-128 columns: the 64 x 128 x 8 tile, one column tile)
+      c = (g.N > 96 && g.N <= 128) ? 5 : (pad64 <= 1.08 * pad32 ? 1 : 7);
+    } else {
+      const double cost64 = pad64, cost48 = W48_COST * (double)(cdiv(g.N, (int64_t)48) * 48) / (double)g.N,
+                   cost32 = W32_COST * pad32;
+      c = cost64 <= cost48 && cost64 <= cost32 ? 1 : (cost48 <= cost32 ? 10 : 7);
+    }
     int sk = g.K < 1500 ? 1 : g.K < 3000 ? 2 : g.K < 7000 ? 4 : 8;
     if (f32) sk = std::min(8, 2 * sk);
     const int64_t tiles = cdiv(g.M, (int64_t)CFGS[c].bm) * cdiv(g.N, (int64_t)CFGS[c].bn);

@@ -178,7 +178,7 @@ def test_filter_matches_oracle(lib, n, k, m):
     assert _rel(_np(Yt), ref) <= 1e-12
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 8, 9])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 8, 9, 10])
 def test_filter_every_tile_shape_matches_oracle(lib, tile):
     """Every tile configuration of the filter step, those forming complex
     products with three real products (64 x 64 and smaller at two
