@@ -124,7 +124,7 @@ struct chfsi_ctx_s {
   // Lanczos
   DBuf LV, Lw, Lh, Lab, mvpart, Tsm, Tz, Tz2, Tw, npart;
   // sparse Jacobi schedules
-  DBuf jint, jrot;
+  DBuf jint, jrot, bjv;
   // eigenvector refinement: six k x k blocks, Rayleigh quotients, max correction
   DBuf rf, rfl, rfc;
   // host staging (pinned)
@@ -387,14 +387,13 @@ struct chfsi_ctx_s {
     // coupling above REF_ETA times the gap of their diagonal entries) are
     // few, a sparse sweep rotates only those; else a sparse sweep over all
     // significant couplings (|g|^2 > 1e-34 ||G||_F^2) when they are few, or
-    // a dense sweep of the parallel (round-robin) ordering.  Sparse sweeps
-    // group their pairs into disjoint rounds.
-    zc *g0 = G2.z(), *z0 = Ztmp.z(), *g1 = Z2.z();
-    zc* z1 = Wz.z();  // Wz (n x k) doubles as the second Z buffer
+    // a dense sweep in a block ordering (blocks of 16 indices paired
+    // round-robin, each pair's 32 x 32 subproblem swept in LDS).  Sparse
+    // sweeps group their pairs into disjoint rounds.
+    zc *g0 = G2.z(), *z0 = Ztmp.z();
     jacobi_init(Gp, ldg, k, g0, z0, st);
     double* nr = norms.d();
     jacobi_norms(g0, k, npart.d(), nr, st);  // nr[0] = off, nr[1] = all (fro2)
-    const int64_t K2 = k + (k & 1);
     const double THR = 1e-34;
     const int64_t max_sparse = 8 * k;
     const int max_rounds = 64;
@@ -475,13 +474,12 @@ struct chfsi_ctx_s {
       const int64_t total = sparse_sweep(0.0);
       if (total == 0) break;
       if (total > 0) continue;
-      // dense sweep
+      // dense sweep, block-ordered (two launches per round of blocks)
       fill_i32(flags.i() + 1, 1, 0, st);
-      for (int64_t r = 0; r < K2 - 1; r++) {
-        jacobi_round(g0, g1, z0, z1, k, r, nr + 1, flags.i() + 1, st, tau);
-        std::swap(g0, g1);
-        std::swap(z0, z1);
-      }
+      bjv.ensure(block_jacobi_v_bytes(k));
+      const int64_t nrounds = block_jacobi_rounds(k);
+      for (int64_t r = 0; r < nrounds; r++)
+        block_jacobi_round(g0, z0, k, r, nr + 1, tau, bjv.z(), flags.i() + 1, st);
     }
     jacobi_sort(g0, z0, k, w, rank.i(), Zo, ldz, st);
   }

@@ -702,58 +702,219 @@ __global__ void k_jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z
   Z0[e] = zmk(i == j ? 1.0 : 0.0, 0.0);
 }
 
-__global__ void k_jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
-                               double tau2, int* rotated) {
-  const int64_t K2 = k + (k & 1), half = K2 / 2;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// ---- block sweeps: cyclic Jacobi in a block ordering ---------------------
+// The indices are cut into blocks of BJB (the last one ragged; a phantom
+// block makes the count even) and the blocks are paired round-robin.  In a
+// round every pair of blocks (P, Q) is one 2 BJB x 2 BJB subproblem: one
+// workgroup runs one cyclic sweep over its 2 BJB indices in LDS (every
+// index pair of P u Q once), accumulating the rotations in V; then every
+// off-diagonal tile of G between two pairs' index sets is updated as
+// V_s^H G(I_s, I_t) V_t and Z's columns as Z(:, I_t) V_t.  Over the rounds
+// every index pair (i, j) is rotated at least once, which makes a round set
+// one sweep of cyclic Jacobi in a block ordering; a sweep takes 2 launches
+// per round instead of one launch per scalar round.
+constexpr int BJB = 16;
+constexpr int BJS = 2 * BJB;   // subproblem size
+constexpr int BJL = BJS + 1;   // LDS leading dimension
+
+// Global index of local index l (0 .. BJS-1) of the pair (P, Q); -1 outside
+// the matrix (ragged last block, phantom block).
+__device__ __forceinline__ int bjac_index(int64_t P, int64_t Q, int l, int64_t k, int64_t nb) {
+  const int64_t blk = l < BJB ? P : Q;
+  const int64_t g = blk * BJB + (l % BJB);
+  return (blk < nb && g < k) ? (int)g : -1;
+}
+
+__global__ void __launch_bounds__(256) k_bjac_solve(zc* G, int64_t k, int64_t nb, int64_t NB2, int64_t round,
+                                                    const double* fro2, double tau2, zc* V, int* rotated) {
+  __shared__ zc S[BJS * BJL];   // the subproblem, column-major
+  __shared__ zc Vs[BJS * BJL];  // its accumulated rotations
+  __shared__ Rot prm[BJB];
+  __shared__ int pidx[BJB], qidx[BJB], gi[BJS];
+  __shared__ int any;
+  const int tid = threadIdx.x;
+  int64_t P, Q;
+  round_pair(NB2, round, blockIdx.x, P, Q);
+  if (tid < BJS) gi[tid] = bjac_index(P, Q, tid, k, nb);
+  if (tid == 0) any = 0;
+  __syncthreads();
+  for (int e = tid; e < BJS * BJS; e += blockDim.x) {
+    const int l = e % BJS, m = e / BJS;
+    const int a = gi[l], b = gi[m];
+    zc v = zmk(0.0, 0.0);
+    if (a >= 0 && b >= 0) {
+      v = G[a + (int64_t)b * k];
+      if (l == m) v.y = 0.0;
+    }
+    S[l + m * BJL] = v;
+    Vs[l + m * BJL] = zmk(l == m ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
   const double skip2 = fmax(1e-36 * fro2[0], tau2);
-  auto rot_of = [&](int64_t t, int64_t& p, int64_t& q) -> Rot {
-    round_pair(K2, round, t, p, q);
-    if (q >= k) {
+  constexpr int NBLK = BJB * (BJB + 1) / 2;
+  for (int r = 0; r < BJS - 1; r++) {
+    if (tid < BJB) {
+      int64_t p, q;
+      round_pair(BJS, r, tid, p, q);
+      pidx[tid] = (int)p;
+      qidx[tid] = (int)q;
       Rot R;
       R.c = 1.0; R.s = 0.0; R.ur = 1.0; R.ui = 0.0; R.tg = 0.0; R.active = 0;
-      return R;
+      if (gi[p] >= 0 && gi[q] >= 0) {
+        R = make_rot(S[p + p * BJL], S[q + q * BJL], S[p + q * BJL], skip2);
+        if (R.active) any = 1;
+      }
+      prm[tid] = R;
     }
-    return make_rot(Gin[p + p * k], Gin[q + q * k], Gin[p + q * k], skip2);
-  };
-  if (e < half * half) {
-    const int64_t rt = e % half, st = e / half;
-    int64_t pr, qr, ps, qs;
-    const Rot Rr = rot_of(rt, pr, qr);
-    const Rot Rs = rot_of(st, ps, qs);
-    const bool qrv = qr < k, qsv = qs < k;
-    zc b00 = Gin[pr + ps * k];
-    zc b01 = qsv ? Gin[pr + qs * k] : zmk(0.0, 0.0);
-    zc b10 = qrv ? Gin[qr + ps * k] : zmk(0.0, 0.0);
-    zc b11 = (qrv && qsv) ? Gin[qr + qs * k] : zmk(0.0, 0.0);
-    if (Rr.active || Rs.active) {
+    __syncthreads();
+    // 2x2 blocks of pair rows rt >= pair columns st, mirrored (S Hermitian);
+    // indices outside the matrix have zero rows and columns and inactive
+    // rotations, so they stay decoupled
+    for (int e = tid; e < NBLK; e += blockDim.x) {
+      int rt = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while (rt * (rt + 1) / 2 > e) rt--;
+      while ((rt + 1) * (rt + 2) / 2 <= e) rt++;
+      const int st = e - rt * (rt + 1) / 2;
+      const Rot& Rr = prm[rt];
+      const Rot& Rs = prm[st];
+      if (!Rr.active && !Rs.active) continue;
+      const int pr = pidx[rt], qr = qidx[rt], ps = pidx[st], qs = qidx[st];
+      zc b00 = S[pr + ps * BJL], b01 = S[pr + qs * BJL], b10 = S[qr + ps * BJL], b11 = S[qr + qs * BJL];
       if (rt == st) {
         const double app = b00.x, aqq = b11.x;
         b00 = zmk(app - Rr.tg, 0.0);
         b11 = zmk(aqq + Rr.tg, 0.0);
         b01 = zmk(0.0, 0.0);
         b10 = zmk(0.0, 0.0);
-        *rotated = 1;
       } else {
         rot_block(Rr, Rs, b00, b01, b10, b11);
       }
+      S[pr + ps * BJL] = b00;
+      S[pr + qs * BJL] = b01;
+      S[qr + ps * BJL] = b10;
+      S[qr + qs * BJL] = b11;
+      if (rt != st) {
+        S[ps + pr * BJL] = zconj(b00);
+        S[qs + pr * BJL] = zconj(b01);
+        S[ps + qr * BJL] = zconj(b10);
+        S[qs + qr * BJL] = zconj(b11);
+      }
     }
-    Gout[pr + ps * k] = b00;
-    if (qsv) Gout[pr + qs * k] = b01;
-    if (qrv) Gout[qr + ps * k] = b10;
-    if (qrv && qsv) Gout[qr + qs * k] = b11;
+    for (int e = tid; e < BJS * BJB; e += blockDim.x) {
+      const int i = e % BJS, st = e / BJS;
+      const Rot& Rs = prm[st];
+      if (!Rs.active) continue;
+      const int ps = pidx[st], qs = qidx[st];
+      zc zp = Vs[i + ps * BJL], zq = Vs[i + qs * BJL];
+      rot_cols(Rs, zp, zq);
+      Vs[i + ps * BJL] = zp;
+      Vs[i + qs * BJL] = zq;
+    }
+    __syncthreads();
+  }
+  // the pair's diagonal tile of G and its rotations out
+  zc* Vo = V + (int64_t)blockIdx.x * BJS * BJS;
+  for (int e = tid; e < BJS * BJS; e += blockDim.x) {
+    const int l = e % BJS, m = e / BJS;
+    const int a = gi[l], b = gi[m];
+    if (a >= 0 && b >= 0) G[a + (int64_t)b * k] = S[l + m * BJL];
+    Vo[e] = Vs[l + m * BJL];
+  }
+  if (tid == 0 && any) *rotated = 1;
+}
+
+// Workgroups [0, NP (NP - 1) / 2): tile (s, t), s > t, of G between pair s's
+// and pair t's index sets, G(I_s, I_t) <- V_s^H G(I_s, I_t) V_t, and its
+// mirror G(I_t, I_s) <- the conjugate transpose; then NP * ceil(k / BJS)
+// workgroups: Z(rows, I_t) <- Z(rows, I_t) V_t.  Each workgroup reads and
+// writes only its own tile (and the mirror, which no workgroup reads), so
+// the update is in place.
+__global__ void __launch_bounds__(256) k_bjac_update(zc* G, zc* Z, int64_t k, int64_t nb, int64_t NB2, int64_t round,
+                                                     const zc* V) {
+  static_assert(BJS * BJS % 256 == 0, "whole tiles per workgroup");
+  constexpr int PER = BJS * BJS / 256;  // tile entries per thread
+  __shared__ zc Ts[BJS * BJL];          // the tile, then G(I_s, I_t) V_t
+  __shared__ zc Va[BJS * BJL];
+  __shared__ zc Vb[BJS * BJL];
+  __shared__ int ga[BJS], gb[BJS];
+  const int tid = threadIdx.x;
+  const int64_t NP = NB2 / 2;
+  const int64_t ntile = NP * (NP - 1) / 2;
+  const int64_t bid = blockIdx.x;
+  if (bid < ntile) {
+    int64_t s = (int64_t)((sqrt(8.0 * (double)bid + 1.0) + 1.0) * 0.5);
+    while (s * (s - 1) / 2 > bid) s--;
+    while ((s + 1) * s / 2 <= bid) s++;
+    const int64_t t = bid - s * (s - 1) / 2;  // 0 <= t < s
+    int64_t Ps, Qs, Pt, Qt;
+    round_pair(NB2, round, s, Ps, Qs);
+    round_pair(NB2, round, t, Pt, Qt);
+    if (tid < BJS) {
+      ga[tid] = bjac_index(Ps, Qs, tid, k, nb);
+      gb[tid] = bjac_index(Pt, Qt, tid, k, nb);
+    }
+    __syncthreads();
+    const zc* V_s = V + s * BJS * BJS;
+    const zc* V_t = V + t * BJS * BJS;
+    for (int e = tid; e < BJS * BJS; e += blockDim.x) {
+      const int l = e % BJS, m = e / BJS;
+      const int a = ga[l], b = gb[m];
+      Ts[l + m * BJL] = (a >= 0 && b >= 0) ? G[a + (int64_t)b * k] : zmk(0.0, 0.0);
+      Va[l + m * BJL] = V_s[e];
+      Vb[l + m * BJL] = V_t[e];
+    }
+    __syncthreads();
+    zc w[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u, l = e % BJS, m = e / BJS;
+      zc acc = zmk(0.0, 0.0);
+#pragma unroll 8
+      for (int j = 0; j < BJS; j++) acc = zadd(acc, zmul(Ts[l + j * BJL], Vb[j + m * BJL]));
+      w[u] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
+      Ts[e % BJS + (e / BJS) * BJL] = w[u];
+    }
+    __syncthreads();
+    for (int e = tid; e < BJS * BJS; e += blockDim.x) {
+      const int l = e % BJS, m = e / BJS;
+      const int a = ga[l], b = gb[m];
+      zc acc = zmk(0.0, 0.0);
+#pragma unroll 8
+      for (int j = 0; j < BJS; j++) acc = zadd(acc, zcmul(Va[j + l * BJL], Ts[j + m * BJL]));
+      if (a >= 0 && b >= 0) {
+        G[a + (int64_t)b * k] = acc;
+        G[b + (int64_t)a * k] = zconj(acc);
+      }
+    }
     return;
   }
-  const int64_t e2 = e - half * half;
-  if (e2 >= k * half) return;
-  const int64_t i = e2 % k, st = e2 / k;
-  int64_t ps, qs;
-  const Rot Rs = rot_of(st, ps, qs);
-  zc zp = Zin[i + ps * k];
-  zc zq = qs < k ? Zin[i + qs * k] : zmk(0.0, 0.0);
-  if (Rs.active) rot_cols(Rs, zp, zq);
-  Zout[i + ps * k] = zp;
-  if (qs < k) Zout[i + qs * k] = zq;
+  const int64_t zb = bid - ntile;
+  const int64_t t = zb % NP, r0 = (zb / NP) * BJS;
+  int64_t Pt, Qt;
+  round_pair(NB2, round, t, Pt, Qt);
+  if (tid < BJS) gb[tid] = bjac_index(Pt, Qt, tid, k, nb);
+  __syncthreads();
+  const zc* V_t = V + t * BJS * BJS;
+  for (int e = tid; e < BJS * BJS; e += blockDim.x) {
+    const int i = e % BJS, m = e / BJS;
+    const int b = gb[m];
+    Ts[i + m * BJL] = (r0 + i < k && b >= 0) ? Z[(r0 + i) + (int64_t)b * k] : zmk(0.0, 0.0);
+    Vb[i + m * BJL] = V_t[e];
+  }
+  __syncthreads();
+  for (int e = tid; e < BJS * BJS; e += blockDim.x) {
+    const int i = e % BJS, m = e / BJS;
+    const int b = gb[m];
+    zc acc = zmk(0.0, 0.0);
+#pragma unroll 8
+    for (int j = 0; j < BJS; j++) acc = zadd(acc, zmul(Ts[i + j * BJL], Vb[j + m * BJL]));
+    if (r0 + i < k && b >= 0) Z[(r0 + i) + (int64_t)b * k] = acc;
+  }
 }
 
 // ---- sparse sweeps: only the pairs whose coupling is significant ----------
@@ -1215,11 +1376,23 @@ void jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0, hipStream_
   LAUNCH(k_jacobi_init, grid1(k * k), dim3(NT), 0, st, G, ldg, k, G0, Z0);
 }
 
-void jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
-                  int* rotated, hipStream_t st, double tau) {
-  const int64_t half = (k + (k & 1)) / 2;
-  LAUNCH(k_jacobi_round, grid1(half * half + k * half), dim3(NT), 0, st, Gin, Gout, Zin, Zout, k, round, fro2, tau * tau,
-         rotated);
+size_t block_jacobi_v_bytes(int64_t k) {
+  const int64_t nb = cdiv(k, (int64_t)BJB), NB2 = nb + (nb & 1);
+  return (size_t)(NB2 / 2) * BJS * BJS * sizeof(zc);
+}
+
+void block_jacobi_round(zc* G, zc* Z, int64_t k, int64_t round, const double* fro2, double tau, zc* V, int* rotated,
+                        hipStream_t st) {
+  const int64_t nb = cdiv(k, (int64_t)BJB), NB2 = nb + (nb & 1), NP = NB2 / 2;
+  if (k < 1 || round < 0 || round >= NB2 - 1) throw Error(ST_EINVAL, "block_jacobi_round: bad size or round");
+  LAUNCH(k_bjac_solve, dim3((unsigned)NP), dim3(256), 0, st, G, k, nb, NB2, round, fro2, tau * tau, V, rotated);
+  const int64_t grid = NP * (NP - 1) / 2 + NP * cdiv(k, (int64_t)BJS);
+  LAUNCH(k_bjac_update, dim3((unsigned)grid), dim3(256), 0, st, G, Z, k, nb, NB2, round, (const zc*)V);
+}
+
+int64_t block_jacobi_rounds(int64_t k) {
+  const int64_t nb = cdiv(k, (int64_t)BJB);
+  return nb + (nb & 1) - 1;
 }
 
 void jacobi_count(const zc* G, int64_t k, const double* fro2, double thr_factor, double tau, double ratio, int* counts,

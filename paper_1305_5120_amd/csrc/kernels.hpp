@@ -71,8 +71,6 @@ void jacobi_small(const zc* G, int64_t ldg, int64_t k, double* w, zc* Z, int64_t
                   hipStream_t st, double tau = 0.0);
 // Multi-launch pieces for larger k.
 void jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z0, hipStream_t st);
-void jacobi_round(const zc* Gin, zc* Gout, const zc* Zin, zc* Zout, int64_t k, int64_t round, const double* fro2,
-                  int* rotated, hipStream_t st, double tau = 0.0);
 // out[0] = sum |G_ij|^2 off the diagonal, out[1] = sum over all (two-stage)
 void jacobi_norms(const zc* G, int64_t k, double* part, double* out, hipStream_t st);
 void jacobi_sort(const zc* G, const zc* Z, int64_t k, double* w, int* rank, zc* Zout, int64_t ldz, hipStream_t st);
@@ -87,6 +85,14 @@ void jacobi_list(const zc* G, int64_t k, const double* fro2, double thr_factor, 
 void jacobi_sparse_round(zc* G, zc* Z, int64_t k, const int* pairs, int np, const int* pairof, void* prm_scratch,
                          const double* fro2, double tau, int* rotated, hipStream_t st);
 size_t jacobi_rot_bytes();
+// One round of the block-ordered Jacobi sweep on G (k x k, ld k, Hermitian,
+// in place) with its rotations accumulated into Z (k x k, ld k, in place);
+// V: block_jacobi_v_bytes(k) of device scratch; rounds 0 .. block_jacobi_rounds(k) - 1
+// make a sweep; *rotated set when a rotation was applied.
+size_t block_jacobi_v_bytes(int64_t k);
+int64_t block_jacobi_rounds(int64_t k);
+void block_jacobi_round(zc* G, zc* Z, int64_t k, int64_t round, const double* fro2, double tau, zc* V, int* rotated,
+                        hipStream_t st);
 
 // ---- Eigenvector refinement for nearly diagonal Hermitian k x k -------------
 // One step's coefficients E (k x k) from S = X^H G X and P = X^H X, both

@@ -307,8 +307,11 @@ def test_orthonormalize_falls_back_on_ill_conditioned_block(lib):
     assert np.linalg.norm(lead - Q @ (Q.conj().T @ lead), 2) <= 1e-9
 
 
-@pytest.mark.parametrize("k", [1, 2, 40, 96, 97, 130])
+@pytest.mark.parametrize("k", [1, 2, 40, 96, 97, 130, 257, 440])
 def test_eigh_matches_oracle(lib, k):
+    """Dense random Hermitian matrices: one workgroup up to k = 96, block-ordered
+    sweeps above (ragged last block at 97, 130 and 257, an odd block count
+    with a phantom block at 97, 130 and 257, 28 blocks at 440)."""
     rng = _rng(k)
     M = _cg(rng, (k, k))
     G = (M + M.conj().T) / 2
