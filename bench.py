@@ -11,9 +11,11 @@ n = 4000, nev = 400, nex = 40, Chebyshev degree 20, tol 1e-10, FP64
 throughout (synthetic FLAPW-shaped inputs; the paper's FLEUR matrices are not
 available).  Prints one JSON line.
 
-The filter kernel is timed live with HIP events around every launch on the
-solver's stream (profile mode of the library); its algorithmic work is
-8 n^2 k_active flops per degree step.
+The filter kernel is timed live with HIP events on the solver's stream
+(profile mode of the library): one event pair around each filter call's
+consecutive degree steps, so the average per launch includes the short gaps
+between back-to-back launches; its algorithmic work is 8 n^2 k_active flops
+per degree step.
 """
 import argparse
 import json

@@ -64,7 +64,7 @@ typedef struct {
                             mixed_switch_digits), FP64 for those, for everything else and for the
                             final sweeps; accepted pairs meet the same FP64 tolerance */
   uint64_t seed;         /* Philox4x32-10 seed of the random start vectors (default 0) */
-  int32_t profile;       /* 1: time every filter kernel launch with device events */
+  int32_t profile;       /* 1: time the filter with device events (one pair around each filter call's degree steps) */
   int32_t qr_mode;       /* re-orthonormalization: 0 = CholeskyQR2, Householder when a Gram
                             matrix is not positive definite (default); 1 = Householder always */
   int32_t filter_tile;   /* filter kernel tile configuration (chfsi_zgemm's numbering; 0 = automatic) */
@@ -83,7 +83,7 @@ typedef struct {
   int32_t qr_householder;  /* re-orthonormalizations that used Householder QR */
   int32_t reserved_i;
   double filter_flops;     /* algorithmic filter work: sum over steps of 8 n^2 k_active */
-  double filter_kernel_seconds; /* summed filter kernel durations (profile = 1, else 0) */
+  double filter_kernel_seconds; /* summed event-timed spans of the filter calls' launches (profile = 1, else 0) */
   double t_reduce, t_lanczos, t_filter, t_qr, t_rr, t_resid, t_total; /* seconds per phase */
   double b_upper;          /* Lanczos upper bound of the standard-form spectrum */
   double theta_min;        /* smallest Lanczos Ritz value */

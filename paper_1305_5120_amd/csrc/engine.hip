@@ -142,7 +142,6 @@ struct chfsi_ctx_s {
   int filt_launches[2] = {0, 0};
   double filt_flops[2] = {0, 0};
   bool filt_pending[2] = {false, false};  // events recorded since the last collection
-  int filt_first_product[2] = {0, 0};     // first degree step of the last filter that ran as a product
   void reset_filter_stats() {
     for (int i = 0; i < 2; i++) {
       filt_kernel_s[i] = 0;
@@ -671,18 +670,20 @@ struct chfsi_ctx_s {
   void* filter_any(int prec, const void* Ap, int64_t lda, void* Yp, int64_t ldy, void* Ybp, int64_t ldyb, int64_t ka, int m,
                    double a, double b, double a0, const zc* AY0 = nullptr, int64_t lday = 0) {
     const bool prof = opts.profile != 0;
+    // profile mode: one event pair around the call's consecutive degree
+    // steps (a pair per step would put a timed marker between every two
+    // launches, which on this runtime costs the stream a few microseconds
+    // each); the per-launch figure then includes the short gaps between
+    // back-to-back launches
     std::vector<EventPair>& ev = fev[prec];
-    if (prof && (int)ev.size() < m) {
-      for (int i = (int)ev.size(); i < m; i++) {
-        EventPair ep;
-        CHFSI_HIP(hipEventCreate(&ep.a));
-        CHFSI_HIP(hipEventCreate(&ep.b));
-        ev.push_back(ep);
-      }
+    if (prof && ev.empty()) {
+      EventPair ep;
+      CHFSI_HIP(hipEventCreate(&ep.a));
+      CHFSI_HIP(hipEventCreate(&ep.b));
+      ev.push_back(ep);
     }
-    auto step = [&](int i, const void* cur, int64_t ldc, void* out, int64_t ldo, double al, double be, double ga,
+    auto step = [&](const void* cur, int64_t ldc, void* out, int64_t ldo, double al, double be, double ga,
                     const void* prev, int64_t ldp) {
-      if (prof) CHFSI_HIP(hipEventRecord(ev[i].a, st));
       GemmOp g;
       g.prec = prec;
       g.M = n; g.N = ka; g.K = n;
@@ -693,41 +694,38 @@ struct chfsi_ctx_s {
       g.cfg = opts.filter_tile;
       g.splitk = opts.filter_splitk;
       zgemm(g, gw(), st);
-      if (prof) CHFSI_HIP(hipEventRecord(ev[i].b, st));
     };
     const std::vector<ChebStep> cs = cheb_schedule(m, a, b, a0);
     // Y_1 = (sigma1/e)(A - cI) Y_0
     const bool reuse = AY0 && prec == PREC_F64;
     if (reuse)
       lincomb2d(cs[0].alpha, AY0, lday, cs[0].beta, static_cast<const zc*>(Yp), ldy, static_cast<zc*>(Ybp), ldyb, n, ka, st);
-    else
-      step(0, Yp, ldy, Ybp, ldyb, cs[0].alpha, cs[0].beta, 0.0, nullptr, 0);
+    if (prof) CHFSI_HIP(hipEventRecord(ev[0].a, st));
+    if (!reuse) step(Yp, ldy, Ybp, ldyb, cs[0].alpha, cs[0].beta, 0.0, nullptr, 0);
     void *cur = Ybp, *prev = Yp;
     int64_t ldc = ldyb, ldp = ldy;
     for (int i = 1; i < m; i++) {
       // Y_{i+1} = alpha (A - cI)-scaled product - sigma sigma' Y_{i-1}, over Y_{i-1}
-      step(i, cur, ldc, prev, ldp, cs[i].alpha, cs[i].beta, cs[i].gamma, prev, ldp);
+      step(cur, ldc, prev, ldp, cs[i].alpha, cs[i].beta, cs[i].gamma, prev, ldp);
       std::swap(cur, prev);
       std::swap(ldc, ldp);
     }
+    if (prof) CHFSI_HIP(hipEventRecord(ev[0].b, st));
     const int products = reuse ? m - 1 : m;
     filt_launches[prec] += products;
     filt_flops[prec] += 8.0 * (double)n * (double)n * (double)ka * (double)products;
     if (prof) filt_pending[prec] = true;
-    filt_first_product[prec] = reuse ? 1 : 0;
     return cur;
   }
 
-  // Add the event times of the filters run since the last call (the
-  // stream must have passed them).
-  void collect_filter_events(int m) {
+  // Add the event time of the filter run since the last call in each
+  // precision (the stream must have passed it).
+  void collect_filter_events() {
     for (int p = 0; p < 2; p++) {
-      if (!filt_pending[p]) continue;
-      for (int i = filt_first_product[p]; i < m && i < (int)fev[p].size(); i++) {
-        float ms = 0.f;
-        CHFSI_HIP(hipEventElapsedTime(&ms, fev[p][i].a, fev[p][i].b));
-        filt_kernel_s[p] += ms * 1e-3;
-      }
+      if (!filt_pending[p] || fev[p].empty()) continue;
+      float ms = 0.f;
+      CHFSI_HIP(hipEventElapsedTime(&ms, fev[p][0].a, fev[p][0].b));
+      filt_kernel_s[p] += ms * 1e-3;
       filt_pending[p] = false;
     }
   }
@@ -1080,7 +1078,7 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   inf.t_qr += ms[1] * 1e-3;
   inf.t_rr += ms[2] * 1e-3;
   inf.t_resid += ms[3] * 1e-3;
-  c->collect_filter_events(c->opts.degree);
+  c->collect_filter_events();
   const double* mu = hb;
   const double* rho = hb + ka;
   for (int64_t j = 0; j < ka; j++)
@@ -1943,7 +1941,7 @@ chfsi_status chfsi_filter(chfsi_ctx c, const void* A, int64_t lda, void* Y, int6
       if (res != (zc*)Y) copy2d(res, n, (zc*)Y, ldy, n, k, c->st);
     }
     c->sync();
-    c->collect_filter_events(m);
+    c->collect_filter_events();
   });
 }
 
