@@ -149,13 +149,6 @@ __global__ void k_column_norms(const zc* R, int64_t ldr, int64_t n, double* out)
   if (threadIdx.x == 0) out[j] = sqrt(s);
 }
 
-__global__ void k_nonfinite(const zc* A, int64_t lda, int64_t n, int64_t k, int* flag) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * k) return;
-  const zc v = A[(e % n) + (e / n) * lda];
-  if (!isfinite(v.x) || !isfinite(v.y)) *flag = 1;
-}
-
 // --------------------------------------------------------------------------
 // Cholesky diagonal block (nb <= 64) and the inverse of its factor, one
 // workgroup, the block in LDS (rows beyond nb padded with the identity).
@@ -1317,10 +1310,6 @@ void column_norms(const zc* R, int64_t ldr, int64_t n, int64_t k, double* out, h
   LAUNCH(k_column_norms, dim3((unsigned)k), dim3(NT), 0, st, R, ldr, n, out);
 }
 
-void nonfinite_check(const zc* A, int64_t lda, int64_t n, int64_t k, int* flag, hipStream_t st) {
-  if (n * k == 0) return;
-  LAUNCH(k_nonfinite, grid1(n * k), dim3(NT), 0, st, A, lda, n, k, flag);
-}
 
 void chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi, int64_t j0, int64_t nb, int* info,
                hipStream_t st) {

@@ -33,7 +33,6 @@ void residual_block(const zc* W, int64_t ldw, const zc* Y, int64_t ldy, const do
 // out[j] = ||R(:, j)||_2
 void column_norms(const zc* R, int64_t ldr, int64_t n, int64_t k, double* out, hipStream_t st);
 // flag[0] = 1 if any entry of the n x k block is not finite (else untouched)
-void nonfinite_check(const zc* A, int64_t lda, int64_t n, int64_t k, int* flag, hipStream_t st);
 
 // ---- Cholesky --------------------------------------------------------------
 // Factor the nb x nb diagonal block W(j0:j0+nb, j0:j0+nb) (lower triangle
