@@ -330,6 +330,25 @@ def test_eigh_matches_oracle(lib, k):
     assert np.all(np.abs(ov[sep] - 1) <= 1e-9)
 
 
+def test_eigh_large_dense_against_library_eigensolver(lib):
+    """k = 1000: 63 blocks of 16 (ragged last block, a phantom block), 32
+    pairs per round, several block-ordered sweeps before the sparse sweeps
+    and the refinement take over.  Eigenvalues against LAPACK's (numpy),
+    eigenpairs by their residual and orthogonality."""
+    k = 1000
+    rng = _rng(1000)
+    M = _cg(rng, (k, k))
+    G = (M + M.conj().T) / 2
+    ref = np.linalg.eigvalsh(G)
+    ctx = lib.create(k)
+    w, Z = lib.eigh(ctx, _t(G))
+    Z = _np(Z)
+    gn = np.linalg.norm(G)
+    assert np.abs(w - ref).max() <= 1e-13 * gn
+    assert np.abs(G @ Z - Z * w).max() <= 1e-12 * gn
+    assert np.abs(Z.conj().T @ Z - np.eye(k)).max() <= 1e-12
+
+
 def test_eigh_clustered_spectrum(lib):
     rng = _rng(44)
     k = 120
