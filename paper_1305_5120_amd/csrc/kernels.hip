@@ -242,28 +242,36 @@ __global__ void __launch_bounds__(CNT) k_chol_diag(const zc* W, int64_t ldw, zc*
       zc p[CPW];
 #pragma unroll
       for (int i = 0; i < CPW; i++) p[i] = S[r * CLD + jb + i];
-      int fail = -1;  // first column of the panel without a positive pivot (uniform)
+      // Branch-free pivot steps (selects, no divergent blocks on the chain
+      // of 64 dependent pivots); after a non-positive pivot the panel goes
+      // on with a unit stand-in and the failure is reported instead.
+      int fail = -1;    // first column of the panel without a positive pivot (uniform)
+      double xd = 0.0;  // lane r in the panel: 1 / l(r, r)
 #pragma unroll
       for (int i = 0; i < CPW; i++) {
         const int j = jb + i;
-        const double d = lane_read(p[i].x, j);
-        if (fail < 0 && !(d > 0.0)) fail = j;
-        if (fail < 0) {
-          double y = __builtin_amdgcn_rsq(d);
-          y = y * fma(-0.5 * d * y, y, 1.5);
-          y = y * fma(-0.5 * d * y, y, 1.5);
-          const double ljj = d * y;
-          p[i] = r > j ? zscale(y, p[i]) : (r == j ? zmk(ljj, 0.0) : zmk(0.0, 0.0));
-          if (r == j) X[j * CLD + j] = zmk(y, 0.0);  // X's diagonal: 1 / l(j, j)
+        const double d0 = lane_read(p[i].x, j);
+        const bool good = d0 > 0.0;
+        fail = (fail < 0 && !good) ? j : fail;
+        const double d = good ? d0 : 1.0;
+        double y = __builtin_amdgcn_rsq(d);
+        y = y * fma(-0.5 * d * y, y, 1.5);
+        y = y * fma(-0.5 * d * y, y, 1.5);
+        // rows below the pivot scale by 1 / l(j, j), the pivot row becomes
+        // l(j, j) = d y, rows above zero
+        const double f = r > j ? y : 0.0;
+        const double dg = r == j ? d * y : 0.0;
+        p[i] = zmk(fma(f, p[i].x, dg), f * p[i].y);
+        xd = r == j ? y : xd;
 #pragma unroll
-          for (int ii = i + 1; ii < CPW; ii++) {
-            // p[ii] -= p[i] conj(l(jb + ii, j))
-            const double lx = lane_read(p[i].x, jb + ii), ly = lane_read(p[i].y, jb + ii);
-            p[ii] = zmk(fma(-p[i].x, lx, fma(-p[i].y, ly, p[ii].x)), fma(-p[i].y, lx, fma(p[i].x, ly, p[ii].y)));
-          }
+        for (int ii = i + 1; ii < CPW; ii++) {
+          // p[ii] -= p[i] conj(l(jb + ii, j))
+          const double lx = lane_read(p[i].x, jb + ii), ly = lane_read(p[i].y, jb + ii);
+          p[ii] = zmk(fma(-p[i].x, lx, fma(-p[i].y, ly, p[ii].x)), fma(-p[i].y, lx, fma(p[i].x, ly, p[ii].y)));
         }
       }
       if (fail >= 0 && r == 0) failed = fail;
+      if (r >= jb && r < jb + CPW) X[r * CLD + r] = zmk(xd, 0.0);  // X's diagonal: 1 / l(r, r)
 #pragma unroll
       for (int i = 0; i < CPW; i++) S[r * CLD + jb + i] = p[i];
     }
