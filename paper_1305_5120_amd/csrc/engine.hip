@@ -588,7 +588,8 @@ struct chfsi_ctx_s {
   // success lands in info_d (INT_MAX: positive definite) without a wait;
   // Qo is meaningless when it failed.
   void cholqr_pass(const zc* Yin, int64_t ldy, int64_t k, zc* Qo, int64_t ldq, int* info_d) {
-    gemm(OP_C, OP_N, k, k, n, 1.0, Yin, ldy, Yin, ldy, G.z(), k);
+    // (lower triangle only: the factorization reads no other part)
+    gemm(OP_C, OP_N, k, k, n, 1.0, Yin, ldy, Yin, ldy, G.z(), k, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_OUT_LOWER);
     chol_factor(k, G.z(), k, G2.z(), Z2.z(), Ztmp.z(), k, info_d);
     gemm(OP_N, OP_C, n, k, k, 1.0, Yin, ldy, Ztmp.z(), k, Qo, ldq, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER);
   }
@@ -737,8 +738,9 @@ struct chfsi_ctx_s {
   void rayleigh_ritz(const zc* Ap, int64_t lda, const zc* Qa, int64_t ldq, int64_t ka, zc* Yo, int64_t ldyo, double* mu_d,
                      zc* Wbuf, zc* WZo, double tau = 0.0) {
     gemm(OP_N, OP_N, n, ka, n, 1.0, Ap, lda, Qa, ldq, Wbuf, n);
-    gemm(OP_C, OP_N, ka, ka, n, 1.0, Qa, ldq, Wbuf, n, G.z(), ka);
-    hermitize(G.z(), ka, ka, st);
+    // the lower triangle of Q^H W, mirrored: an exactly Hermitian G
+    gemm(OP_C, OP_N, ka, ka, n, 1.0, Qa, ldq, Wbuf, n, G.z(), ka, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_OUT_LOWER);
+    hermitian_from_lower(G.z(), ka, ka, st);
     eigh(G.z(), ka, ka, mu_d, Z.z(), ka, tau);
     gemm(OP_N, OP_N, n, ka, ka, 1.0, Qa, ldq, Z.z(), ka, Yo, ldyo);
     if (WZo) gemm(OP_N, OP_N, n, ka, ka, 1.0, Wbuf, n, Z.z(), ka, WZo, n);
@@ -2104,7 +2106,7 @@ chfsi_status chfsi_zgemm(chfsi_ctx c, int32_t opA, int32_t opB, int64_t M, int64
       c->P_elems = need;
     }
     c->gemm(opA, opB, M, N, K, alpha, (const zc*)A, lda, (const zc*)B, ldb, (zc*)C, ldc, beta, (const zc*)X, ldx, gamma,
-            (const zc*)Z, ldz, structure, !(structure & GEMM_OUT_LOWER), false, cfg, nsplit);
+            (const zc*)Z, ldz, structure, true, false, cfg, nsplit);
     c->sync();
   });
 }

@@ -117,21 +117,6 @@ __global__ void k_hermitian_from_lower(zc* A, int64_t lda, int64_t n) {
   else A[j + i * lda] = zconj(A[i + j * lda]);
 }
 
-__global__ void k_hermitize(zc* A, int64_t lda, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * n) return;
-  const int64_t i = e % n, j = e / n;
-  if (i < j) return;
-  if (i == j) {
-    A[i + i * lda].y = 0.0;
-    return;
-  }
-  const zc x = A[i + j * lda], y = A[j + i * lda];
-  const zc m = zmk(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
-  A[i + j * lda] = m;
-  A[j + i * lda] = zconj(m);
-}
-
 __global__ void k_residual(const zc* W, int64_t ldw, const zc* Y, int64_t ldy, const double* mu, zc* R, int64_t ldr, int64_t n,
                            int64_t k) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1301,10 +1286,6 @@ void zero_strict_upper(zc* A, int64_t lda, int64_t n, hipStream_t st) {
 
 void hermitian_from_lower(zc* A, int64_t lda, int64_t n, hipStream_t st) {
   LAUNCH(k_hermitian_from_lower, grid1(n * n), dim3(NT), 0, st, A, lda, n);
-}
-
-void hermitize(zc* A, int64_t lda, int64_t n, hipStream_t st) {
-  LAUNCH(k_hermitize, grid1(n * n), dim3(NT), 0, st, A, lda, n);
 }
 
 void residual_block(const zc* W, int64_t ldw, const zc* Y, int64_t ldy, const double* mu, zc* R, int64_t ldr, int64_t n,

@@ -23,7 +23,6 @@ void to_f32(const zc* src, int64_t lds, cc* dst, int64_t ldd, int64_t m, int64_t
 void to_f64(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st);
 void set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st);
 void zero_strict_upper(zc* A, int64_t lda, int64_t n, hipStream_t st);
-void hermitize(zc* A, int64_t lda, int64_t n, hipStream_t st);  // A <- (A + A^H)/2, in place
 // A <- the Hermitian matrix whose lower triangle A holds (upper triangle
 // overwritten by the conjugate transpose, diagonal made real)
 void hermitian_from_lower(zc* A, int64_t lda, int64_t n, hipStream_t st);

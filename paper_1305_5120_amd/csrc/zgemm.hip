@@ -475,6 +475,8 @@ __device__ __forceinline__ void splitk_reduce_elem(const ZGemmParams& p, int64_t
   using E = typename PT::E;
   using R = typename PT::R;
   const int64_t m = e % p.M, n = e / p.M;
+  // lower-triangle products: the tiles above the diagonal wrote no partials
+  if ((p.flags & GEMM_OUT_LOWER) && m < n) return;
   const E* P = static_cast<const E*>(p.P) + (int64_t)batch * p.splitk * p.M * p.N;
   R re = 0, im = 0;
   // unrolled so that several partial loads are in flight; the sum is still
@@ -757,14 +759,16 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
     splitk = sk;
     return;
   }
-  // Small outputs of deep products (Gram matrices Y^H Y, Q^H W): 32 x 32
-  // tiles split 16 ways, and further (up to 64, each split at least two
-  // slabs deep) while the tiles and splits give fewer than 256 workgroups;
-  // tall products with a short K (n x k times k x k): 32 x 32 tiles, no
-  // split (both read off the same sweep).
-  if (batch == 1 && g.M * g.N <= 512 * 512 && g.K >= 2048 && g.allow_splitk && P_elems &&
-      !(g.flags & GEMM_OUT_LOWER) && g.prec == PREC_F64) {
-    const int64_t tiles = cdiv(g.M, (int64_t)32) * cdiv(g.N, (int64_t)32);
+  // Small outputs of deep products (Gram matrices Y^H Y, Q^H W, full or
+  // lower triangle): 32 x 32 tiles split 16 ways, and further (up to 64,
+  // each split at least two slabs deep) while the tiles and splits give
+  // fewer than 256 workgroups; tall products with a short K (n x k times
+  // k x k): 32 x 32 tiles, no split (both read off the same sweep).
+  const int gram_struct = g.flags & ~GEMM_OUT_LOWER;
+  if (batch == 1 && g.M * g.N <= 512 * 512 && g.K >= 2048 && g.allow_splitk && P_elems && !gram_struct &&
+      g.prec == PREC_F64) {
+    const int64_t tm = cdiv(g.M, (int64_t)32), tn = cdiv(g.N, (int64_t)32);
+    const int64_t tiles = (g.flags & GEMM_OUT_LOWER) && tm == tn ? tm * (tm + 1) / 2 : tm * tn;
     int sk = 16;
     while (sk < 64 && tiles * sk < 256 && g.K >= (int64_t)2 * sk * 2 * CFGS[2].bk) sk *= 2;
     const int min_slabs = sk > 16 ? 2 : 4;
@@ -838,8 +842,8 @@ void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st) {
     throw Error(ST_EINVAL, "zgemm: FP32 products support op = N and no structure flags only");
   if (sk > 1) {
     const size_t cap = f32 ? 2 * w.P_elems : w.P_elems;
-    if (!w.P || (size_t)sk * g.M * g.N * batch > cap || (g.flags & GEMM_OUT_LOWER))
-      throw Error(ST_EINVAL, "zgemm: split-K scratch too small or not allowed");
+    if (!w.P || (size_t)sk * g.M * g.N * batch > cap)
+      throw Error(ST_EINVAL, "zgemm: split-K scratch too small");
     const int bk = CFGS[cfg].bk;
     p.kchunk = cdiv(cdiv(g.K, sk), bk) * bk;
     p.splitk = (int)std::max<int64_t>(1, cdiv(g.K, p.kchunk));

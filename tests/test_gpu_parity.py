@@ -118,13 +118,10 @@ def test_zgemm_structured_products_many_tile_rows(lib, flag, tile, split):
     """Triangular op(A) (lower, upper), lower-only output, and upper op(B)
     with lower-only output over 18 tile rows (an odd count: the products
     deal their rows heaviest / lightest alternately), several column tiles,
-    automatic and explicit tiles and K splits (none with a lower-only
-    output, which takes no split)."""
+    automatic and explicit tiles and K splits."""
     rng = _rng(100 + flag)
     n, w = 1100, 300
     ctx = lib.create(8)
-    if flag & 16 and split > 1:
-        split = 1
     bits = flag | (tile << 8) | (split << 16)
     if flag in (1, 2):
         Am = np.tril(_cg(rng, (n, n))) if flag == 1 else np.triu(_cg(rng, (n, n)))
@@ -145,6 +142,29 @@ def test_zgemm_structured_products_many_tile_rows(lib, flag, tile, split):
         ref = Am @ Bl.conj().T
         low = np.tril_indices(n)
         assert np.linalg.norm(C[low] - ref[low]) <= 1e-13 * np.linalg.norm(ref[low])
+
+
+@pytest.mark.parametrize("split", [0, 1, 4, 16])
+def test_zgemm_lower_gram_with_k_split(lib, split):
+    """Gram matrices Y^H Y of a tall block (K = 4000, 200 x 200 output) with
+    only the lower triangle formed, as the CholeskyQR and Rayleigh-Ritz steps
+    request them: automatic and explicit K splits.  The lower triangle
+    matches the product; with a split the strictly upper triangle of C is
+    not written (its sentinel survives)."""
+    rng = _rng(300 + split)
+    K, k = 4000, 200
+    Y = _cg(rng, (K, k))
+    ctx = lib.create(8)
+    sentinel = 7.0 + 7.0j
+    C = _t(np.full((k, k), sentinel))
+    C = lib.zgemm(ctx, 1, 0, _t(Y), _t(Y), C=C, flags=16 | (split << 16))
+    C = _np(C)
+    ref = Y.conj().T @ Y
+    low = np.tril_indices(k)
+    assert np.linalg.norm(C[low] - ref[low]) <= 1e-13 * np.linalg.norm(ref[low])
+    if split > 1:
+        up = np.triu_indices(k, 1)
+        assert np.all(C[up] == sentinel)
 
 
 def test_zgemm_in_place_epilogue(lib):
