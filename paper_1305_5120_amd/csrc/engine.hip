@@ -1067,11 +1067,15 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   CHFSI_HIP(hipEventRecord(s.ev[2], st));
   c->rayleigh_ritz(c->A.z(), n, Qb + cl * n, n, ka, Y + cl * n, n, mu_d, c->Wk.z(), c->Wz.z(), 1e-3 * s.hs);
   CHFSI_HIP(hipEventRecord(s.ev[3], st));
-  c->residual_norms(c->L.z(), n, c->Wz.z(), Y + cl * n, n, ka, mu_d, c->Wk.z(), F, rho_d);
+  // residuals of the columns that can lock (at most nev - cl of them: the
+  // extra columns never do); mixed precision reads every active column's
+  // residual for its precision rules
+  const int64_t kr = s.mixed ? ka : std::min(ka, s.nev - cl);
+  c->residual_norms(c->L.z(), n, c->Wz.z(), Y + cl * n, n, kr, mu_d, c->Wk.z(), F, rho_d);
   s.wz_first = cl;  // Wz = A Y(:, cl:k) until the next Rayleigh-Ritz step
   double* hb = c->hbuf;
   CHFSI_HIP(hipMemcpyAsync(hb, mu_d, ka * sizeof(double), hipMemcpyDeviceToHost, st));
-  CHFSI_HIP(hipMemcpyAsync(hb + ka, rho_d, ka * sizeof(double), hipMemcpyDeviceToHost, st));
+  CHFSI_HIP(hipMemcpyAsync(hb + ka, rho_d, kr * sizeof(double), hipMemcpyDeviceToHost, st));
   CHFSI_HIP(hipEventRecord(s.ev[4], st));
   c->sync();
   float ms[4];
@@ -1082,10 +1086,11 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   inf.t_resid += ms[3] * 1e-3;
   c->collect_filter_events();
   const double* mu = hb;
-  const double* rho = hb + ka;
+  double* rho = hb + ka;
   for (int64_t j = 0; j < ka; j++)
-    if (!std::isfinite(mu[j]) || !std::isfinite(rho[j]))
+    if (!std::isfinite(mu[j]) || (j < kr && !std::isfinite(rho[j])))
       throw Error(ST_ENAN, "non-finite Ritz value or residual at iteration " + std::to_string(s.it));
+  for (int64_t j = kr; j < ka; j++) rho[j] = INFINITY;  // not formed
   int64_t nl = 0;
   while (cl + nl < s.nev && nl < ka && rho[nl] <= s.hs) {
     s.lam[cl + nl] = mu[nl];
