@@ -715,6 +715,9 @@ void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const i
 // per matrix-core product).  With these weights the rule picks the fastest
 // of the three at every width of the sweep.
 constexpr double W48_COST = 1.10, W32_COST = 1.08;
+// The same for the FP32 tiles (a sweep of active widths 40 to 440 at
+// n = 4000).
+constexpr double W48_COST_F32 = 1.07, W32_COST_F32 = 1.08;
 
 void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   const int batch = g.batch > 0 ? g.batch : 1;
@@ -726,23 +729,20 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   // does.  K is split so that each workgroup's range stays near 1000 (the A
   // panels of the workgroups resident on one XCD then fit its 4 MB L2), and
   // further where the tiles alone would leave the CUs short of work (FP32
-  // steps are shorter and want about twice as many workgroups).  FP64: the
-  // tile width (64, 48 or 32 columns) that computes the fewest padded
-  // columns, each width's columns weighted by its measured cost relative
-  // to the 64-wide tile's.
+  // steps are shorter and want about twice as many workgroups).  The tile
+  // width (64, 48 or 32 columns) that computes the fewest padded columns,
+  // each width's columns weighted by its measured cost relative to the
+  // 64-wide tile's (per precision).
   if (nn && batch == 1 && g.M >= 1024 && g.K >= 1024 && !(g.flags & GEMM_OUT_LOWER)) {
     const bool f32 = g.prec == PREC_F32;
     const double pad64 = (double)(cdiv(g.N, (int64_t)64) * 64) / (double)g.N;
     const double pad32 = (double)(cdiv(g.N, (int64_t)32) * 32) / (double)g.N;
-    int c;
-    if (f32) {
-      // (blocks of 97-128 columns: the 64 x 128 x 8 tile, one column tile)
-      c = (g.N > 96 && g.N <= 128) ? 5 : (pad64 <= 1.08 * pad32 ? 1 : 7);
-    } else {
-      const double cost64 = pad64, cost48 = W48_COST * (double)(cdiv(g.N, (int64_t)48) * 48) / (double)g.N,
-                   cost32 = W32_COST * pad32;
-      c = cost64 <= cost48 && cost64 <= cost32 ? 1 : (cost48 <= cost32 ? 10 : 7);
-    }
+    const double pad48 = (double)(cdiv(g.N, (int64_t)48) * 48) / (double)g.N;
+    const double cost64 = pad64, cost48 = (f32 ? W48_COST_F32 : W48_COST) * pad48,
+                 cost32 = (f32 ? W32_COST_F32 : W32_COST) * pad32;
+    int c = cost64 <= cost48 && cost64 <= cost32 ? 1 : (cost48 <= cost32 ? 10 : 7);
+    // (FP32 blocks of 97-128 columns: the 64 x 128 x 8 tile, one column tile)
+    if (f32 && g.N > 96 && g.N <= 128) c = 5;
     int sk = g.K < 1500 ? 1 : g.K < 3000 ? 2 : g.K < 7000 ? 4 : 8;
     if (f32) sk = std::min(8, 2 * sk);
     const int64_t tiles = cdiv(g.M, (int64_t)CFGS[c].bm) * cdiv(g.N, (int64_t)CFGS[c].bn);
