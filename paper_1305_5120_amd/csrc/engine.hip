@@ -1791,6 +1791,21 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
           int best = BATCH_CANDIDATES[0];
           for (int q = 0; q < BATCH_NCAND; q++)
             if (b->rate[p][BATCH_CANDIDATES[q]] > b->rate[p][best]) best = BATCH_CANDIDATES[q];
+          // near ties (within 2 % of the best rate): the narrower tile, which
+          // pads less as the active widths shrink in later iterations (the
+          // trials run on the first iterations of a cold start)
+          const double top = b->rate[p][best];
+          int bm = 0, bn_best = 0;
+          zgemm_tile_shape(best, &bm, &bn_best);
+          for (int q = 0; q < BATCH_NCAND; q++) {
+            const int cq = BATCH_CANDIDATES[q];
+            int bn = 0;
+            zgemm_tile_shape(cq, &bm, &bn);
+            if (bn < bn_best && b->rate[p][cq] >= 0.98 * top) {
+              best = cq;
+              bn_best = bn;
+            }
+          }
           b->cfg[p] = best;
         }
       }

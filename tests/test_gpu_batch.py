@@ -58,13 +58,18 @@ def test_batch_cold_members_match_oracle_and_spectrum(lib):
         _check(p, ev[i], _np(X[i]), nevs[i])
         assert infos[i]["converged"] >= nevs[i]
         assert infos[i]["filter_flops"] > 0
-    # online choice: five candidate shapes tried, the fastest kept
+    # online choice: five candidate shapes tried, the fastest kept, or a
+    # narrower one within 2 % of it
     assert rep["outer_iterations"] >= 5
     assert rep["tile_config"] in (1, 3, 4, 5, 7)
     rates = rep["tile_rate"]
     tried = [c for c in (1, 3, 4, 5, 7) if rates[c] > 0]
     assert len(tried) == 5
-    assert rates[rep["tile_config"]] == max(rates[c] for c in tried)
+    width = {1: 64, 3: 64, 4: 64, 5: 128, 7: 32}
+    top = max(tried, key=lambda c: rates[c])
+    chosen = rep["tile_config"]
+    assert chosen == top or (rates[chosen] >= 0.98 * rates[top] and width[chosen] < width[top])
+    assert all(not (width[c] < width[chosen] and rates[c] >= 0.98 * rates[top]) for c in tried)
     assert rep["graph"] == 1
     assert rep["grouped_launches"] == 10 * rep["outer_iterations"]
     assert rep["filter_flops"] == pytest.approx(sum(i["filter_flops"] for i in infos), rel=1e-12)
