@@ -242,7 +242,7 @@ struct chfsi_ctx_s {
   void free_all() {
     for (DBuf* b : {&A32, &Y32, &Y32b, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
                     &flags, &P, &hpart, &htop, &tau, &Tall, &gram, &Vp, &Wt, &W2, &LV, &Lw, &Lh, &Lab, &mvpart, &Tsm,
-                    &Tz, &Tz2, &Tw, &npart, &jint, &jrot, &rf, &rfl, &rfc})
+                    &Tz, &Tz2, &Tw, &npart, &jint, &jrot, &bjv, &rf, &rfl, &rfc})
       b->release();
     if (hbuf) (void)hipHostFree(hbuf);
     hbuf = nullptr;
