@@ -692,13 +692,15 @@ __global__ void k_jacobi_init(const zc* G, int64_t ldg, int64_t k, zc* G0, zc* Z
 // The indices are cut into blocks of BJB (the last one ragged; a phantom
 // block makes the count even) and the blocks are paired round-robin.  In a
 // round every pair of blocks (P, Q) is one 2 BJB x 2 BJB subproblem: one
-// workgroup runs one cyclic sweep over its 2 BJB indices in LDS (every
-// index pair of P u Q once), accumulating the rotations in V; then every
-// off-diagonal tile of G between two pairs' index sets is updated as
-// V_s^H G(I_s, I_t) V_t and Z's columns as Z(:, I_t) V_t.  Over the rounds
-// every index pair (i, j) is rotated at least once, which makes a round set
-// one sweep of cyclic Jacobi in a block ordering; a sweep takes 2 launches
-// per round instead of one launch per scalar round.
+// workgroup rotates its index pairs in LDS, accumulating the rotations in V
+// -- in the first round of a sweep every index pair of P u Q once (which
+// covers the pairs inside each block), in the other rounds the pairs across
+// P and Q -- then every off-diagonal tile of G between two pairs' index sets
+// is updated as V_s^H G(I_s, I_t) V_t and Z's columns as Z(:, I_t) V_t.
+// Over the rounds every index pair (i, j) is rotated at least once (two
+// blocks meet in exactly one round), which makes a round set one sweep of
+// cyclic Jacobi in a block ordering; a sweep takes 2 launches per round
+// instead of one launch per scalar round.
 constexpr int BJB = 16;
 constexpr int BJS = 2 * BJB;   // subproblem size
 constexpr int BJL = BJS + 1;   // LDS leading dimension
@@ -738,10 +740,21 @@ __global__ void __launch_bounds__(256) k_bjac_solve(zc* G, int64_t k, int64_t nb
   __syncthreads();
   const double skip2 = fmax(1e-36 * fro2[0], tau2);
   constexpr int NBLK = BJB * (BJB + 1) / 2;
-  for (int r = 0; r < BJS - 1; r++) {
+  // the first round of a sweep visits every index pair of P u Q (31
+  // disjoint-pair rounds: the pairs inside a block are covered there);
+  // the other rounds visit the pairs across P and Q only (16 rounds,
+  // i in P with Q's (i + r) mod 16)
+  const bool full = round == 0;
+  const int inner = full ? BJS - 1 : BJB;
+  for (int r = 0; r < inner; r++) {
     if (tid < BJB) {
       int64_t p, q;
-      round_pair(BJS, r, tid, p, q);
+      if (full) {
+        round_pair(BJS, r, tid, p, q);
+      } else {
+        p = tid;
+        q = BJB + (tid + r) % BJB;
+      }
       pidx[tid] = (int)p;
       qidx[tid] = (int)q;
       Rot R;
