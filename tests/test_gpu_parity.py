@@ -259,6 +259,43 @@ def test_filter_fp32_against_oracle(lib, n, k, m):
     assert err >= 1e-9  # really computed in FP32
 
 
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 9, 10])
+def test_filter_fp32_every_tile_shape(lib, tile):
+    """The FP32 filter step in every tile shape (64x48 with 4x1 waves among
+    them), with and without a K split, to FP32 accuracy against the FP64
+    oracle."""
+    n, k, m = 300, 37, 5
+    p = workloads.make_problem(n, 13)
+    Y = _cg(_rng(14), (n, k))
+    lam = np.sort(p.lam)
+    a, b, a0 = float(lam[k]), float(lam[-1] * 1.05), float(lam[0])
+    ref = oracle.chebyshev_filter(p.A, Y, m, a, b, a0)
+    for sk in (1, 4):
+        ctx = lib.create(n, precision=1, filter_tile=tile, filter_splitk=sk)
+        Yt = _t(Y)
+        lib.filter(ctx, _t(p.A), Yt, m, a, b, a0)
+        err = _rel(_np(Yt), ref)
+        assert 1e-9 <= err <= 2e-5, (tile, sk, err)
+        ctx.release()
+
+
+def test_filter_fp32_tall_rule_takes_48_wide_tile(lib):
+    """n = 1100, 44 columns: the tall-product rule picks the 48-wide tile for
+    FP32 (64 columns would pad 45 %); the result agrees with the FP64 oracle
+    to FP32 accuracy."""
+    n, k, m = 1100, 44, 6
+    p = workloads.make_problem(n, 15)
+    Y = _cg(_rng(16), (n, k))
+    lam = np.sort(p.lam)
+    a, b, a0 = float(lam[k]), float(lam[-1] * 1.05), float(lam[0])
+    ref = oracle.chebyshev_filter(p.A, Y, m, a, b, a0)
+    ctx = lib.create(n, precision=1)
+    Yt = _t(Y)
+    lib.filter(ctx, _t(p.A), Yt, m, a, b, a0)
+    err = _rel(_np(Yt), ref)
+    assert 1e-9 <= err <= 2e-5, err
+
+
 def test_filter_closed_form_on_diagonal(lib):
     n, k, m = 100, 6, 9
     t = np.linspace(-1.0, 3.0, n)
