@@ -271,7 +271,9 @@ def _batch_sizes(count, seed):
 def run_batch(args):
     """k-point sequences in lockstep (grouped filter launches, captured
     graphs, online tile choice, mixed precision) against the same problems
-    solved one after another with one context per sequence."""
+    solved one after another with one context per sequence.  The sequences
+    advance together: only the current step's matrices are resident (the
+    one-after-another pass draws the same sequences again)."""
     import torch
     from paper_1305_5120_amd import chfsi
     import workloads
@@ -279,56 +281,68 @@ def run_batch(args):
     sizes = _batch_sizes(G, 3)
     nevs = [n // 10 for n in sizes]
     nexs = [max(1, v // 10) for v in nevs]
-    seqs = []
-    for i, n in enumerate(sizes):
-        seqs.append(list(workloads.make_sequence_torch(n, steps, 3 + i, device="cuda")))
-        log(f"[bench] generated sequence {i + 1}/{G} (n={n})")
-    torch.cuda.synchronize()
     prec = 1
+    sample = list(range(0, G, max(1, G // 4)))
 
-    def step_inputs(ell):
-        H = [s[ell]["H"] for s in seqs]
-        S = [s[0]["S"] if ell == 0 else None for s in seqs]
-        return H, S
+    def sequences():
+        return [workloads.make_sequence_torch(n, steps, 3 + i, device="cuda", rng_kind=args.gen_rng)
+                for i, n in enumerate(sizes)]
+
+    def first_step(gens):
+        ps = []
+        for i, g in enumerate(gens):
+            ps.append(next(g))
+            log(f"[bench] generated sequence {i + 1}/{G} (n={sizes[i]})")
+        return [p["H"] for p in ps], [p["S"] for p in ps]
 
     # batched: step 0 cold (and the online tile choice), steps 1.. timed
+    gens = sequences()
+    H, S0 = first_step(gens)
+    torch.cuda.synchronize()
     b = chfsi.Batch(sizes, use_graph=True, degree=20, seed=0, precision=prec)
-    H, S = step_inputs(0)
-    _, _, _, st, rep0 = b.solve(H, S, nevs, nexs, tol=1e-10)
+    _, _, _, st, rep0 = b.solve(H, S0, nevs, nexs, tol=1e-10)
     log(f"[bench] batch cold step: {rep0['seconds']:.2f} s, tile {rep0['tile_config']}/{rep0['tile_config_fp32']}")
     reps = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    tb = 0.0
+    worst = 0.0
+    none = [None] * G
     for ell in range(1, steps):
-        H, S = step_inputs(ell)
-        ev, X, infos, st, rep = b.solve(H, S, nevs, nexs, tol=1e-10)
+        H = [next(g)["H"] for g in gens]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, X, infos, st, rep = b.solve(H, none, nevs, nexs, tol=1e-10)
+        torch.cuda.synchronize()
+        tb += time.perf_counter() - t0
         reps.append(rep)
         log(f"[bench] batch step {ell}: {rep['seconds']:.2f} s, {rep['outer_iterations']} outer iterations, "
             f"grouped filter {rep['filter_seconds']:.2f} s ({rep['filter_flops'] / max(rep['filter_seconds'], 1e-9) / 1e12:.1f} TFLOP/s)")
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    worst = max(residual_check({"H": seqs[i][steps - 1]["H"], "S": seqs[i][0]["S"]}, ev[i], X[i])
-                for i in range(0, G, max(1, G // 4)))
+        if ell == steps - 1:
+            worst = max(residual_check({"H": H[i], "S": S0[i]}, ev[i], X[i]) for i in sample)
+        del ev, X
     b.close()
-    del ev, X
-    # one after another
+    del gens, H
+    # one after another (the same sequences drawn again)
+    gens = sequences()
+    H, S0 = first_step(gens)
     ctxs = [chfsi.create(n, degree=20, seed=0, precision=prec) for n in sizes]
-    H, S = step_inputs(0)
     for i in range(G):
-        chfsi.solve(ctxs[i], H[i], S[i], nevs[i], nexs[i], tol=1e-10, want_vectors=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+        chfsi.solve(ctxs[i], H[i], S0[i], nevs[i], nexs[i], tol=1e-10, want_vectors=False)
+    ts = 0.0
     seq_filter = 0.0
     for ell in range(1, steps):
-        H, S = step_inputs(ell)
+        H = [next(g)["H"] for g in gens]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         for i in range(G):
-            _, _, inf, _ = chfsi.solve(ctxs[i], H[i], S[i], nevs[i], nexs[i], tol=1e-10)
+            _, _, inf, _ = chfsi.solve(ctxs[i], H[i], None, nevs[i], nexs[i], tol=1e-10)
             seq_filter += inf["t_filter"]
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        ts += time.perf_counter() - t0
+        log(f"[bench] one after another, step {ell}: {ts:.2f} s so far")
     log(f"[bench] one after another: {ts:.2f} s for {G * (steps - 1)} solves, filter phases {seq_filter:.2f} s")
     for c in ctxs:
         c.release()
+    del gens, H
     solves = G * (steps - 1)
     ff = sum(r["filter_flops"] for r in reps)
     fs = sum(r["filter_seconds"] for r in reps)
@@ -337,7 +351,7 @@ def run_batch(args):
                 {"workload": "independent k-point sequences of correlated complex Hermitian DGEVPs",
                  "sequences": G, "n": f"uniform integers in [2000, 6000] (seed 3): {sizes}",
                  "nev": "n/10", "nex": "nev/10", "degree": 20, "tol": 1e-10, "precision": "mixed",
-                 "warm_start": True, "sequence_steps_timed": steps - 1})
+                 "warm_start": True, "sequence_steps_timed": steps - 1, "generator_draws": args.gen_rng})
     out.update({"sequential_solves_per_s": solves / ts, "speedup_vs_sequential": ts / tb,
                 "grouped_filter_tflops": ff / fs / 1e12 if fs else None,
                 "tile_config": rep0["tile_config"], "tile_config_fp32": rep0["tile_config_fp32"],
@@ -556,6 +570,8 @@ def main():
     ap.add_argument("--workers", type=int, default=4, help="serving workers")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving device-memory budget")
     ap.add_argument("--wc-n", type=int, default=4000, help="problem size of the warm/cold study")
+    ap.add_argument("--gen-rng", choices=["host", "device"], default="host",
+                    help="where the batch form's sequences draw their Gaussian matrices (device: faster at scale)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not time filter launches with events")
     ap.add_argument("--no-mixed", action="store_true",

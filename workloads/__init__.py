@@ -150,18 +150,37 @@ def _colmajor(t):
     return t.mT.contiguous().mT
 
 
-def make_problem_torch(n: int, seed: int, device="cuda"):
+def _cgauss_device(gen, shape, device):
+    """Complex Gaussian drawn on the device from a seeded torch generator
+    (E|z|^2 = 1); a faster stand-in for the host draws at large sizes."""
+    import torch
+    re = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+    im = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+    return torch.complex(re, im) * math.sqrt(0.5)
+
+
+def make_problem_torch(n: int, seed: int, device="cuda", rng_kind: str = "host"):
+    """Device variant of make_problem.  rng_kind "host" draws the Gaussian
+    matrices with numpy (the same numbers as make_problem); "device" draws
+    them on the device from torch generators seeded with the same seed (other
+    numbers, same distribution; for the large benchmark forms)."""
     import torch
     rng = np.random.default_rng(seed)
     lam = spectrum(n, rng)
-    G = torch.from_numpy(_cgauss(rng, (n, n))).to(device)
+    if rng_kind == "device":
+        gen = torch.Generator(device=device)
+        gen.manual_seed(seed)
+        draw = lambda shape: _cgauss_device(gen, shape, device)
+    else:
+        draw = lambda shape: torch.from_numpy(_cgauss(rng, shape)).to(device)
+    G = draw((n, n))
     Q, R = torch.linalg.qr(G)
     d = torch.diagonal(R)
     Q = Q * (d / d.abs())[None, :]
     lam_t = torch.from_numpy(lam).to(device=device, dtype=torch.complex128)
     A = (Q * lam_t[None, :]) @ Q.conj().T
     A = (A + A.conj().T) / 2
-    Gl = torch.from_numpy(_cgauss(rng, (n, n))).to(device)
+    Gl = draw((n, n))
     L = torch.eye(n, dtype=torch.complex128, device=device) + L_OFFDIAG * torch.tril(Gl, -1) / math.sqrt(n)
     S = L @ L.conj().T
     S = (S + S.conj().T) / 2
@@ -171,16 +190,24 @@ def make_problem_torch(n: int, seed: int, device="cuda"):
     return {"H": _colmajor(H), "S": _colmajor(S), "L": L, "A": A, "Q": Q, "lam": lam}
 
 
-def make_sequence_torch(n: int, steps: int, seed: int, eps: float = 1e-4, device="cuda", eps_decay: float = 1.0):
+def make_sequence_torch(n: int, steps: int, seed: int, eps: float = 1e-4, device="cuda", eps_decay: float = 1.0,
+                        rng_kind: str = "host"):
     """Device variant of make_sequence; yields dicts with H (and S, L for the
     first problem).  Step l (l >= 1) perturbs by eps * eps_decay**(l - 1)
-    (eps_decay < 1: a converging self-consistent cycle)."""
+    (eps_decay < 1: a converging self-consistent cycle).  rng_kind as in
+    make_problem_torch."""
     import torch
-    p0 = make_problem_torch(n, seed, device)
+    p0 = make_problem_torch(n, seed, device, rng_kind)
     yield p0
+    A, L, S0 = p0["A"], p0["L"], p0["S"]
+    del p0  # keep only what the later steps need (S, L, A)
     rng = np.random.default_rng(seed + 1_000_003)
-    A = p0["A"]
-    L = p0["L"]
+    if rng_kind == "device":
+        gen = torch.Generator(device=device)
+        gen.manual_seed(seed + 1_000_003)
+        draw = lambda shape: _cgauss_device(gen, shape, device)
+    else:
+        draw = lambda shape: torch.from_numpy(_cgauss(rng, shape)).to(device)
     for step in range(1, steps):
         v = torch.from_numpy(_cgauss(np.random.default_rng(12345), (n,))).to(device)
         v = v / torch.linalg.vector_norm(v)
@@ -190,8 +217,8 @@ def make_sequence_torch(n: int, steps: int, seed: int, eps: float = 1e-4, device
             s = torch.linalg.vector_norm(w)
             v = w / s
         nrm = float(s)
-        E = torch.from_numpy(_cgauss(rng, (n, n))).to(device)
-        u = torch.from_numpy(_cgauss(rng, (n,))).to(device)
+        E = draw((n, n))
+        u = draw((n,))
         u = u / torch.linalg.vector_norm(u)
         se = 1.0
         for _ in range(30):
@@ -205,4 +232,4 @@ def make_sequence_torch(n: int, steps: int, seed: int, eps: float = 1e-4, device
         H = L @ A @ L.conj().T
         H = (H + H.conj().T) / 2
         del E, P
-        yield {"H": _colmajor(H), "S": p0["S"], "L": L, "A": A}
+        yield {"H": _colmajor(H), "S": S0, "L": L, "A": A}
