@@ -703,9 +703,12 @@ def test_release_returns_device_memory(lib, precision):
     """Release frees a context's device buffers (filter blocks, factors,
     split-K partials, eigensolver scratch; a cold solve with a 110-column
     block takes the block Jacobi sweeps): device free memory after a second
-    create / solve / release cycle equals the memory before it within 4 MB,
-    far below the tens of MB the context allocates (the first cycle loads
-    the code objects)."""
+    create / solve / release cycle is not below the memory before it by more
+    than 4 MB, far below the tens of MB the context allocates (the first
+    cycle loads the code objects; objects of earlier tests are collected
+    before each reading, and memory they still free in between only raises
+    the second reading)."""
+    import gc
     import torch
     p = workloads.make_problem(600, 77)
 
@@ -717,13 +720,17 @@ def test_release_returns_device_memory(lib, precision):
         ctx.release()
         torch.cuda.synchronize()
 
+    def free_now():
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return torch.cuda.mem_get_info()[0]
+
     cycle()
-    torch.cuda.empty_cache()
-    free0 = torch.cuda.mem_get_info()[0]
+    free0 = free_now()
     cycle()
-    torch.cuda.empty_cache()
-    free1 = torch.cuda.mem_get_info()[0]
-    assert abs(free1 - free0) <= 4 << 20, (free0, free1)
+    free1 = free_now()
+    assert free1 >= free0 - (4 << 20), (free0, free1)
 
 
 def test_row_major_input_is_not_transposed(lib):
