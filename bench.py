@@ -580,7 +580,7 @@ def main():
                     help="after the timed region, run a device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs one problem sequence on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU (no multi-GPU path); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0:
