@@ -777,6 +777,36 @@ def test_filter_full_size_sampled_columns(lib, n, k, m):
     assert _rel(got, ref) <= 1e-12
 
 
+def test_solve_precision_configuration_full_size(lib):
+    """n=10000, nev=600, nex=60, degree 20, mixed precision (the filter in
+    complex FP32 until columns approach the tolerance, everything else FP64):
+    every eigenvalue against the spectrum known by construction, the
+    generalized residuals of the returned pairs, and S-orthonormality.
+    Gaussian draws on the device (same laws as the host generator)."""
+    import torch
+    n, nev, nex = 10000, 600, 60
+    p = workloads.make_problem_torch(n, 2, device="cuda", rng_kind="device")
+    ctx = lib.create(n, degree=20, seed=0, precision=1)
+    ev, X, info, st = lib.solve(ctx, p["H"], p["S"], nev, nex, tol=1e-10)
+    assert st == 0
+    assert info["iterations_fp32"] > 0
+    lam = np.sort(p["lam"])[:nev]
+    H, S = p["H"], p["S"]
+    v = torch.ones(n, dtype=torch.complex128, device="cuda")
+    for _ in range(50):
+        v = H @ v
+        v = v / torch.linalg.vector_norm(v)
+    hn = float(torch.linalg.vector_norm(H @ v))
+    ok, dmax = _checks.eig_ok(ev, lam, hn)
+    assert ok, dmax
+    lt = torch.from_numpy(ev).cuda().to(torch.complex128)
+    R = H @ X - (S @ X) * lt[None, :]
+    assert float(torch.linalg.vector_norm(R, dim=0).max()) <= 1e-10 * hn
+    G = X.conj().T @ (S @ X)
+    assert float((G - torch.eye(nev, dtype=torch.complex128, device="cuda")).abs().max()) <= 1e-12
+    ctx.release()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solve_full_size_first_problem_of_sequence(lib, precision):
     """n=4000, nev=400, nex=40, degree 20 (the benchmark's sequence, first
