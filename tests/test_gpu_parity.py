@@ -777,6 +777,35 @@ def test_filter_full_size_sampled_columns(lib, n, k, m):
     assert _rel(got, ref) <= 1e-12
 
 
+def test_solve_sequence_configuration_full_size(lib):
+    """The benchmark's workload at full size: three problems of the n=4000
+    sequence (nev=400, nex=40, degree 20, S fixed and cached, warm starts)
+    in the benchmark's launch configuration.  Each solve's eigenvalues
+    against a library eigensolver (rocSOLVER through torch) on the step's
+    standard-form matrix, which the generator builds directly; residuals of
+    the returned pairs; warm solves need fewer iterations than the cold
+    one."""
+    import torch
+    n, nev, nex = 4000, 400, 40
+    ctx = lib.create(n, degree=20, seed=0)
+    iters = []
+    for ell, p in enumerate(workloads.make_sequence_torch(n, 3, 1, device="cuda")):
+        ev, X, info, st = lib.solve(ctx, p["H"], p["S"] if ell == 0 else None, nev, nex, tol=1e-10)
+        assert st == 0
+        assert info["warm_start"] == (1 if ell > 0 else 0)
+        ref = torch.linalg.eigvalsh(p["A"]).cpu().numpy()[:nev]
+        hn = float(np.abs(torch.linalg.eigvalsh(p["H"]).cpu().numpy()).max())
+        ok, dmax = _checks.eig_ok(ev, ref, hn)
+        assert ok, (ell, dmax)
+        lt = torch.from_numpy(ev).cuda().to(torch.complex128)
+        R = p["H"] @ X - (p["S"] @ X) * lt[None, :]
+        assert float(torch.linalg.vector_norm(R, dim=0).max()) <= 1e-10 * hn
+        iters.append(info["iterations"])
+        del X, R
+    assert max(iters[1:]) < iters[0]
+    ctx.release()
+
+
 def test_solve_precision_configuration_full_size(lib):
     """n=10000, nev=600, nex=60, degree 20, mixed precision (the filter in
     complex FP32 until columns approach the tolerance, everything else FP64):
