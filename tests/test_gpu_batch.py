@@ -154,3 +154,37 @@ def test_batch_rejects_bad_arguments(lib):
     with pytest.raises(lib.ChfsiError):
         lib.Batch([64], filter_tile=6)  # not a grouped tile shape
     b.close()
+
+
+def test_batch_members_at_configuration_sizes(lib):
+    """Four k-point sequences with n drawn like the batching configuration's
+    (uniform in [2000, 6000]; nev = n/10, nex = nev/10), two steps each, mixed
+    precision, graph replay on: every member's eigenvalues against a library
+    eigensolver (rocSOLVER through torch) on its step's standard-form matrix,
+    and its generalized residuals, at both steps.  Gaussian draws on the
+    device."""
+    import torch
+    sizes = [int(v) for v in np.random.default_rng(3).integers(2000, 6001, 4)]
+    nevs = [n // 10 for n in sizes]
+    nexs = [max(1, v // 10) for v in nevs]
+    gens = [workloads.make_sequence_torch(n, 2, 3 + i, device="cuda", rng_kind="device") for i, n in enumerate(sizes)]
+    b = lib.Batch(sizes, use_graph=True, degree=20, seed=0, precision=1)
+    S0 = None
+    for ell in range(2):
+        ps = [next(g) for g in gens]
+        if ell == 0:
+            S0 = [p["S"] for p in ps]
+        ev, X, infos, st, rep = b.solve([p["H"] for p in ps], S0 if ell == 0 else [None] * 4, nevs, nexs, tol=1e-10)
+        assert st == [0, 0, 0, 0]
+        for i, p in enumerate(ps):
+            ref = torch.linalg.eigvalsh(p["A"]).cpu().numpy()[:nevs[i]]
+            hn = float(np.abs(torch.linalg.eigvalsh(p["H"]).cpu().numpy()).max())
+            ok, dmax = _checks.eig_ok(ev[i], ref, hn)
+            assert ok, (ell, i, dmax)
+            lt = torch.from_numpy(ev[i]).cuda().to(torch.complex128)
+            R = p["H"] @ X[i] - (S0[i] @ X[i]) * lt[None, :]
+            assert float(torch.linalg.vector_norm(R, dim=0).max()) <= 1e-10 * hn
+            assert infos[i]["warm_start"] == (1 if ell > 0 else 0)
+        del X, ps
+    assert rep["graph"] == 1
+    b.close()
