@@ -112,3 +112,39 @@ def test_server_rejects_invalid_block_sizes(lib, sequences):
             srv.submit(0, H, S, nev, nex)
         assert e.value.status == -1
     srv.close()
+
+
+def test_server_at_configuration_sizes(lib):
+    """Three sequences with n in the serving configuration's range (2000,
+    4500, 8000; nev 3 %, 10 % and 5 % of n, nex = nev/10), two steps each,
+    mixed precision, two workers under the 200 GB budget, submitted
+    interleaved: every result against a library eigensolver (rocSOLVER
+    through torch) on its step's standard-form matrix, with generalized
+    residuals.  Gaussian draws on the device."""
+    import torch
+    cases = [(2000, 0.03), (4500, 0.10), (8000, 0.05)]
+    seqs = [list(workloads.make_sequence_torch(n, 2, 700 + i, device="cuda", rng_kind="device"))
+            for i, (n, _) in enumerate(cases)]
+    srv = lib.Server(workers=2, hbm_budget_bytes=200 << 30, degree=20, seed=0, precision=1)
+    tickets = {}
+    for ell in range(2):
+        for s, (n, f) in enumerate(cases):
+            nev = int(n * f)
+            p = seqs[s][ell]
+            tickets[(s, ell)] = srv.submit(s, p["H"], seqs[s][0]["S"], nev, max(1, nev // 10), tol=1e-10)
+    for (s, ell), t in tickets.items():
+        ev, X, info, lat, st = srv.wait(t)
+        assert st == 0, (s, ell)
+        p = seqs[s][ell]
+        nev = len(ev)
+        ref = torch.linalg.eigvalsh(p["A"]).cpu().numpy()[:nev]
+        hn = float(np.abs(torch.linalg.eigvalsh(p["H"]).cpu().numpy()).max())
+        ok, dmax = _checks.eig_ok(ev, ref, hn)
+        assert ok, (s, ell, dmax)
+        lt = torch.from_numpy(ev).cuda().to(torch.complex128)
+        R = p["H"] @ X - (seqs[s][0]["S"] @ X) * lt[None, :]
+        assert float(torch.linalg.vector_norm(R, dim=0).max()) <= 1e-10 * hn
+        del X, R
+    stats = srv.stats()
+    assert stats["completed"] == 6 and stats["failed"] == 0
+    srv.close()
