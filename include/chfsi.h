@@ -170,8 +170,11 @@ chfsi_status chfsi_qr(chfsi_ctx ctx, void* Y, int64_t ldy, int64_t k);
  * by Householder QR.  *used_householder (may be NULL) tells which. */
 chfsi_status chfsi_orthonormalize(chfsi_ctx ctx, void* Y, int64_t ldy, int64_t k, int32_t* used_householder);
 
-/* Hermitian eigensolver (Jacobi): G (device k x k, read only) = Z diag(w) Z^H,
- * w host (k, ascending), Z device k x k. */
+/* Hermitian eigensolver of the reduced problem (Algorithm 1's Rayleigh-Ritz
+ * step; exact to working accuracy): G (device k x k, Hermitian, both
+ * triangles read, read only) = Z diag(w) Z^H, w host (k, ascending), Z device
+ * k x k.  Cyclic Jacobi (one workgroup up to k = 96, block-ordered sweeps
+ * above), eigenvector refinement once G is nearly diagonal. */
 chfsi_status chfsi_eigh(chfsi_ctx ctx, const void* G, int64_t ldg, int64_t k, double* w, void* Z, int64_t ldz);
 
 /* Rayleigh-Ritz on an orthonormal block: G = Y^H A Y, G = Z diag(mu) Z^H,
