@@ -2,14 +2,18 @@
 """Benchmark: Chebyshev-filtered subspace iteration on one MI355X.
 
 One step = one complete solve (Algorithm 1: reduction, Lanczos, filter, QR,
-Rayleigh-Ritz, locking, back-transform) of one generalized eigenproblem of a
-correlated sequence, warm-started from the previous solve's vectors, with the
-matrices already resident in device memory.
+Rayleigh-Ritz, locking, back-transform) of one generalized eigenproblem with
+the matrices already resident in device memory.
 
-Default workload: a sequence of correlated complex Hermitian DGEVPs with
-n = 4000, nev = 400, nex = 40, Chebyshev degree 20, tol 1e-10, FP64
-throughout (synthetic FLAPW-shaped inputs; the paper's FLEUR matrices are not
-available).  Prints one JSON line.
+Default workload: a single complex Hermitian DGEVP with n = 10000,
+nev = 600, nex = 60, Chebyshev degree 20, tol 1e-10, solved cold (random
+start block) at every step, FP64 throughout (`value`); the same problem is
+then solved with the mixed-precision filter (complex FP32 degree steps, FP64
+everything else and FP64 final sweeps), reported beside it with the error of
+every eigenpair against the constructed spectrum and the FP64 path.  The
+inputs are synthetic FLAPW-shaped problems (the paper's FLEUR matrices are
+not available).  Prints one JSON line.  `--workload seq4000` runs the
+correlated n = 4000 sequence (warm starts) instead.
 
 The filter kernel is timed live with HIP events on the solver's stream
 (profile mode of the library): one event pair around each filter call's
@@ -39,10 +43,11 @@ WORKLOADS = {
     # single problem of the small configuration
     "single512": dict(n=512, nev=51, nex=13, degree=10, seed=0, sequence=False,
                       desc="single complex Hermitian DGEVP, FLAPW-shaped synthetic spectrum"),
-    # single large problem (FP64 path of the precision study)
+    # single large problem, cold solves: FP64 (the value) and mixed precision
     "single10000": dict(n=10000, nev=600, nex=60, degree=20, seed=2, sequence=False,
-                        desc="single complex Hermitian DGEVP, FLAPW-shaped synthetic spectrum"),
+                        desc="single complex Hermitian DGEVP, FLAPW-shaped synthetic spectrum, cold start"),
 }
+DEFAULT_WORKLOAD = "single10000"
 
 
 def log(*a):
@@ -63,19 +68,16 @@ def make_problems(cfg, count, device):
     return [p] * count
 
 
-def residual_check(p, evals, X):
-    """max_j ||H x_j - lam_j S x_j|| / ||H||_2 estimate, on the device (a
-    check of the result, not part of the timed path)."""
+def residual_norm_scale(H):
+    """||H||_2 from 40 Lanczos steps with full re-orthogonalization on the
+    device: an estimate from below that is accurate to many digits (a check of
+    results, not part of any timed path)."""
+    import numpy as np
     import torch
-    H, S = p["H"], p["S"]
-    lam = torch.as_tensor(evals, dtype=torch.complex128, device=X.device)
-    R = H @ X - (S @ X) * lam[None, :]
-    # ||H||_2 from the Lanczos process of 40 steps (full re-orthogonalization),
-    # an estimate from below that is accurate to many digits
     n = H.shape[0]
     g = torch.Generator(device="cpu").manual_seed(7)
     v = torch.complex(torch.randn(n, generator=g, dtype=torch.float64),
-                      torch.randn(n, generator=g, dtype=torch.float64)).to(X.device)
+                      torch.randn(n, generator=g, dtype=torch.float64)).to(H.device)
     V = [v / torch.linalg.vector_norm(v)]
     alpha, beta = [], []
     for j in range(min(40, n)):
@@ -88,33 +90,65 @@ def residual_check(p, evals, X):
             break
         beta.append(b)
         V.append(w / b)
-    import numpy as np
     T = np.diag(alpha) + np.diag(beta[:len(alpha) - 1], 1) + np.diag(beta[:len(alpha) - 1], -1)
-    hn = float(np.abs(np.linalg.eigvalsh(T)).max())
+    return float(np.abs(np.linalg.eigvalsh(T)).max())
+
+
+def residual_check(p, evals, X, hnorm=None):
+    """max_j ||H x_j - lam_j S x_j|| / ||H||_2 on the device (a check of the
+    result, not part of the timed path)."""
+    import torch
+    H, S = p["H"], p["S"]
+    lam = torch.as_tensor(evals, dtype=torch.complex128, device=X.device)
+    R = H @ X - (S @ X) * lam[None, :]
+    hn = hnorm if hnorm is not None else residual_norm_scale(H)
     return float(torch.linalg.vector_norm(R, dim=0).max()) / hn
 
 
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "chebyshev_step_f64_seq4000_traffic.md")
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1305_5120_amd", "csrc", "zgemm.hip")
 
 
-def measured_traffic(workload):
-    """HBM bytes per filter launch from the committed counter summary, or
-    None when the summary is absent, for another workload, or was taken on a
-    different version of the kernel source."""
-    import hashlib
-    if workload != "seq4000" or not os.path.exists(TRAFFIC_FILE):
-        return None
+def _summary_fields(path):
+    """`- key: value` lines of a committed profile summary."""
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if vals.get("kernel_source_sha256") != sha:
+    return vals
+
+
+def _current_summary(name):
+    """Fields of profiles/<name> when it exists and was taken on the current
+    kernel source (its kernel_source_sha256 matches), else None."""
+    import hashlib
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
         return None
+    vals = _summary_fields(path)
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    return vals if vals.get("kernel_source_sha256") == sha else None
+
+
+def measured_traffic(workload):
+    """HBM bytes per filter launch from the committed counter summary of this
+    workload, or None when the summary is absent or was taken on a different
+    version of the kernel source."""
+    vals = _current_summary(f"chebyshev_step_f64_{workload}_traffic.md")
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]) if vals else None
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_mfma_busy(workload):
+    """Matrix-core busy fraction of the filter kernel from the committed
+    counter summary (SQ_VALU_MFMA_BUSY_CYCLES over the CUs' busy cycles), or
+    None."""
+    vals = _current_summary(f"chebyshev_step_f64_{workload}_mfma.md")
+    try:
+        return float(vals["mfma_busy_fraction"]) if vals else None
     except (KeyError, ValueError):
         return None
 
@@ -140,54 +174,105 @@ def calibrate_copy():
     log(f"[bench] copy calibration: k_copy2d launches with grid {n * n} moving {16 * n * n} bytes each way")
 
 
-def cpu_baseline(cfg, gpu_filter_flops_per_solve, target_seconds=12.0):
-    """Time the CPU oracle's filter on a bounded sample of the same problem
-    and scale it to solves/s of the filter work of one GPU solve."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_c0_solves(threads, runs, warmup, budget_s):
+    """Full oracle solves of the small configuration (n = 512, nev = 51,
+    nex = 13, degree 10, tol 1e-10, cold start) on `threads` threads: median
+    of up to `runs` timed solves after `warmup` untimed ones, stopping early
+    once `budget_s` seconds have been spent."""
     import numpy as np
     import oracle
     import workloads
+    p = workloads.make_problem(512, 0)
+    prev = oracle.set_threads(threads)
+    try:
+        t_all = time.perf_counter()
+        for _ in range(warmup):
+            oracle.solve(p.H, p.S, 51, 13, tol=1e-10, degree=10, seed=0)
+        times = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            r = oracle.solve(p.H, p.S, 51, 13, tol=1e-10, degree=10, seed=0)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_all > budget_s:
+                break
+        assert r["info"]["status"] == 0
+        return {"threads": oracle.set_threads(prev), "median_s": float(np.median(times)), "runs": len(times),
+                "warmup": warmup, "iterations": r["info"]["iterations"]}
+    finally:
+        oracle.set_threads(prev)
+
+
+def cpu_baseline(cfg, gpu_filter_flops_per_solve, target_seconds=8.0):
+    """The CPU oracle timed on this host.
+
+    * value: the oracle's Chebyshev filter timed on a bounded sample of the
+      benchmarked problem's size (n, a few columns and degree steps, about
+      target_seconds), its rate applied to the filter work of one GPU solve
+      -- an upper bound on the oracle's solve rate, since the rest of its
+      solve (reduction, QR, Rayleigh-Ritz, residuals) is not counted;
+    * c0_full_solve: complete oracle solves of the small configuration
+      (n = 512) on all threads (warm-up, median of 5) and on one thread."""
+    import numpy as np
+    import oracle
+    import workloads
+    threads = oracle.set_threads(0)
+    full = _oracle_c0_solves(threads, 5, 1, 25.0)
+    one = _oracle_c0_solves(1, 3, 0, 20.0)
+    log(f"[bench] oracle n=512 solve: {full['median_s']:.2f} s on {full['threads']} threads, "
+        f"{one['median_s']:.2f} s on 1 thread")
     n = cfg["n"]
     rng = np.random.default_rng(99)
-    # standard-form matrix with the workload's spectrum law (host copy)
     lam = workloads.spectrum(n, rng)
-    G = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / math.sqrt(2)
-    Q, _ = np.linalg.qr(G)
-    A = np.asfortranarray((Q * lam) @ Q.conj().T)
-    A = (A + A.conj().T) / 2
-    del G, Q
+    # the oracle's filter runs the full dense n x n product for every column
+    # whatever the values, so a diagonal matrix with the workload's spectrum
+    # costs what a dense one does (and needs no n x n QR on the host); its
+    # loops are parallel over columns, so the sample takes a multiple of the
+    # thread count
+    A = np.asfortranarray(np.diag(lam).astype(np.complex128))
     lo, hi = float(np.sort(lam)[cfg["nev"] + cfg["nex"]]), float(lam.max() * 1.1)
-    m = 2
-    k = 8
-    Y = oracle.gauss_block(1, 3, n, k)
-    t0 = time.perf_counter()
-    oracle.chebyshev_filter(A, Y, m, lo, hi, float(lam.min()))
-    dt = time.perf_counter() - t0
-    rate = 8.0 * n * n * k * m / dt
-    # scale the sample (columns first, then degree) to about target_seconds;
-    # the rate grows with the column count, so rescale once more from the
-    # second measurement
-    for _ in range(2):
-        k2 = int(max(8, min(cfg["nev"] + cfg["nex"], rate * target_seconds / (8.0 * n * n * m))))
-        m2 = int(max(2, min(cfg["degree"], round(rate * target_seconds / (8.0 * n * n * k2)))))
-        if (k2 <= k and m2 <= m) or dt >= 0.5 * target_seconds:
-            break
-        Y = oracle.gauss_block(1, 3, n, k2)
+    k, m = threads, 1
+    rate, dt = 0.0, 0.0
+    for _ in range(3):
+        Y = oracle.gauss_block(1, 3, n, k)
         t0 = time.perf_counter()
-        oracle.chebyshev_filter(A, Y, m2, lo, hi, float(lam.min()))
+        oracle.chebyshev_filter(A, Y, m, lo, hi, float(lam.min()))
         dt = time.perf_counter() - t0
-        rate = 8.0 * n * n * k2 * m2 / dt
-        k, m = k2, m2
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        rate = 8.0 * n * n * k * m / dt
+        if dt >= 0.4 * target_seconds:
+            break
+        grow = target_seconds / dt
+        m2 = int(min(cfg["degree"], max(1, round(m * grow))))
+        k2 = k if m2 * dt / m >= 0.4 * target_seconds else \
+            int(min(cfg["nev"] + cfg["nex"], threads * max(1, round(k * grow * m / m2 / threads))))
+        if (m2, k2) == (m, k):
+            break
+        m, k = m2, k2
     solve_s = gpu_filter_flops_per_solve / rate
     return {
         "value": 1.0 / solve_s,
         "unit": "solves/s",
-        "cores": cores,
+        "cores": threads,
+        "cpu_model": cpu_model(),
         "kind": "oracle",
-        "sample": (f"oracle Chebyshev filter, n={n}, {k} columns, degree {m} ({dt:.1f} s, "
-                   f"{rate / 1e9:.2f} GFLOP/s); solve rate = that rate applied to the filter work of one GPU "
-                   f"solve ({gpu_filter_flops_per_solve / 1e12:.2f} TFLOP), the rest of the solve not counted"),
+        "sample": (f"oracle Chebyshev filter at n={n}: {k} columns, degree {m} ({dt:.1f} s, "
+                   f"{rate / 1e9:.2f} GFLOP/s on {threads} threads); value = that rate applied to the filter work "
+                   f"of one GPU solve ({gpu_filter_flops_per_solve / 1e12:.2f} TFLOP), the rest of the solve not "
+                   f"counted (an upper bound on the oracle's solve rate)"),
         "filter_gflops": rate / 1e9,
+        "c0_full_solve": {"workload": "n=512, nev=51, nex=13, degree 10, tol 1e-10, cold start",
+                          "all_threads": full, "one_thread": one,
+                          "solves_per_s_all_threads": 1.0 / full["median_s"],
+                          "solves_per_s_one_thread": 1.0 / one["median_s"]},
     }
 
 
@@ -431,6 +516,32 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def theta_angles(prevX, X, S):
+    """Angles theta_i between consecutive eigenvectors x_i^(l-1), x_i^(l) in
+    the S inner product (Sec. 2's correlation measure, read for S-normalized
+    vectors as theta_i = arccos |<x_i^(l-1), x_i^(l)>_S|).  sin(theta) is taken
+    from the S-norm of the part of x^(l) orthogonal to x^(l-1) and theta =
+    atan2(sin, cos), which resolves small angles that arccos of a cosine near
+    1 would round away.  Tensors of any device; returns a numpy array."""
+    import torch
+    c = torch.sum(prevX.conj() * (S @ X), dim=0)           # <x_(l-1), x_l>_S
+    R = X - prevX * c[None, :]                             # part orthogonal to x_(l-1)
+    sin = torch.sqrt(torch.clamp(torch.real(torch.sum(R.conj() * (S @ R), dim=0)), min=0.0))
+    return torch.atan2(sin, torch.abs(c)).cpu().numpy()
+
+
+def _standard_eigvals(H, S, count):
+    """The `count` smallest eigenvalues of the pencil (H, S) from a dense
+    library solver on the device (Cholesky, two triangular solves,
+    eigvalsh): the reference of the warm/cold study's checks."""
+    import torch
+    Lc = torch.linalg.cholesky(S)
+    W = torch.linalg.solve_triangular(Lc, H, upper=False)
+    A = torch.linalg.solve_triangular(Lc, W.conj().T.contiguous(), upper=False)
+    A = (A + A.conj().T) / 2
+    return torch.linalg.eigvalsh(A)[:count].cpu().numpy()
+
+
 def run_warmcold(args):
     """Warm versus cold starts along correlated sequences: a fixed
     perturbation with fixed S, the same with S varying (through the
@@ -462,11 +573,7 @@ def run_warmcold(args):
     torch.cuda.synchronize()
 
     def theta_median(prevX, X, S):
-        c = torch.sum(prevX.conj() * (S @ X), dim=0)           # <x_(l-1), x_l>_S
-        R = X - prevX * c[None, :]                             # part orthogonal to x_(l-1)
-        sin = torch.sqrt(torch.clamp(torch.real(torch.sum(R.conj() * (S @ R), dim=0)), min=0.0))
-        th = torch.atan2(sin, torch.abs(c)).cpu().numpy()
-        return float(np.median(th))
+        return float(np.median(theta_angles(prevX, X, S)))
 
     rows = {}
     for variant in ("fixed_S", "varying_S", "converging"):
@@ -488,15 +595,27 @@ def run_warmcold(args):
             tw = time.perf_counter() - t0
             cold.reset()
             t0 = time.perf_counter()
-            evc, Xc, ic, _ = chfsi.solve(cold, H, S_c, nev, nex, tol=1e-10, want_vectors=False)
+            evc, Xc, ic, _ = chfsi.solve(cold, H, S_c, nev, nex, tol=1e-10)
             torch.cuda.synchronize()
             tc = time.perf_counter() - t0
             theta = theta_median(prevX, X, Sm) if prevX is not None else None
+            # verification (outside the timed solves): residuals of both
+            # starts' pairs and their eigenvalues against a dense solver
+            Sfull = Sm
+            ref = _standard_eigvals(H, Sfull, nev)
+            hn = residual_norm_scale(H)
+            err_w = float(np.abs(np.asarray(ev) - ref).max() / hn)
+            err_c = float(np.abs(np.asarray(evc) - ref).max() / hn)
+            res_w = residual_check({"H": H, "S": Sfull}, ev, X, hnorm=hn)
+            res_c = residual_check({"H": H, "S": Sfull}, evc, Xc, hnorm=hn)
             prevX = X
             recs.append({"step": ell, "warm_iterations": iw["iterations"], "cold_iterations": ic["iterations"],
-                         "warm_s": tw, "cold_s": tc, "warm_start": iw["warm_start"], "median_theta": theta})
+                         "warm_s": tw, "cold_s": tc, "warm_start": iw["warm_start"], "median_theta": theta,
+                         "warm_max_rel_residual": res_w, "cold_max_rel_residual": res_c,
+                         "warm_max_eig_error": err_w, "cold_max_eig_error": err_c})
             log(f"[bench] {variant} step {ell}: warm {iw['iterations']} it {tw:.3f} s, cold {ic['iterations']} it "
-                f"{tc:.3f} s, median theta {theta}")
+                f"{tc:.3f} s, median theta {theta}; residual warm {res_w:.1e} cold {res_c:.1e}, "
+                f"eigenvalue error warm {err_w:.1e} cold {err_c:.1e} (x ||H||)")
         warm.release()
         cold.release()
         rows[variant] = recs
@@ -525,7 +644,10 @@ def run_mixed_same_workload(args, cfg, probs, fp64_rate):
     n, nev, nex = cfg["n"], cfg["nev"], cfg["nex"]
     ctx = chfsi.create(n, degree=cfg["degree"], seed=0, precision=1, profile=0 if args.no_profile else 1)
     S0 = probs[0]["S"]
-    total = args.warmup + args.steps
+    # a bounded pass: the timed FP64 region above is the benchmark's value
+    warmup = min(args.warmup, 1)
+    steps = min(args.steps, 5)
+    total = warmup + steps
 
     def one(i):
         p = probs[i]
@@ -534,35 +656,63 @@ def run_mixed_same_workload(args, cfg, probs, fp64_rate):
             ctx.reset()
         return chfsi.solve(ctx, p["H"], S, nev, nex, tol=1e-10)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         one(i)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for i in range(args.warmup, total):
+    for i in range(warmup, total):
         ev, X, info, st = one(i)
         infos.append(info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     rel_res = residual_check(probs[total - 1], ev, X)
+    del X
     ctx.release()
     f32s = sum(i["filter_kernel_seconds_fp32"] for i in infos)
     f32f = sum(i["filter_flops_fp32"] for i in infos)
-    rate = args.steps / elapsed
+    rate = steps / elapsed
     log(f"[bench] mixed precision, same problems: {rate:.3f} solves/s ({rate / fp64_rate:.2f}x FP64), "
         f"iterations {[i['iterations'] for i in infos]}, residual {rel_res:.2e}")
-    return {"solves_per_s": rate, "speedup_vs_fp64": rate / fp64_rate, "ms_per_step": 1e3 * elapsed / args.steps,
+    f64s = sum(i["filter_kernel_seconds"] for i in infos) - f32s
+    f64f = sum(i["filter_flops"] for i in infos) - f32f
+    phase = {k: sum(i[k] for i in infos) / len(infos)
+             for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid", "t_total")}
+    return {"evals": ev, "solves_per_s": rate, "speedup_vs_fp64": rate / fp64_rate, "ms_per_step": 1e3 * elapsed / steps,
+            "steps": steps, "warmup": warmup,
             "iterations": [i["iterations"] for i in infos], "iterations_fp32": [i["iterations_fp32"] for i in infos],
             "max_rel_residual": rel_res, "filter_tflops_fp32": f32f / f32s / 1e12 if f32s else None,
-            "filter_flops_fp32_share": f32f / max(1.0, sum(i["filter_flops"] for i in infos))}
+            "filter_tflops_fp64_part": f64f / f64s / 1e12 if f64s > 0 else None,
+            "filter_flops_fp32_share": f32f / max(1.0, sum(i["filter_flops"] for i in infos)),
+            "fp32_roofline": {"bound": "mfma", "achieved": f32f / f32s / 1e12 if f32s else None, "peak": 157.3,
+                              "unit": "TFLOP/s", "frac": f32f / f32s / 1e12 / 157.3 if f32s else None},
+            "phase_seconds_per_solve": phase}
+
+
+def _eig_report(lam_exact, ev64, ev_mixed, anorm):
+    """Per-eigenpair errors (3 significant digits) relative to ||A||_2: FP64
+    and mixed against the constructed spectrum, mixed against FP64."""
+    import numpy as np
+    ex = np.sort(np.asarray(lam_exact))[:len(ev64)]
+
+    def vec(d):
+        return [float(f"{x:.3g}") for x in np.asarray(d)]
+
+    d64 = np.abs(np.asarray(ev64) - ex) / anorm
+    dmx = np.abs(np.asarray(ev_mixed) - ex) / anorm
+    dmf = np.abs(np.asarray(ev_mixed) - np.asarray(ev64)) / anorm
+    return {"norm": "|dlambda_i| / ||A||_2, i = 1..nev ascending",
+            "max": {"fp64_vs_exact": float(d64.max()), "mixed_vs_exact": float(dmx.max()),
+                    "mixed_vs_fp64": float(dmf.max())},
+            "fp64_vs_exact": vec(d64), "mixed_vs_exact": vec(dmx), "mixed_vs_fp64": vec(dmf)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="seq4000",
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
                     choices=sorted(WORKLOADS) + ["precision", "batch", "serve", "warmcold"])
     ap.add_argument("--members", type=int, default=16, help="sequences (batch / serve forms)")
     ap.add_argument("--seq-steps", type=int, default=3, help="problems per sequence (batch / serve / warmcold)")
@@ -596,6 +746,7 @@ def main():
     dev = torch.device("cuda:0")
     cfg = WORKLOADS[args.workload]
     total = args.warmup + args.steps
+    log(f"[bench] workload {args.workload}: generating inputs")
     probs = make_problems(cfg, total, dev)
     torch.cuda.synchronize()
 
@@ -608,7 +759,7 @@ def main():
         p = probs[i]
         S = S0 if i == 0 else (None if cfg["sequence"] else p["S"])
         if not cfg["sequence"]:
-            ctx.reset()
+            ctx.reset()  # cold start: the timed work is the whole solve from a random block
         ev, X, info, st = chfsi.solve(ctx, p["H"], S, nev, nex, tol=1e-10)
         return ev, X, info
 
@@ -620,23 +771,26 @@ def main():
     for i in range(args.warmup, total):
         ev, X, info = one(i)
         infos.append(info)
+        log(f"[bench] timed solve {i - args.warmup}: {info['iterations']} iterations, warm={info['warm_start']}, "
+            f"{info['t_total']:.3f} s, filter {info['t_filter']:.3f} s")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for i, info in enumerate(infos):
-        log(f"[bench] timed solve {i}: {info['iterations']} iterations, warm={info['warm_start']}, "
-            f"{info['t_total']:.3f} s, filter {info['t_filter']:.3f} s")
     elapsed = t1 - t0
     rel_res = residual_check(probs[total - 1], ev, X)
+    ev64 = ev
+    del X
 
     flops = sum(i["filter_flops"] for i in infos)
     fsec = sum(i["filter_kernel_seconds"] for i in infos)
     launches = sum(i["filter_launches"] for i in infos)
     achieved = flops / fsec / 1e12 if fsec > 0 else None
-    phase = {k: sum(i[k] for i in infos) for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid")}
+    phase = {k: sum(i[k] for i in infos) / len(infos)
+             for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid", "t_total")}
     # algorithmic bytes per launch: A once, Y_i and Y_{i-1} read, Y_{i+1}
     # written; 8 n^2 k_a flops per launch give the mean k_a
     mean_ka = (flops / launches) / (8.0 * n * n) if launches else 0.0
     alg_bytes = 16.0 * n * n + 48.0 * n * mean_ka
+    busy = measured_mfma_busy(args.workload)
     out = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -657,21 +811,27 @@ def main():
         "filter_launches": launches,
         "max_rel_residual": rel_res,
         "iterations": [i["iterations"] for i in infos],
-        "phase_seconds": phase,
+        "phase_seconds_per_solve": phase,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_MFMA) if achieved else None,
                      "flop_count": FLOP_COUNT_NOTE,
-                     "matrix_core_frac": (GAUSS3_SHARE * achieved / PEAK_FP64_MFMA) if achieved else None,
+                     "matrix_core_frac_from_flops": (GAUSS3_SHARE * achieved / PEAK_FP64_MFMA) if achieved else None,
+                     "matrix_core_busy_counter": busy,
                      "traffic": measured_traffic(args.workload),
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "algorithmic_flops_per_launch": flops / launches if launches else None},
     }
     if not args.no_mixed:
-        out["mixed_precision"] = run_mixed_same_workload(args, cfg, probs, out["value"])
+        mixed = run_mixed_same_workload(args, cfg, probs, out["value"])
+        ev_mixed = mixed.pop("evals")
+        out["mixed_precision"] = mixed
+        if not cfg["sequence"]:
+            anorm = float(abs(probs[0]["lam"]).max())
+            out["eigenpair_errors"] = _eig_report(probs[0]["lam"], ev64, ev_mixed, anorm)
     if args.calibrate_copy:
         calibrate_copy()
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a sample")
+        log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(cfg, flops / len(infos))
     print(json.dumps(out), flush=True)
     ctx.release()

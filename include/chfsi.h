@@ -8,7 +8,7 @@
  * Napoli, "A Parallel and Scalable Iterative Solver for Sequences of Dense
  * Eigenproblems Arising in FLAPW" (arXiv 1305.5120): reduction to standard
  * form (Section 3), a Lanczos estimate of the spectrum's upper end, then
- * repeated Chebyshev filtering (eq. (3)), QR re-orthonormalization,
+ * repeated Chebyshev filtering (eq. (2)), QR re-orthonormalization,
  * Rayleigh-Ritz and locking of converged pairs.  Solving a sequence of
  * correlated problems (Section 2) warm-starts each solve from the previous
  * solution, which the context keeps on the device.
@@ -151,7 +151,7 @@ chfsi_status chfsi_solve(chfsi_ctx ctx, const void* H, int64_t ldh, const void* 
  * factor, zero upper triangle), Linv = L^{-1}.  Any pointer may be NULL. */
 chfsi_status chfsi_copy_factors(chfsi_ctx ctx, void* A, int64_t lda, void* L, int64_t ldl, void* Linv, int64_t ldi);
 
-/* Chebyshev filter (eq. (3), scaled and shifted): Y (device n x k) is
+/* Chebyshev filter (eq. (2), scaled and shifted): Y (device n x k) is
  * overwritten with p(A) Y, p(t) = C_m((t - c)/e) / C_m((a0 - c)/e),
  * c = (a + b)/2, e = (b - a)/2.  Requires b > a, m >= 1.  With the context's
  * precision = 1 the recurrence runs in complex FP32 (A and Y rounded to FP32,
@@ -222,15 +222,15 @@ chfsi_status chfsi_zgemm(chfsi_ctx ctx, int32_t opA, int32_t opB, int64_t M, int
  * one sequence of eigenproblems per k-point, all of one SCF step solved
  * together).  A batch solve runs Algorithm 1 for every member in lockstep:
  * each outer iteration launches the degree steps of all members' Chebyshev
- * filters (eq. (3)) as one persistent grouped launch per step and precision,
+ * filters (eq. (2)) as one persistent grouped launch per step and precision,
  * then orthonormalizes, projects and locks each member on its own stream.
  * The grouped step's tile shape is chosen online: the first outer iterations
  * of each precision try the candidate shapes on the real work and the one
  * with the highest measured rate is kept for the rest of the batch's life
- * (the block-size study of Section 4, made automatic).  With use_graph = 1
+ * (the block-size study of Sec. 3 and Fig. 2, made automatic).  With use_graph = 1
  * the degree steps of an iteration replay as one captured HIP graph whose
  * kernels read the members' widths, pointers and alpha / beta / gamma
- * (eq. (3)) from device memory, so the same graph serves every iteration
+ * (eq. (2)) from device memory, so the same graph serves every iteration
  * while columns lock.  Each member keeps its block and bounds between calls
  * and warm-starts from them, as chfsi_solve does. */
 typedef struct chfsi_batch_s* chfsi_batch;

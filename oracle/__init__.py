@@ -61,6 +61,8 @@ def lib():
         L.orc_solve.argtypes = [c_i64, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp,
                                 c_dbl, ctypes.POINTER(OrcOpts), c_vp, c_vp, c_i64, c_vp, ctypes.POINTER(OrcInfo)]
         L.orc_solve.restype = ctypes.c_int32
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -72,6 +74,12 @@ def _f(a):
 
 def _p(a):
     return a.ctypes.data_as(c_vp)
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (n < 1: unchanged); returns the
+    previous count."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def philox4x32_10(ctr, key):

@@ -28,8 +28,25 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct { double re, im; } cplx;
+
+/* Thread count of the OpenMP loops (timing on a chosen number of cores);
+   returns the count in effect before the call, 1 without OpenMP.  n < 1
+   leaves it unchanged. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  int prev = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return prev;
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 static inline cplx c_mul(cplx a, cplx b) { cplx r = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; return r; }
 /* conj(a) * b */
@@ -451,7 +468,7 @@ void orc_lanczos(int64_t n, const cplx* A, int64_t lda, int64_t steps, const cpl
 
 /* ------------------------------------------------------------------------ */
 /* Chebyshev filter (Algorithm 1, filter step; three-term recurrence of      */
-/* Chebyshev polynomials of the first kind, eq. (3)).  The recurrence is     */
+/* Chebyshev polynomials of the first kind, eq. (2)).  The recurrence is     */
 /* applied to (A - c I)/e, which maps the unwanted interval [a, b] onto      */
 /* [-1, 1], and is scaled so that the polynomial equals 1 at a0:             */
 /*   e = (b - a)/2, c = (b + a)/2, sigma_1 = e/(a0 - c), tau = 2/sigma_1,     */

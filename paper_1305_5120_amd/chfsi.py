@@ -116,8 +116,22 @@ def _check_dev(t, name):
         raise TypeError(f"{name} must be a matrix")
 
 
+def _check_shape(t, rows, cols, name):
+    """Exact logical shape: the C side sees only a pointer and a leading
+    dimension, so a larger matrix would be read as its leading block and a
+    smaller view would be read past its end."""
+    if tuple(t.shape) != (rows, cols):
+        raise ValueError(f"{name} must be {rows} x {cols}, got {tuple(t.shape)}")
+
+
 def colmajor(t):
-    """(tensor whose storage is the column-major matrix, leading dimension)."""
+    """(tensor whose storage is the column-major matrix, leading dimension).
+    A tensor with a pending conjugation (``H.conj()``) or negation is
+    materialised first, so the pointer holds the values the tensor shows."""
+    if t.is_conj():
+        t = t.resolve_conj()
+    if t.is_neg():
+        t = t.resolve_neg()
     rows = t.shape[0]
     if t.stride(0) == 1 and (t.shape[1] <= 1 or t.stride(1) >= max(rows, 1)):
         return t, max(t.stride(1), rows, 1)
@@ -183,9 +197,11 @@ def reset(ctx):
 
 def reduce(ctx, H, S=None):
     _check_dev(H, "H")
+    _check_shape(H, ctx.n, ctx.n, "H")
     Hc, ldh = colmajor(H)
     if S is not None:
         _check_dev(S, "S")
+        _check_shape(S, ctx.n, ctx.n, "S")
         Sc, lds = colmajor(S)
         sp = Sc.data_ptr()
     else:
@@ -208,15 +224,19 @@ def solve(ctx, H, S, nev, nex, V_warm=None, tol=1e-10, want_vectors=True, raise_
     """Algorithm 1 on (H, S).  Returns (evals numpy (nev,), X tensor n x nev
     or None, info dict, status)."""
     _check_dev(H, "H")
+    _check_shape(H, ctx.n, ctx.n, "H")
     Hc, ldh = colmajor(H)
     if S is not None:
         _check_dev(S, "S")
+        _check_shape(S, ctx.n, ctx.n, "S")
         Sc, lds = colmajor(S)
         sp = Sc.data_ptr()
     else:
         Sc, lds, sp = None, ctx.n, None
     if V_warm is not None:
         _check_dev(V_warm, "V_warm")
+        if V_warm.shape[0] != ctx.n or V_warm.shape[1] > nev + nex:
+            raise ValueError(f"V_warm must be {ctx.n} x kw with kw <= nev + nex, got {tuple(V_warm.shape)}")
         Vc, ldv = colmajor(V_warm)
         vp, kw = Vc.data_ptr(), V_warm.shape[1]
     else:
@@ -236,6 +256,8 @@ def filter(ctx, A, Y, m, a, b, a0):
     """Y <- p(A) Y (in place on Y, a complex128 device matrix)."""
     _check_dev(A, "A")
     _check_dev(Y, "Y")
+    _check_shape(A, ctx.n, ctx.n, "A")
+    _check_shape(Y, ctx.n, Y.shape[1], "Y")
     Ac, lda = colmajor(A)
     Yc, ldy = colmajor(Y)
     ctx._raise(ctx.lib.chfsi_filter(ctx.h, Ac.data_ptr(), lda, Yc.data_ptr(), ldy, Y.shape[1], int(m), float(a),
@@ -248,6 +270,7 @@ def filter(ctx, A, Y, m, a, b, a0):
 def qr(ctx, Y):
     """Y <- Q (Householder), in place."""
     _check_dev(Y, "Y")
+    _check_shape(Y, ctx.n, Y.shape[1], "Y")
     Yc, ldy = colmajor(Y)
     ctx._raise(ctx.lib.chfsi_qr(ctx.h, Yc.data_ptr(), ldy, Y.shape[1]))
     if Yc.data_ptr() != Y.data_ptr():
@@ -259,6 +282,7 @@ def orthonormalize(ctx, Y):
     """Y <- orthonormal basis of span(Y), in place (the solver's step).
     Returns True when Householder QR was used."""
     _check_dev(Y, "Y")
+    _check_shape(Y, ctx.n, Y.shape[1], "Y")
     Yc, ldy = colmajor(Y)
     used = c_i32(0)
     ctx._raise(ctx.lib.chfsi_orthonormalize(ctx.h, Yc.data_ptr(), ldy, Y.shape[1], ctypes.byref(used)))
@@ -270,6 +294,7 @@ def orthonormalize(ctx, Y):
 def eigh(ctx, G):
     """(w numpy ascending, Z tensor) of a Hermitian device matrix."""
     _check_dev(G, "G")
+    _check_shape(G, G.shape[0], G.shape[0], "G")
     Gc, ldg = colmajor(G)
     k = G.shape[0]
     w = np.zeros(k)
@@ -282,6 +307,8 @@ def rayleigh_ritz(ctx, A, Y):
     """(mu numpy ascending, Y <- Y Z in place)."""
     _check_dev(A, "A")
     _check_dev(Y, "Y")
+    _check_shape(A, ctx.n, ctx.n, "A")
+    _check_shape(Y, ctx.n, Y.shape[1], "Y")
     Ac, lda = colmajor(A)
     Yc, ldy = colmajor(Y)
     k = Y.shape[1]
@@ -296,6 +323,11 @@ def residuals(ctx, A, L, Y, mu):
     _check_dev(A, "A")
     _check_dev(L, "L")
     _check_dev(Y, "Y")
+    _check_shape(A, ctx.n, ctx.n, "A")
+    _check_shape(L, ctx.n, ctx.n, "L")
+    _check_shape(Y, ctx.n, Y.shape[1], "Y")
+    if len(mu) != Y.shape[1]:
+        raise ValueError("one Ritz value per column of Y")
     Ac, lda = colmajor(A)
     Lc, ldl = colmajor(L)
     Yc, ldy = colmajor(Y)
@@ -309,6 +341,7 @@ def residuals(ctx, A, L, Y, mu):
 
 def lanczos(ctx, A, steps, seed, stream_id):
     _check_dev(A, "A")
+    _check_shape(A, ctx.n, ctx.n, "A")
     Ac, lda = colmajor(A)
     out = np.zeros(3)
     ctx._raise(ctx.lib.chfsi_lanczos(ctx.h, Ac.data_ptr(), lda, int(steps), int(seed), int(stream_id),
@@ -345,6 +378,16 @@ def zgemm(ctx, opA, opB, A, B, alpha=1.0, beta=0.0, X=None, gamma=0.0, Z=None, C
     M = M if M is not None else (A.shape[0] if opA == 0 else A.shape[1])
     K = K if K is not None else (A.shape[1] if opA == 0 else A.shape[0])
     N = N if N is not None else (B.shape[1] if opB == 0 else B.shape[0])
+    # op(A) must hold at least M x K, op(B) K x N, X / Z / C M x N
+    ra, ca = (M, K) if opA == 0 else (K, M)
+    rb, cb = (K, N) if opB == 0 else (N, K)
+    if A.shape[0] < ra or A.shape[1] < ca or B.shape[0] < rb or B.shape[1] < cb:
+        raise ValueError("zgemm: A or B smaller than the product's sizes")
+    for t, nm in ((X, "X"), (Z, "Z"), (C, "C")):
+        if t is not None:
+            _check_dev(t, nm)
+            if t.shape[0] < M or t.shape[1] < N:
+                raise ValueError(f"zgemm: {nm} smaller than M x N")
     if C is None:
         C = empty_colmajor(M, N, A.device)
     Cc, ldc = colmajor(C)
@@ -420,9 +463,11 @@ class Server:
         import torch
         _check_dev(H, "H")
         _check_dev(S, "S")
+        n = H.shape[0]
+        _check_shape(H, n, n, "H")
+        _check_shape(S, n, n, "S")
         Hc, ldh = colmajor(H)
         Sc, lds = colmajor(S)
-        n = H.shape[0]
         evals = np.zeros(nev)
         X = empty_colmajor(n, nev, H.device) if want_vectors else None
         # the workers run on their own streams: inputs must be complete first
@@ -538,6 +583,7 @@ class Batch:
             lh.append(ldh)
             if S[i] is not None:
                 _check_dev(S[i], f"S[{i}]")
+                _check_shape(S[i], n, n, f"S[{i}]")
                 Sc, lds = colmajor(S[i])
                 keep.append(Sc)
                 sp.append(Sc.data_ptr())

@@ -76,7 +76,7 @@ bool block_sizes_ok(int64_t n, int64_t nev, int64_t nex) {
 constexpr const char* BLOCK_SIZES_RULE = "need 1 <= nev, nev + nex <= n and nex >= 1 unless nev = n";
 
 // Coefficients of the m degree steps of the scaled Chebyshev filter
-// (eq. (3) on (A - cI)/e, normalized at a0): step i computes
+// (eq. (2) on (A - cI)/e, normalized at a0): step i computes
 //   Y_{i+1} = alpha_i A Y_i + beta_i Y_i + gamma_i Y_{i-1}   (gamma_0 = 0).
 struct ChebStep {
   double alpha, beta, gamma;
@@ -350,11 +350,32 @@ struct chfsi_ctx_s {
     have_factors = true;
   }
 
-  void reduce(const zc* H, int64_t ldh, const zc* S, int64_t lds) {
+  // keep_warm: a kept warm block (standard form of the factor being
+  // replaced) is carried over to the new factor through the generalized
+  // space, X = L_old^{-H} Y, Y = L_new^H X (Sec. 2: the previous problem's
+  // eigenvectors start the next one; with a new overlap matrix they are the
+  // generalized vectors that carry over).  Without keep_warm, or when the new
+  // factorization fails, the kept block is dropped: it would no longer match
+  // the context's factor.
+  void reduce(const zc* H, int64_t ldh, const zc* S, int64_t lds, bool keep_warm = true) {
     ensure_nn();
     ensure_small();
-    if (S) cholesky(S, lds);
-    else if (!have_factors) throw Error(ST_EINVAL, "no cached factor of S: pass S");
+    if (warm_valid && !have_factors) warm_valid = false;
+    if (S) {
+      const bool remap = keep_warm && warm_valid && Y.p && warm_k > 0 && warm_k <= kcap;
+      if (remap)
+        gemm(OP_C, OP_N, n, warm_k, n, 1.0, Linv.z(), n, Y.z(), n, F.z(), n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+             GEMM_TRI_A_UPPER);
+      warm_valid = false;  // until the block is in the new factor's standard form
+      cholesky(S, lds);
+      if (remap) {
+        gemm(OP_C, OP_N, n, warm_k, n, 1.0, L.z(), n, F.z(), n, Y.z(), n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+             GEMM_TRI_A_UPPER);
+        warm_valid = true;
+      }
+    } else if (!have_factors) {
+      throw Error(ST_EINVAL, "no cached factor of S: pass S");
+    }
     // A = Linv H Linv^H; A is Hermitian, so the second product forms only
     // the tiles that touch its lower triangle and the upper one is mirrored
     gemm(OP_N, OP_N, n, n, n, 1.0, Linv.z(), n, H, ldh, W.z(), n, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_A_LOWER);
@@ -581,47 +602,50 @@ struct chfsi_ctx_s {
   }
 
   // ------------------------------------------------------------------------
-  // One CholeskyQR pass: G = Yin^H Yin = Lg Lg^H, Qo = Yin Lg^{-H}.  False
-  // when the Gram matrix is not numerically positive definite.
+  // One CholeskyQR pass: G = Yin^H Yin = Lg Lg^H, Qo = Yin Lg^{-H}.
   // ------------------------------------------------------------------------
   // (The Cholesky reads only the Gram matrix's lower triangle.)  The pass's
   // success lands in info_d (INT_MAX: positive definite) without a wait;
-  // Qo is meaningless when it failed.
-  void cholqr_pass(const zc* Yin, int64_t ldy, int64_t k, zc* Qo, int64_t ldq, int* info_d) {
+  // Qo is meaningless when it failed.  cond_d (nullable): the ratio of the
+  // factor's largest to smallest diagonal entry, a lower bound on cond(Yin).
+  void cholqr_pass(const zc* Yin, int64_t ldy, int64_t k, zc* Qo, int64_t ldq, int* info_d, double* cond_d = nullptr) {
     // (lower triangle only: the factorization reads no other part)
     gemm(OP_C, OP_N, k, k, n, 1.0, Yin, ldy, Yin, ldy, G.z(), k, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_OUT_LOWER);
     chol_factor(k, G.z(), k, G2.z(), Z2.z(), Ztmp.z(), k, info_d);
+    if (cond_d) diag_ratio(Z2.z(), k, k, cond_d, st);
     gemm(OP_N, OP_C, n, k, k, 1.0, Yin, ldy, Ztmp.z(), k, Qo, ldq, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER);
   }
 
-  // Both passes' outcomes (infos at flags[2], flags[3]) with one wait.
-  std::pair<bool, bool> cholqr_outcome() {
+  // The passes' outcomes (infos at flags[2], flags[3]) and the first pass's
+  // condition estimate with one wait.
+  struct CholQROutcome {
+    bool first, second;
+    double cond;
+  };
+  CholQROutcome cholqr_outcome() {
     CHFSI_HIP(hipMemcpyAsync(hbuf, flags.i() + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CHFSI_HIP(hipMemcpyAsync(hbuf + 1, norms.d() + COND_SLOT, sizeof(double), hipMemcpyDeviceToHost, st));
     sync();
     int h[2];
     std::memcpy(h, hbuf, sizeof(h));
-    return {h[0] == INT_MAX, h[1] == INT_MAX};
+    return {h[0] == INT_MAX, h[1] == INT_MAX, hbuf[1]};
   }
 
+  // CholeskyQR2 leaves Q orthonormal to working precision when the first
+  // pass's orthogonality error (about eps cond(F)^2) is small; its Cholesky
+  // succeeds up to cond(F) near 1e8.  Between a condition estimate of
+  // COND_GRAY and that breakdown the second pass may leave a visible loss,
+  // so a third pass runs there (its Gram matrix is then close to I).
+  static constexpr double COND_GRAY = 1e6;
+  static constexpr int COND_SLOT = 6;  // norms slot of the condition estimate
+
   // Orthonormal basis of span(F) (F: n x k, ld n, destroyed) into Qo.
-  // CholeskyQR2 (two passes; orthogonal to working precision while
-  // cond(F) is below ~1e7); if a Gram matrix is not positive definite the
-  // block is too ill-conditioned for it and Householder QR takes over on
-  // the best basis at hand.  Returns true when Householder was used.
+  // CholeskyQR2 (a third pass above the gray-zone estimate); if a Gram
+  // matrix is not positive definite the block is too ill-conditioned for
+  // it and Householder QR takes over on the best basis at hand.  Returns
+  // true when Householder was used.
   bool orthonormalize(zc* Fp, int64_t k, zc* Qo, int64_t ldq) {
-    if (opts.qr_mode == 0) {
-      zc* mid = Wk.z();
-      cholqr_pass(Fp, n, k, mid, n, flags.i() + 2);
-      cholqr_pass(mid, n, k, Qo, ldq, flags.i() + 3);
-      const auto ok = cholqr_outcome();
-      if (ok.first && ok.second) return false;
-      if (ok.first) {
-        qr(mid, n, k, Qo, ldq);
-        return true;
-      }
-    }
-    qr(Fp, n, k, Qo, ldq);
-    return true;
+    return orthonormalize_active(nullptr, Fp, 0, k, Qo, ldq);
   }
 
   // Orthonormal basis of [Y_lock | F(:, cl:k)] with the locked columns
@@ -639,17 +663,32 @@ struct chfsi_ctx_s {
       zc* Fa = Fp + cl * n;
       zc* mid = Wk.z();
       zc* B = Z2.z();  // cl x ka coefficients (Z2 is free between the passes' factorizations)
-      auto project = [&](zc* X) {
+      auto project = [&](zc* X, int64_t ldx) {
         if (cl == 0) return;
-        gemm(OP_C, OP_N, cl, ka, n, 1.0, Yl, n, X, n, B, cl);
-        gemm(OP_N, OP_N, n, ka, cl, -1.0, Yl, n, B, cl, X, n, 1.0, X, n);  // X -= Y_lock B
+        gemm(OP_C, OP_N, cl, ka, n, 1.0, Yl, n, X, ldx, B, cl);
+        gemm(OP_N, OP_N, n, ka, cl, -1.0, Yl, n, B, cl, X, ldx, 1.0, X, ldx);  // X -= Y_lock B
       };
-      project(Fa);
-      cholqr_pass(Fa, n, ka, mid, n, flags.i() + 2);
-      project(mid);
-      cholqr_pass(mid, n, ka, Qo + cl * ldq, ldq, flags.i() + 3);
-      const auto ok = cholqr_outcome();
-      if (ok.first && ok.second) return false;
+      zc* Qa = Qo + cl * ldq;
+      project(Fa, n);
+      cholqr_pass(Fa, n, ka, mid, n, flags.i() + 2, norms.d() + COND_SLOT);
+      project(mid, n);
+      cholqr_pass(mid, n, ka, Qa, ldq, flags.i() + 3);
+      const CholQROutcome ok = cholqr_outcome();
+      if (ok.first && ok.second) {
+        if (!(ok.cond > COND_GRAY)) return false;
+        // gray zone: one more pass on the second pass's result
+        project(Qa, ldq);
+        cholqr_pass(Qa, ldq, ka, mid, n, flags.i() + 2);
+        fill_i32(flags.i() + 3, 1, INT_MAX, st);
+        const CholQROutcome ok3 = cholqr_outcome();
+        if (ok3.first) {
+          copy2d(mid, n, Qa, ldq, n, ka, st);
+          return false;
+        }
+        copy2d(Qa, ldq, Fa, n, n, ka, st);  // Householder from the second pass's basis
+      } else if (ok.first) {
+        copy2d(mid, n, Fa, n, n, ka, st);  // from the first pass's, far better conditioned than F
+      }
     }
     if (cl > 0) copy2d(Yl, n, Fp, n, n, cl, st);
     qr(Fp, n, k, Qo, ldq);
@@ -924,17 +963,16 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
 
   c->ensure_nn();
   c->ensure_small();
-  const bool state_ok = c->warm_valid && c->warm_k == k && c->Y.p;
+  // start block: explicit warm vectors, else the block (and filter bounds)
+  // kept from the context's previous solve when its width matches, else a
+  // seeded random block
+  const bool explicit_warm = s.Vw != nullptr && s.kw > 0;
+  const bool use_state = !explicit_warm && c->warm_valid && c->have_factors && c->warm_k == k && c->Y.p;
   c->ensure_k(k);
-  // a warm block meant for a changed S goes through the generalized space:
-  // X_old = L_old^{-H} Y (into F) before the new factor replaces L_old
-  const bool use_state = (s.Vw == nullptr || s.kw == 0) && state_ok;
-  if (use_state && s.S && c->have_factors)
-    c->gemm(OP_C, OP_N, n, k, n, 1.0, c->Linv.z(), n, c->Y.z(), n, c->F.z(), n, 0.0, nullptr, 0, 0.0, nullptr, 0,
-            GEMM_TRI_A_UPPER);
 
   auto t0 = std::chrono::steady_clock::now();
-  c->reduce(s.H, s.ldh, s.S, s.lds);
+  // (a kept block meant for a changed S is carried to the new factor here)
+  c->reduce(s.H, s.ldh, s.S, s.lds, use_state);
   s.mixed = o.precision == 1;
   s.mixed_switch = o.mixed_switch_digits > 0 ? std::pow(10.0, -o.mixed_switch_digits) : MIXED_SWITCH;
   if (s.mixed) {
@@ -960,13 +998,14 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
   zc* Qb = c->Qb.z();
   // start block
   bool warm = false;
-  if (s.Vw && s.kw > 0) {
+  // the kept block survived the reduction (it is in the current standard form)
+  const bool kept = use_state && c->warm_valid;
+  if (explicit_warm) {
     c->gemm(OP_C, OP_N, n, s.kw, n, 1.0, c->L.z(), n, s.Vw, s.ldv, Y, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
             GEMM_TRI_A_UPPER);
     if (s.kw < k) random_block(o.seed, 3u, n, k - s.kw, s.kw, Y + s.kw * n, n, st);
     warm = true;
-  } else if (use_state) {
-    if (s.S) c->gemm(OP_C, OP_N, n, k, n, 1.0, c->L.z(), n, F, n, Y, n, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_A_UPPER);
+  } else if (kept) {
     warm = true;
   } else {
     random_block(o.seed, 3u, n, k, 0, Y, n, st);
@@ -974,11 +1013,14 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
   copy2d(Y, n, F, n, n, k, st);
   inf.qr_householder += c->orthonormalize(F, k, Qb, n) ? 1 : 0;
   s.b = inf.b_upper;
+  // filter bounds: the caller's; else, for the kept block, the ones kept
+  // with it; else (cold start, or explicit vectors without bounds) from one
+  // Rayleigh-Ritz step of the start block
   if (warm && s.bounds_in) {
     copy2d(Qb, n, Y, n, n, k, st);
     s.a0 = s.bounds_in[0];
     s.a = s.bounds_in[1];
-  } else if (warm && c->warm_valid && c->warm_k == k) {
+  } else if (kept) {
     copy2d(Qb, n, Y, n, n, k, st);
     s.a0 = c->warm_a0;
     s.a = c->warm_a;

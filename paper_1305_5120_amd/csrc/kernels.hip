@@ -134,6 +134,32 @@ __global__ void k_column_norms(const zc* R, int64_t ldr, int64_t n, double* out)
   if (threadIdx.x == 0) out[j] = sqrt(s);
 }
 
+// Ratio of the largest to the smallest diagonal entry of a triangular factor
+// (real, positive diagonal): a lower bound on its condition number.  One
+// workgroup; +inf when a diagonal entry is zero or not finite.
+__global__ void __launch_bounds__(256) k_diag_ratio(const zc* L, int64_t ld, int64_t k, double* out) {
+  __shared__ double smax[256], smin[256];
+  double mx = 0.0, mn = INFINITY;
+  bool bad = false;
+  for (int64_t j = threadIdx.x; j < k; j += blockDim.x) {
+    const double d = fabs(L[j + j * ld].x);
+    if (!(d > 0.0) || !isfinite(d)) bad = true;
+    mx = fmax(mx, d);
+    mn = fmin(mn, d);
+  }
+  smax[threadIdx.x] = bad ? INFINITY : mx;
+  smin[threadIdx.x] = mn;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = isfinite(smax[0]) && smin[0] > 0.0 ? smax[0] / smin[0] : INFINITY;
+}
+
 // --------------------------------------------------------------------------
 // Cholesky diagonal block (nb <= 64) and the inverse of its factor, one
 // workgroup, the block in LDS (rows beyond nb padded with the identity).
@@ -1310,6 +1336,10 @@ void residual_block(const zc* W, int64_t ldw, const zc* Y, int64_t ldy, const do
 void column_norms(const zc* R, int64_t ldr, int64_t n, int64_t k, double* out, hipStream_t st) {
   if (k == 0) return;
   LAUNCH(k_column_norms, dim3((unsigned)k), dim3(NT), 0, st, R, ldr, n, out);
+}
+
+void diag_ratio(const zc* L, int64_t ld, int64_t k, double* out, hipStream_t st) {
+  LAUNCH(k_diag_ratio, dim3(1), dim3(256), 0, st, L, ld, k, out);
 }
 
 

@@ -31,6 +31,9 @@ void residual_block(const zc* W, int64_t ldw, const zc* Y, int64_t ldy, const do
                     int64_t k, hipStream_t st);
 // out[j] = ||R(:, j)||_2
 void column_norms(const zc* R, int64_t ldr, int64_t n, int64_t k, double* out, hipStream_t st);
+// out[0] = max_j |L(j,j)| / min_j |L(j,j)| (+inf for a zero or non-finite
+// diagonal entry): a lower bound on the condition number of triangular L
+void diag_ratio(const zc* L, int64_t ld, int64_t k, double* out, hipStream_t st);
 // flag[0] = 1 if any entry of the n x k block is not finite (else untouched)
 
 // ---- Cholesky --------------------------------------------------------------

@@ -2,7 +2,7 @@
 //
 //   out = alpha * op(A) op(B) + beta * X + gamma * Z      (alpha, beta, gamma real)
 //
-// This is the Chebyshev filter step of Algorithm 1 (eq. (3), scaled and
+// This is the Chebyshev filter step of Algorithm 1 (eq. (2), scaled and
 // shifted): with op = N, X = Y_i and Z = Y_{i-1}, one launch computes
 // Y_{i+1} = alpha A Y_i + beta Y_i + gamma Y_{i-1} and writes it over Y_{i-1},
 // so every degree step reads A, Y_i, Y_{i-1} and writes Y_{i+1} once.  The

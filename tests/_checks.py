@@ -89,3 +89,31 @@ def exact_standard_vectors(Q, lam):
 
 def spectral_norm(M):
     return float(sl.norm(M, 2))
+
+
+def subspace_check_torch(Y, Q_sorted, lam_sorted, A, mu, nev):
+    """subspace_check on the device (torch tensors Y n x nev, Q_sorted n x N
+    the exact standard-form eigenvectors in ascending order, A n x n; host
+    arrays lam_sorted, mu), for the full-size tests."""
+    import torch
+    lam_sorted = np.asarray(lam_sorted)
+    mu = np.asarray(mu)
+    worst = 0.0
+    ratio = 0.0
+    ok = True
+    for (s, e, fe) in groups(lam_sorted, nev):
+        YG = Y[:, s:e]
+        E = Q_sorted[:, s:fe]
+        P = YG - E @ (E.conj().T @ YG)
+        sin = float(torch.linalg.matrix_norm(P, ord=2))
+        m = torch.from_numpy(mu[s:e]).to(device=Y.device, dtype=Y.dtype)
+        RG = A @ YG - YG * m[None, :]
+        lo = lam_sorted[s - 1] if s > 0 else -np.inf
+        hi = lam_sorted[fe] if fe < len(lam_sorted) else np.inf
+        delta = min(np.min(mu[s:e]) - lo, hi - np.max(mu[s:e]))
+        bound = max(1e-8, float(torch.linalg.matrix_norm(RG)) / max(delta, 1e-300))
+        worst = max(worst, sin)
+        ratio = max(ratio, sin / bound)
+        if sin > bound:
+            ok = False
+    return ok, worst, ratio

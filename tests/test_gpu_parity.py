@@ -364,6 +364,48 @@ def test_orthonormalize_falls_back_on_ill_conditioned_block(lib):
     assert np.linalg.norm(lead - Q @ (Q.conj().T @ lead), 2) <= 1e-9
 
 
+@pytest.mark.parametrize("cond", [1e6, 1e7, 5e7])
+@pytest.mark.parametrize("n,k", [(1000, 130), (600, 40)])
+def test_orthonormalize_gray_zone(lib, n, k, cond):
+    """cond(F) between 1e6 and near the Cholesky breakdown: the Gram
+    Cholesky succeeds but two passes alone can leave a visible loss of
+    orthogonality.  Whichever path runs (a third CholeskyQR pass or
+    Householder), Q is orthonormal to working precision and spans F's
+    column space (up to the rounding of F itself, ~eps cond)."""
+    rng = _rng(int(math.log10(cond) * 10) + n)
+    U, _ = np.linalg.qr(_cg(rng, (n, k)))
+    V, _ = np.linalg.qr(_cg(rng, (k, k)))
+    Y = U @ np.diag(np.logspace(0, -math.log10(cond), k)) @ V
+    ctx = lib.create(n)
+    Yt = _t(Y)
+    lib.orthonormalize(ctx, Yt)
+    Q = _np(Yt)
+    assert np.abs(Q.conj().T @ Q - np.eye(k)).max() <= 1e-13
+    assert np.linalg.norm(U - Q @ (Q.conj().T @ U), 2) <= 1e-15 * cond * 100
+
+
+def test_orthonormalize_gray_zone_block_nearly_in_a_subspace(lib):
+    """[Y_lock | F] with F's part outside span(Y_lock) graded down to 1e-7
+    (the shape of a filtered block next to converged vectors): orthonormal to
+    working precision and spanning [Y_lock | U]."""
+    rng = _rng(77)
+    n, cl, ka = 800, 30, 60
+    Yl, _ = np.linalg.qr(_cg(rng, (n, cl)))
+    U, _ = np.linalg.qr(_cg(rng, (n, ka)))
+    V, _ = np.linalg.qr(_cg(rng, (ka, ka)))
+    F = U @ np.diag(np.logspace(0, -7, ka)) @ V + Yl @ _cg(rng, (cl, ka))
+    B = np.concatenate([Yl, F], axis=1)
+    ctx = lib.create(n)
+    Bt = _t(B)
+    lib.orthonormalize(ctx, Bt)
+    Q = _np(Bt)
+    k = cl + ka
+    assert np.abs(Q.conj().T @ Q - np.eye(k)).max() <= 1e-13
+    # span of [Y_lock | F] is span of [Y_lock | U]
+    W = np.concatenate([Yl, U], axis=1)
+    assert np.linalg.norm(W - Q @ (Q.conj().T @ W), 2) <= 1e-7
+
+
 @pytest.mark.parametrize("k", [1, 2, 40, 96, 97, 130, 257, 440])
 def test_eigh_matches_oracle(lib, k):
     """Dense random Hermitian matrices: one workgroup up to k = 96, block-ordered
@@ -806,19 +848,39 @@ def test_solve_sequence_configuration_full_size(lib):
     ctx.release()
 
 
-def test_solve_precision_configuration_full_size(lib):
-    """n=10000, nev=600, nex=60, degree 20, mixed precision (the filter in
-    complex FP32 until columns approach the tolerance, everything else FP64):
-    every eigenvalue against the spectrum known by construction, the
-    generalized residuals of the returned pairs, and S-orthonormality.
-    Gaussian draws on the device (same laws as the host generator)."""
+@pytest.fixture(scope="module")
+def precision_problem():
+    """The precision configuration's problem (n = 10000, spectrum law of the
+    small configuration), Gaussian draws on the device."""
+    import workloads as w
+    p = w.make_problem_torch(10000, 2, device="cuda", rng_kind="device")
+    yield p
+    del p
+
+
+def _subspace_full_size(p, X, ev, nev):
+    """Subspace angles per cluster-closed group against the constructed
+    eigenvectors (Davis-Kahan reading of the 1e-8 rule), on the device."""
+    Y = p["L"].conj().T @ X
+    ok, worst, ratio = _checks.subspace_check_torch(Y, p["Q"], np.sort(p["lam"]), p["A"], ev, nev)
+    assert ok, (worst, ratio)
+    return worst
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_precision_configuration_full_size(lib, precision_problem, precision):
+    """n=10000, nev=600, nex=60, degree 20, FP64 throughout and mixed
+    precision (the filter in complex FP32 until columns approach the
+    tolerance, everything else FP64): every eigenvalue against the spectrum
+    known by construction, the generalized residuals of the returned pairs,
+    S-orthonormality and subspace angles against the constructed vectors."""
     import torch
     n, nev, nex = 10000, 600, 60
-    p = workloads.make_problem_torch(n, 2, device="cuda", rng_kind="device")
-    ctx = lib.create(n, degree=20, seed=0, precision=1)
+    p = precision_problem
+    ctx = lib.create(n, degree=20, seed=0, precision=precision)
     ev, X, info, st = lib.solve(ctx, p["H"], p["S"], nev, nex, tol=1e-10)
     assert st == 0
-    assert info["iterations_fp32"] > 0
+    assert (info["iterations_fp32"] > 0) == (precision == 1)
     lam = np.sort(p["lam"])[:nev]
     H, S = p["H"], p["S"]
     v = torch.ones(n, dtype=torch.complex128, device="cuda")
@@ -833,6 +895,8 @@ def test_solve_precision_configuration_full_size(lib):
     assert float(torch.linalg.vector_norm(R, dim=0).max()) <= 1e-10 * hn
     G = X.conj().T @ (S @ X)
     assert float((G - torch.eye(nev, dtype=torch.complex128, device="cuda")).abs().max()) <= 1e-12
+    del R, G
+    _subspace_full_size(p, X, ev, nev)
     ctx.release()
 
 
@@ -860,3 +924,4 @@ def test_solve_full_size_first_problem_of_sequence(lib, precision):
     assert float(torch.linalg.vector_norm(R, dim=0).max()) <= 1e-10 * hn
     G = X.conj().T @ (S @ X)
     assert float((G - torch.eye(400, dtype=torch.complex128, device="cuda")).abs().max()) <= 1e-12
+    _subspace_full_size(p, X, ev, 400)

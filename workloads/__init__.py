@@ -140,6 +140,24 @@ def make_sequence(n: int, steps: int, seed: int, eps: float = 1e-4):
         yield Problem(np.asfortranarray(H), p0.S, p0.L, np.asfortranarray(A), None, None)
 
 
+def make_sequence_varying_s(n: int, steps: int, seed: int, eps: float = 1e-4, eps_s: float = 1e-4):
+    """As make_sequence, with the overlap matrix changing along the sequence
+    too: L_{l+1} = L_l + eps_s tril(G, -1)/sqrt(n) (G complex Gaussian),
+    S_l = L_l L_l^H, H_l = L_l A_l L_l^H.  L_l keeps a unit diagonal, so it is
+    exactly the Cholesky factor of S_l."""
+    rng = np.random.default_rng(seed + 2_000_003)
+    L = None
+    for ell, p in enumerate(make_sequence(n, steps, seed, eps)):
+        if ell == 0:
+            L = p.L
+            yield p
+            continue
+        L = L + eps_s * np.tril(_cgauss(rng, (n, n)), -1) / math.sqrt(n)
+        S = _herm(L @ L.conj().T)
+        H = _herm(L @ p.A @ L.conj().T)
+        yield Problem(np.asfortranarray(H), np.asfortranarray(S), np.asfortranarray(L), p.A, None, None)
+
+
 # --------------------------------------------------------------------------
 # Device (torch) variant for large sizes: same host draws, dense algebra on
 # the device.  Tensors come back column-major (transposed storage), complex128.
