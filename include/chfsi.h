@@ -110,7 +110,10 @@ chfsi_status chfsi_create(chfsi_ctx* out, int64_t n, const chfsi_opts* opts, voi
 /* Free every device buffer owned by ctx.  NULL-safe. */
 void chfsi_release(chfsi_ctx ctx);
 
-/* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
+/* Message of the last failed call on ctx ("" if none).  Owned by ctx.  With
+ * ctx = NULL: the message of the calling thread's last failed
+ * chfsi_zgemm_static call, or "null context" if there is none (owned by the
+ * library, valid until that thread's next such call). */
 const char* chfsi_last_error(chfsi_ctx ctx);
 
 /* Forget the warm state kept from the previous solve (next solve starts cold). */
@@ -216,6 +219,29 @@ chfsi_status chfsi_philox(chfsi_ctx ctx, const uint32_t* ctr, const uint32_t* ke
 chfsi_status chfsi_zgemm(chfsi_ctx ctx, int32_t opA, int32_t opB, int64_t M, int64_t N, int64_t K, double alpha,
                          const void* A, int64_t lda, const void* B, int64_t ldb, double beta, const void* X, int64_t ldx,
                          double gamma, const void* Z, int64_t ldz, void* C, int64_t ldc, int32_t flags);
+
+/* Bytes of the fixed per-GPU scratch of chfsi_zgemm_static. */
+#define CHFSI_STATIC_SCRATCH_BYTES ((int64_t)64 << 20)
+
+/* Allocation-free chfsi_zgemm, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops and harnesses that forbid
+ * hipMalloc): the same operation, arguments, flags and kernels as chfsi_zgemm,
+ * without a context.  The work is queued on `stream` (a hipStream_t, NULL =
+ * the null stream) and the call returns without waiting for it.  It calls no
+ * hipMalloc / hipFree: the split-K partial tiles (split x M x N complex
+ * numbers) live in a fixed device array of CHFSI_STATIC_SCRATCH_BYTES per GPU
+ * that the library holds until the process ends.  An automatic split
+ * (flags bits 16-23 = 0) is limited to what fits there; an explicit split
+ * whose partial tiles exceed it returns CHFSI_EINVAL before any work is
+ * queued.  Every call on one GPU uses that GPU's one array: calls whose work
+ * overlaps in time on the same GPU (other streams, other host threads) race
+ * and must be ordered by the caller.  Errors as chfsi_zgemm;
+ * chfsi_last_error(NULL) gives the message of the calling thread's last
+ * failed call of this function. */
+chfsi_status chfsi_zgemm_static(void* stream, int32_t opA, int32_t opB, int64_t M, int64_t N, int64_t K,
+                                double alpha, const void* A, int64_t lda, const void* B, int64_t ldb, double beta,
+                                const void* X, int64_t ldx, double gamma, const void* Z, int64_t ldz, void* C,
+                                int64_t ldc, int32_t flags);
 
 /* ---- Batching -----------------------------------------------------------------
  * One solver per k-point for a fixed set of independent sequences (Section 2:

@@ -86,9 +86,11 @@ def load():
     L.chfsi_philox.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64]
     L.chfsi_zgemm.argtypes = [c_vp, c_i32, c_i32, c_i64, c_i64, c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_dbl, c_vp,
                               c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_i32]
+    L.chfsi_zgemm_static.argtypes = [c_vp, c_i32, c_i32, c_i64, c_i64, c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_dbl,
+                                     c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_i32]
     for name in ("chfsi_create", "chfsi_reset", "chfsi_reduce", "chfsi_solve", "chfsi_copy_factors", "chfsi_filter",
                  "chfsi_qr", "chfsi_orthonormalize", "chfsi_eigh", "chfsi_rayleigh_ritz", "chfsi_residuals", "chfsi_lanczos",
-                 "chfsi_random_block", "chfsi_philox", "chfsi_zgemm"):
+                 "chfsi_random_block", "chfsi_philox", "chfsi_zgemm", "chfsi_zgemm_static"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -404,6 +406,48 @@ def zgemm(ctx, opA, opB, A, B, alpha=1.0, beta=0.0, X=None, gamma=0.0, Z=None, C
                                    Cc.data_ptr(), ldc, int(flags)))
     if Cc.data_ptr() != C.data_ptr():
         C.copy_(Cc)
+    return C
+
+
+def zgemm_static(opA, opB, A, B, C, alpha=1.0, beta=0.0, X=None, gamma=0.0, Z=None, flags=0, M=None, N=None,
+                 K=None):
+    """chfsi_zgemm_static: C = alpha op(A) op(B) + beta X + gamma Z without a
+    context and without device allocation in the library (split-K partial
+    tiles in its fixed per-GPU scratch), queued on torch's current stream.
+    Every tensor must already be a column-major device tensor (the binding
+    makes no copies either); C is written in place."""
+    import torch
+    for t, nm in ((A, "A"), (B, "B"), (C, "C"), (X, "X"), (Z, "Z")):
+        if t is None:
+            continue
+        _check_dev(t, nm)
+        if t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
+            raise ValueError(f"zgemm_static: {nm} must be column-major (stride (1, ld))")
+        if t.is_conj():
+            raise ValueError(f"zgemm_static: {nm} has the conjugate bit set")
+    M = M if M is not None else (A.shape[0] if opA == 0 else A.shape[1])
+    K = K if K is not None else (A.shape[1] if opA == 0 else A.shape[0])
+    N = N if N is not None else (B.shape[1] if opB == 0 else B.shape[0])
+    ra, ca = (M, K) if opA == 0 else (K, M)
+    rb, cb = (K, N) if opB == 0 else (N, K)
+    if A.shape[0] < ra or A.shape[1] < ca or B.shape[0] < rb or B.shape[1] < cb:
+        raise ValueError("zgemm_static: A or B smaller than the product's sizes")
+    for t, nm in ((X, "X"), (Z, "Z"), (C, "C")):
+        if t is not None and (t.shape[0] < M or t.shape[1] < N):
+            raise ValueError(f"zgemm_static: {nm} smaller than M x N")
+
+    def ld(t):
+        return max(1, t.stride(1))
+
+    lib = load()
+    stream = torch.cuda.current_stream(C.device).cuda_stream
+    st = lib.chfsi_zgemm_static(stream, int(opA), int(opB), int(M), int(N), int(K), float(alpha), A.data_ptr(), ld(A),
+                                B.data_ptr(), ld(B), float(beta), X.data_ptr() if X is not None else None,
+                                ld(X) if X is not None else int(M), float(gamma),
+                                Z.data_ptr() if Z is not None else None, ld(Z) if Z is not None else int(M),
+                                C.data_ptr(), ld(C), int(flags))
+    if st != 0:
+        raise ChfsiError(st, lib.chfsi_last_error(None).decode())
     return C
 
 

@@ -1881,6 +1881,67 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free GEMM (chfsi_zgemm_static): its split-K partial tiles live
+// in this fixed array, one copy per GPU, held until the process ends.  Host
+// code never passes the array's name to a kernel or a copy (on the host it is
+// only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)64 << 20;  // CHFSI_STATIC_SCRATCH_BYTES in chfsi.h
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[STATIC_MAX_DEVICES] = {};
+thread_local std::string g_static_err;
+
+// Argument checks shared by chfsi_zgemm and chfsi_zgemm_static (throws
+// CHFSI_EINVAL); false when the product is empty (nothing to launch).
+bool zgemm_args_ok(int32_t opA, int32_t opB, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
+                   int64_t ldb, const void* X, int64_t ldx, const void* Z, int64_t ldz, const void* C, int64_t ldc,
+                   int32_t flags) {
+  const int cfg = (flags >> 8) & 0xff;
+  if (M < 0 || N < 0 || K < 0 || (opA != 0 && opA != 1) || (opB != 0 && opB != 1) || (flags & 0xff0000e0) ||
+      cfg >= zgemm_num_configs())
+    throw Error(ST_EINVAL, "zgemm: bad sizes, ops or flags");
+  if (M == 0 || N == 0) return false;
+  check_ptr(C, "C");
+  check_ld(ldc, M, "ldc");
+  if (K > 0) {
+    check_ptr(A, "A");
+    check_ptr(B, "B");
+    check_ld(lda, opA == 0 ? M : K, "lda");
+    check_ld(ldb, opB == 0 ? K : N, "ldb");
+  }
+  if (X) check_ld(ldx, M, "ldx");
+  if (Z) check_ld(ldz, M, "ldz");
+  return true;
+}
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device).
+void* static_scratch_ptr() {
+  int dev = -1;
+  CHFSI_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) throw Error(ST_EHIP, "static scratch: device index out of range");
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(ST_EHIP, std::string("static scratch: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+    }
+    g_static_ptr[dev] = p;
+  }
+  return g_static_ptr[dev];
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1938,7 +1999,10 @@ void chfsi_release(chfsi_ctx c) {
   delete c;
 }
 
-const char* chfsi_last_error(chfsi_ctx c) { return c ? c->err.c_str() : "null context"; }
+const char* chfsi_last_error(chfsi_ctx c) {
+  if (c) return c->err.c_str();
+  return g_static_err.empty() ? "null context" : g_static_err.c_str();
+}
 
 chfsi_status chfsi_reset(chfsi_ctx c) {
   return guarded(c, [&] { c->warm_valid = false; });
@@ -2144,20 +2208,7 @@ chfsi_status chfsi_zgemm(chfsi_ctx c, int32_t opA, int32_t opB, int64_t M, int64
                          double gamma, const void* Z, int64_t ldz, void* C, int64_t ldc, int32_t flags) {
   return guarded(c, [&] {
     const int structure = flags & 31, cfg = (flags >> 8) & 0xff, nsplit = (flags >> 16) & 0xff;
-    if (M < 0 || N < 0 || K < 0 || (opA != 0 && opA != 1) || (opB != 0 && opB != 1) || (flags & 0xff0000e0) ||
-        cfg >= zgemm_num_configs())
-      throw Error(ST_EINVAL, "zgemm: bad sizes, ops or flags");
-    if (M == 0 || N == 0) return;
-    check_ptr(C, "C");
-    check_ld(ldc, M, "ldc");
-    if (K > 0) {
-      check_ptr(A, "A");
-      check_ptr(B, "B");
-      check_ld(lda, opA == 0 ? M : K, "lda");
-      check_ld(ldb, opB == 0 ? K : N, "ldb");
-    }
-    if (X) check_ld(ldx, M, "ldx");
-    if (Z) check_ld(ldz, M, "ldz");
+    if (!zgemm_args_ok(opA, opB, M, N, K, A, lda, B, ldb, X, ldx, Z, ldz, C, ldc, flags)) return;
     c->ensure_small();
     // split-K scratch: the requested split, or 16-way for small outputs
     size_t need = (cdiv(M, 32) * cdiv(N, 32) < 256) ? (size_t)M * N * 16 : 0;
@@ -2171,6 +2222,43 @@ chfsi_status chfsi_zgemm(chfsi_ctx c, int32_t opA, int32_t opB, int64_t M, int64
             (const zc*)Z, ldz, structure, true, false, cfg, nsplit);
     c->sync();
   });
+}
+
+chfsi_status chfsi_zgemm_static(void* stream, int32_t opA, int32_t opB, int64_t M, int64_t N, int64_t K, double alpha,
+                                const void* A, int64_t lda, const void* B, int64_t ldb, double beta, const void* X,
+                                int64_t ldx, double gamma, const void* Z, int64_t ldz, void* C, int64_t ldc,
+                                int32_t flags) {
+  try {
+    g_static_err.clear();
+    const int structure = flags & 31, cfg = (flags >> 8) & 0xff, nsplit = (flags >> 16) & 0xff;
+    if (!zgemm_args_ok(opA, opB, M, N, K, A, lda, B, ldb, X, ldx, Z, ldz, C, ldc, flags)) return CHFSI_OK;
+    if (nsplit > 1 && (double)nsplit * (double)M * (double)N * sizeof(zc) > (double)STATIC_SCRATCH_BYTES)
+      throw Error(ST_EINVAL, "zgemm_static: the split-K partial tiles (" + std::to_string(nsplit) + " x " +
+                                 std::to_string(M) + " x " + std::to_string(N) + " x 16 bytes) exceed the static " +
+                                 "scratch of " + std::to_string(STATIC_SCRATCH_BYTES) + " bytes");
+    void* P = static_scratch_ptr();
+    GemmOp g;
+    g.cfg = cfg;
+    g.splitk = nsplit;
+    g.opA = opA; g.opB = opB; g.M = M; g.N = N; g.K = K;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+    g.X = X; g.ldx = ldx; g.Z = Z; g.ldz = ldz;
+    g.alpha = alpha; g.beta = beta; g.gamma = gamma;
+    g.flags = structure;
+    g.allow_splitk = true;
+    zgemm(g, GemmWork{static_cast<zc*>(P), STATIC_SCRATCH_BYTES / sizeof(zc)}, (hipStream_t)stream);
+    return CHFSI_OK;
+  } catch (const Error& e) {
+    g_static_err = e.what();
+    (void)hipGetLastError();
+    return (chfsi_status)e.code;
+  } catch (const std::exception& e) {
+    g_static_err = e.what();
+    return CHFSI_EHIP;
+  } catch (...) {
+    g_static_err = "unknown error";
+    return CHFSI_EHIP;
+  }
 }
 
 chfsi_status chfsi_server_create(chfsi_server* out, const chfsi_server_config* cfg) {

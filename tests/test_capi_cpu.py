@@ -96,6 +96,28 @@ def test_solve_argument_validation_without_device_work():
         lib.chfsi_release(h)
 
 
+def test_static_gemm_validation_without_device_work():
+    """The allocation-free GEMM rejects bad arguments, and an explicit K
+    split whose partial tiles exceed its fixed scratch, before touching the
+    device; its message is the thread's context-free error."""
+    lib = chfsi.load()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.chfsi_zgemm_static(None, 2, 0, 1, 1, 1, 1.0, fake, 1, fake, 1, 0.0, None, 1, 0.0, None, 1, fake, 1,
+                                  0) == -1
+    assert b"bad sizes" in lib.chfsi_last_error(None)
+    M = N = 2000  # two splits of 2000 x 2000 complex numbers: 128 MB > 64 MiB
+    assert lib.chfsi_zgemm_static(None, 0, 0, M, N, 64, 1.0, fake, M, fake, 64, 0.0, None, M, 0.0, None, M, fake, M,
+                                  (1 << 8) | (2 << 16)) == -1
+    assert b"static scratch" in lib.chfsi_last_error(None)
+    assert lib.chfsi_zgemm_static(None, 0, 0, M, N, 64, 1.0, fake, M - 1, fake, 64, 0.0, None, M, 0.0, None, M, fake,
+                                  M, 0) == -1
+    assert b"lda" in lib.chfsi_last_error(None)
+    # an empty product succeeds without work and clears the message
+    assert lib.chfsi_zgemm_static(None, 0, 0, 0, 5, 5, 1.0, None, 1, None, 1, 0.0, None, 1, 0.0, None, 1, None, 1,
+                                  0) == 0
+    assert lib.chfsi_last_error(None) == b"null context"
+
+
 def test_batch_create_and_solve_validation_without_device_work():
     """Batch creation rejects bad member counts, sizes and tile shapes before
     any device call; a null batch is rejected by every entry point."""
