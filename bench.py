@@ -54,6 +54,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+class _Marker:
+    """A named host range for profilers that record ROCTX markers
+    (rocprofv3 --marker-trace): the timed region is marked so a profile can
+    be restricted to it.  A no-op where the marker library is absent."""
+
+    def __init__(self):
+        import ctypes
+        try:
+            self.lib = ctypes.CDLL("librocprofiler-sdk-roctx.so.1")
+            self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+        except OSError:
+            self.lib = None
+
+    def push(self, name):
+        if self.lib:
+            self.lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self.lib:
+            self.lib.roctxRangePop()
+
+
+MARKER = _Marker()
+
+
 def make_problems(cfg, count, device):
     import torch
     import workloads
@@ -445,28 +470,73 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def serving_law(nseq, seed, n_lo, n_hi):
+    """Sizes of the serving form's sequences: n log-uniform in [n_lo, n_hi],
+    nev uniform in 3-20 % of n (at least 4), nex = nev/10 (at least 1)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sizes = [int(round(math.exp(v))) for v in rng.uniform(math.log(n_lo), math.log(n_hi), nseq)]
+    nevs = [max(4, int(n * f)) for n, f in zip(sizes, rng.uniform(0.03, 0.20, nseq))]
+    nexs = [max(1, v // 10) for v in nevs]
+    return sizes, nevs, nexs, rng
+
+
+def serving_trace(nseq, requests, seed):
+    """The first `requests` arrivals of the serving configuration's trace:
+    each arrival is the next problem of a sequence drawn uniformly from the
+    nseq sequences.  Returns [(sequence, step)]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    count = [0] * nseq
+    out = []
+    for s in rng.integers(0, nseq, requests):
+        out.append((int(s), count[s]))
+        count[s] += 1
+    return out
+
+
 def run_serve(args):
     """Poisson arrivals of problems from many k-point sequences, served twice
     on the same arrival trace: by the plain FP64 path (one worker, one
     request at a time, warm starts) and by the full server (several workers
     on their own streams admitted by device memory, mixed-precision filter,
-    warm starts).  Both must reach the same residual bound."""
+    warm starts).  Both must reach the same residual bound.  Later problems
+    of a sequence pass no overlap matrix (S fixed along a sequence), so a
+    worker holding the sequence's factor reuses it.
+
+    --law small: sequences of the scaled-down law (n log-uniform in
+    [1000, 6000], every sequence's steps in order); --law full: the serving
+    configuration's law (128 sequences, n log-uniform in [2000, 20000]),
+    bounded to the first --requests arrivals of its trace (each arrival the
+    next problem of a uniformly drawn sequence); --serve-paths runs one of
+    the two paths (the same trace and seeds either way)."""
     import numpy as np
     import torch
     from paper_1305_5120_amd import chfsi
     import workloads
-    nseq, steps = args.members, args.seq_steps
-    rng = np.random.default_rng(4)
-    sizes = [int(round(math.exp(v))) for v in rng.uniform(math.log(1000), math.log(6000), nseq)]
-    nevs = [max(4, int(n * f)) for n, f in zip(sizes, rng.uniform(0.03, 0.20, nseq))]
-    nexs = [max(1, v // 10) for v in nevs]
-    seqs = []
-    for i, n in enumerate(sizes):
-        seqs.append(list(workloads.make_sequence_torch(n, steps, 400 + i, device="cuda")))
-        log(f"[bench] generated sequence {i + 1}/{nseq} (n={n}, nev={nevs[i]})")
+    full = args.law == "full"
+    if full:
+        nseq = 128
+        sizes, nevs, nexs, rng = serving_law(nseq, 4, 2000, 20000)
+        order = serving_trace(nseq, args.requests, 41)
+        rate = args.rate if args.rate_set else 0.05
+    else:
+        nseq, steps = args.members, args.seq_steps
+        sizes, nevs, nexs, rng = serving_law(nseq, 4, 1000, 6000)
+        order = [(s, ell) for ell in range(steps) for s in range(nseq)]
+        rate = args.rate
+    need = {}
+    for s, ell in order:
+        need[s] = max(need.get(s, 0), ell + 1)
+    seqs = {}
+    for i, s in enumerate(sorted(need)):
+        # only H and S stay resident (the generator's A, Q, L are freed)
+        seqs[s] = [{"H": p["H"], "S": p["S"]} for p in
+                   workloads.make_sequence_torch(sizes[s], need[s], 400 + s, device="cuda",
+                                                 rng_kind="device" if full else "host")]
+        log(f"[bench] generated sequence {s} ({i + 1}/{len(need)}: n={sizes[s]}, nev={nevs[s]}, steps {need[s]})")
     torch.cuda.synchronize()
-    order = [(s, ell) for ell in range(steps) for s in range(nseq)]
-    gaps = rng.exponential(1.0 / args.rate, len(order))
+    gaps = rng.exponential(1.0 / rate, len(order))
 
     def serve(workers, precision, label):
         srv = chfsi.Server(workers=workers, hbm_budget_bytes=int(args.budget_gb * (1 << 30)), degree=20, seed=0,
@@ -479,12 +549,14 @@ def run_serve(args):
             d = t_next - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            tickets.append(srv.submit(s, seqs[s][ell]["H"], seqs[s][0]["S"], nevs[s], nexs[s], tol=1e-10,
-                                      want_vectors=False))
+            tickets.append(srv.submit(s, seqs[s][ell]["H"], seqs[s][0]["S"] if ell == 0 else None, nevs[s],
+                                      nexs[s], tol=1e-10, want_vectors=False))
+            log(f"[bench] {label}: submitted sequence {s} step {ell} (n={sizes[s]}, nev={nevs[s]})")
         worst = 0.0
         for t in tickets:
-            _, _, info, _, _ = srv.wait(t)
+            _, _, info, lat, _ = srv.wait(t)
             worst = max(worst, info["max_rel_residual"])
+            log(f"[bench] {label}: request done in {lat:.2f} s, {info['iterations']} iterations")
         elapsed = time.perf_counter() - t0
         stats = srv.stats()
         srv.close()
@@ -492,24 +564,39 @@ def run_serve(args):
             f"solves/s, p50 {stats['p50_latency']:.3f} s, p99 {stats['p99_latency']:.3f} s, worst residual {worst:.2e}")
         return stats, elapsed, worst
 
+    def path_report(st, res):
+        return {"solves_per_s": st["solves_per_second"], "p50_latency_s": st["p50_latency"],
+                "p99_latency_s": st["p99_latency"], "mean_latency_s": st["mean_latency"],
+                "completed": st["completed"], "failed": st["failed"], "peak_bytes": st["peak_bytes"],
+                "max_rel_residual": res}
+
+    config = {"workload": "Poisson arrivals of DGEVP requests from k-point sequences", "sequences": nseq,
+              "law": args.law,
+              "n": (f"log-uniform in [2000, 20000] (seed 4)" if full else f"log-uniform in [1000, 6000] (seed 4)"),
+              "requests": [{"sequence": s, "step": ell, "n": sizes[s], "nev": nevs[s], "nex": nexs[s]}
+                           for s, ell in order],
+              "nev": "uniform 3-20% of n", "nex": "nev/10", "arrival_rate_per_s": rate,
+              "workers": args.workers, "hbm_budget_gb": args.budget_gb, "degree": 20, "tol": 1e-10}
+    if args.serve_paths != "both":
+        plain_only = args.serve_paths == "plain"
+        st, elapsed, res = (serve(1, 0, "plain FP64, one worker") if plain_only else
+                            serve(args.workers, 1, f"server, {args.workers} workers, mixed precision"))
+        out = _base("eigensolves/s and p50/p99 latency under Poisson arrivals, residual <=1e-10",
+                    st["solves_per_second"], "solves/s", len(order), 0, 1e3 * elapsed / len(order),
+                    "complex128 (f64)" if plain_only else "complex64 filter + f64",
+                    dict(config, path="plain FP64, one worker" if plain_only else "server, mixed precision"))
+        out.update(path_report(st, res))
+        print(json.dumps(out), flush=True)
+        return
     plain, _, plain_res = serve(1, 0, "plain FP64, one worker")
     stats, elapsed, res = serve(args.workers, 1, f"server, {args.workers} workers, mixed precision")
     out = _base("eigensolves/s and p50/p99 latency under Poisson arrivals, residual <=1e-10",
                 stats["solves_per_second"], "solves/s", len(order), 0, 1e3 * elapsed / len(order),
-                "complex64 filter + f64",
-                {"workload": "Poisson arrivals of DGEVP requests from k-point sequences", "sequences": nseq,
-                 "n": f"log-uniform in [1000, 6000] (seed 4): {sizes}", "nev": "uniform 3-20% of n",
-                 "nex": "nev/10", "steps_per_sequence": steps, "arrival_rate_per_s": args.rate,
-                 "workers": args.workers, "hbm_budget_gb": args.budget_gb, "degree": 20, "tol": 1e-10,
-                 "precision": "mixed"})
+                "complex64 filter + f64", dict(config, precision="mixed"))
     out.update({"p50_latency_s": stats["p50_latency"], "p99_latency_s": stats["p99_latency"],
                 "mean_latency_s": stats["mean_latency"], "completed": stats["completed"], "failed": stats["failed"],
                 "peak_bytes": stats["peak_bytes"], "max_rel_residual": res,
-                "plain_fp64_one_worker": {"solves_per_s": plain["solves_per_second"],
-                                          "p50_latency_s": plain["p50_latency"],
-                                          "p99_latency_s": plain["p99_latency"],
-                                          "completed": plain["completed"], "failed": plain["failed"],
-                                          "max_rel_residual": plain_res},
+                "plain_fp64_one_worker": path_report(plain, plain_res),
                 "gain_vs_plain": {"solves_per_s": stats["solves_per_second"] / plain["solves_per_second"],
                                   "p50": plain["p50_latency"] / stats["p50_latency"],
                                   "p99": plain["p99_latency"] / stats["p99_latency"]}})
@@ -716,7 +803,13 @@ def main():
                     choices=sorted(WORKLOADS) + ["precision", "batch", "serve", "warmcold"])
     ap.add_argument("--members", type=int, default=16, help="sequences (batch / serve forms)")
     ap.add_argument("--seq-steps", type=int, default=3, help="problems per sequence (batch / serve / warmcold)")
-    ap.add_argument("--rate", type=float, default=3.0, help="Poisson arrival rate per second (serve form)")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="Poisson arrival rate per second (serve form; default 3 for the small law, 0.05 for the full)")
+    ap.add_argument("--law", choices=["small", "full"], default="small",
+                    help="serve form: the scaled-down law or the serving configuration's law (bounded trace)")
+    ap.add_argument("--requests", type=int, default=16, help="serve form, full law: arrivals of the trace served")
+    ap.add_argument("--serve-paths", choices=["both", "plain", "server"], default="both",
+                    help="serve form: run both paths or one of them on the trace")
     ap.add_argument("--workers", type=int, default=4, help="serving workers")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving device-memory budget")
     ap.add_argument("--wc-n", type=int, default=4000, help="problem size of the warm/cold study")
@@ -729,6 +822,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, run a device copy of known size (counter calibration)")
     args = ap.parse_args()
+    args.rate_set = args.rate is not None
+    if args.rate is None:
+        args.rate = 3.0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU (no multi-GPU path); --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -767,6 +863,7 @@ def main():
         ev, X, info = one(i)
         log(f"[bench] warmup solve {i}: {info['iterations']} iterations, {info['t_total']:.3f} s")
     torch.cuda.synchronize()
+    MARKER.push("bench.timed_region")
     t0 = time.perf_counter()
     for i in range(args.warmup, total):
         ev, X, info = one(i)
@@ -775,6 +872,7 @@ def main():
             f"{info['t_total']:.3f} s, filter {info['t_filter']:.3f} s")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    MARKER.pop()
     elapsed = t1 - t0
     rel_res = residual_check(probs[total - 1], ev, X)
     ev64 = ev

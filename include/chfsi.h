@@ -336,11 +336,19 @@ typedef struct {
 /* Start a server on the current HIP device.  CHFSI_EINVAL on bad config. */
 chfsi_status chfsi_server_create(chfsi_server* out, const chfsi_server_config* cfg);
 
-/* Queue one problem of sequence `seq`.  H, S: device n x n (S required);
- * evals: host, nev doubles; X: device n x nev (may be NULL).  All four must
- * stay valid until chfsi_server_wait returns for the ticket.  The problem is
- * solved as by chfsi_solve, warm-started from the sequence's previous problem
- * when its size and block width match. */
+/* Queue one problem of sequence `seq`.  H, S: device n x n; evals: host,
+ * nev doubles; X: device n x nev (may be NULL).  All four must stay valid
+ * until chfsi_server_wait returns for the ticket.  S == NULL: the overlap
+ * matrix is the one of the sequence's last request that passed S (same n),
+ * which must then still be valid and unchanged until this request
+ * completes; the request reuses that matrix's Cholesky factor when a
+ * worker's context still holds it (such requests go to that worker when it
+ * is idle), else factors it again (CHFSI_EINVAL at completion if the
+ * sequence never passed S).  The problem is solved as by chfsi_solve,
+ * warm-started from the sequence's previous problem when its size and block
+ * width match.  A worker's context serves every problem size up to the
+ * largest it has taken; a larger one grows it, or replaces it when the
+ * budget does not allow growth. */
 chfsi_status chfsi_server_submit(chfsi_server s, int64_t seq, int64_t n, const void* H, int64_t ldh, const void* S,
                                  int64_t lds, int64_t nev, int64_t nex, double tol, double* evals, void* X, int64_t ldx,
                                  int64_t* ticket);

@@ -52,7 +52,7 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
         if p.returncode != 0:
             raise RuntimeError(f"command failed ({p.returncode}): {' '.join(cmd)}\n{out}")
     tmp = LIB + ".tmp"
-    _run(["hipcc", *FLAGS, "-shared", "-o", tmp, *objs], verbose)
+    _run(["hipcc", *FLAGS, "-shared", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

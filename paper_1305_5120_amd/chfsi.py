@@ -504,20 +504,27 @@ class Server:
         self._live = {}
 
     def submit(self, seq, H, S, nev, nex, tol=1e-10, want_vectors=True):
+        """Queue one problem of sequence `seq`.  S = None: the sequence's
+        overlap matrix is unchanged since its last request that passed S
+        (which must stay valid until this request completes)."""
         import torch
         _check_dev(H, "H")
-        _check_dev(S, "S")
         n = H.shape[0]
         _check_shape(H, n, n, "H")
-        _check_shape(S, n, n, "S")
         Hc, ldh = colmajor(H)
-        Sc, lds = colmajor(S)
+        if S is not None:
+            _check_dev(S, "S")
+            _check_shape(S, n, n, "S")
+            Sc, lds = colmajor(S)
+        else:
+            Sc, lds = None, n
         evals = np.zeros(nev)
         X = empty_colmajor(n, nev, H.device) if want_vectors else None
         # the workers run on their own streams: inputs must be complete first
         torch.cuda.current_stream().synchronize()
         t = c_i64()
-        st = self.lib.chfsi_server_submit(self.h, int(seq), n, Hc.data_ptr(), ldh, Sc.data_ptr(), lds, int(nev), int(nex),
+        st = self.lib.chfsi_server_submit(self.h, int(seq), n, Hc.data_ptr(), ldh,
+                                          Sc.data_ptr() if Sc is not None else None, lds, int(nev), int(nex),
                                           float(tol), evals.ctypes.data_as(c_vp),
                                           X.data_ptr() if X is not None else None, n, ctypes.byref(t))
         if st != 0:

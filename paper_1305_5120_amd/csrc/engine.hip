@@ -19,6 +19,11 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
+#include <cstdio>
+#include <cstdlib>
+
 #include "../../include/chfsi.h"
 #include "gemm.hpp"
 #include "kernels.hpp"
@@ -26,6 +31,27 @@
 using namespace chfsi;
 
 namespace {
+
+// Named host ranges around the solver's phases, for profilers that record
+// ROCTX markers (rocprofv3 --marker-trace); without one they cost a call.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
+// Diagnostics on stderr, from the environment variable CHFSI_LOG: 1 = one
+// line per solve (sizes, iterations, phase times, residual), 2 = also one
+// line per outer iteration (locked count, active width, precision split,
+// filter interval, first active residual).
+int log_level() {
+  static const int level = [] {
+    const char* e = std::getenv("CHFSI_LOG");
+    return e ? std::atoi(e) : 0;
+  }();
+  return level;
+}
 
 struct DBuf {
   void* p = nullptr;
@@ -115,6 +141,7 @@ struct chfsi_ctx_s {
   // n x k blocks
   DBuf Y, Yb, F, Qb, Wk, Wz;
   int64_t kcap = 0;
+  int64_t nk_n = 0;  // n the n x k blocks were sized for
   // k x k and small
   DBuf G, Z, Z2, G2, Ztmp, mu, rho, rank, norms, flags;
   DBuf P;  // split-K partial tiles
@@ -150,7 +177,17 @@ struct chfsi_ctx_s {
     }
   }
 
-  GemmWork gw() const { return GemmWork{P.z(), P_elems}; }
+  // Split scratch the products may use: the part sized for the current
+  // problem (n, k), not all the buffer has grown to, so that the splits
+  // chosen - and the rounding of the results - do not depend on the sizes
+  // a context served before (the serving loop reuses contexts across sizes).
+  // Entry points that size the scratch for their own product widen it.
+  size_t P_cap = 0;
+  GemmWork gw() const { return GemmWork{P.z(), std::min(P_elems, P_cap)}; }
+  static size_t split_scratch_elems(int64_t n, int64_t k, int filter_splitk) {
+    return 8 * (size_t)k * k + (size_t)n * std::max((size_t)filter_splitk * k, splitk_columns(k)) + ((size_t)1 << 16);
+  }
+
 
   void ensure_host(size_t elems) {
     if (hbuf_elems >= elems) return;
@@ -173,7 +210,8 @@ struct chfsi_ctx_s {
   }
 
   void ensure_k(int64_t k) {
-    if (k <= kcap && Y.p) return;
+    P_cap = split_scratch_elems(n, k, opts.filter_splitk);
+    if (k <= kcap && Y.p && n <= nk_n) return;
     const int64_t kk = std::max<int64_t>(k, kcap);
     // keep the warm block across growth
     DBuf oldY;
@@ -197,8 +235,7 @@ struct chfsi_ctx_s {
     mu.release(); mu.ensure((size_t)kk * sizeof(double));
     rho.release(); rho.ensure((size_t)kk * sizeof(double));
     rank.release(); rank.ensure((size_t)kk * sizeof(int));
-    P_elems = 8 * (size_t)kk * kk + (size_t)n * std::max((size_t)opts.filter_splitk * kk, splitk_columns(kk)) +
-              ((size_t)1 << 16);
+    P_elems = split_scratch_elems(n, kk, opts.filter_splitk);
     P.release();
     P.ensure(P_elems * sizeof(zc));
     const int64_t npan = cdiv(kk, HH_NB);
@@ -217,6 +254,19 @@ struct chfsi_ctx_s {
       oldY.release();
     }
     kcap = kk;
+    nk_n = n;
+  }
+
+  // Take problems of size n_new with the same buffers: every buffer is
+  // checked against the size it needs before use and only grows, so a
+  // context made for a larger n serves smaller ones without new
+  // allocations.  The factor and the kept block belong to the old size and
+  // are dropped.
+  void resize(int64_t n_new) {
+    if (n_new == n) return;
+    n = n_new;
+    have_factors = false;
+    warm_valid = false;
   }
 
   void ensure_small() {
@@ -971,8 +1021,14 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
   c->ensure_k(k);
 
   auto t0 = std::chrono::steady_clock::now();
+  roctxRangePushA("chfsi.reduce");
   // (a kept block meant for a changed S is carried to the new factor here)
-  c->reduce(s.H, s.ldh, s.S, s.lds, use_state);
+  try {
+    c->reduce(s.H, s.ldh, s.S, s.lds, use_state);
+  } catch (...) {
+    roctxRangePop();
+    throw;
+  }
   s.mixed = o.precision == 1;
   s.mixed_switch = o.mixed_switch_digits > 0 ? std::pow(10.0, -o.mixed_switch_digits) : MIXED_SWITCH;
   if (s.mixed) {
@@ -982,16 +1038,21 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
     to_f32(c->A.z(), n, (cc*)c->A32.p, n, n, n, st);
   }
   c->sync();
+  roctxRangePop();
   inf.t_reduce = secs_since(t0);
 
   t0 = std::chrono::steady_clock::now();
   double lz[3];
-  c->lanczos(c->A.z(), n, o.lanczos_steps, o.seed, 1u, lz);
-  inf.theta_min = lz[0];
-  inf.b_upper = lz[2];
-  c->lanczos(s.H, s.ldh, o.lanczos_steps, o.seed, 2u, lz);
-  inf.h_H = std::max(std::fabs(lz[0]), std::fabs(lz[1]));
+  {
+    Range r_lanczos("chfsi.lanczos");
+    c->lanczos(c->A.z(), n, o.lanczos_steps, o.seed, 1u, lz);
+    inf.theta_min = lz[0];
+    inf.b_upper = lz[2];
+    c->lanczos(s.H, s.ldh, o.lanczos_steps, o.seed, 2u, lz);
+    inf.h_H = std::max(std::fabs(lz[0]), std::fabs(lz[1]));
+  }
   inf.t_lanczos = secs_since(t0);
+  Range r_start("chfsi.start_block");
 
   zc* Y = c->Y.z();
   zc* F = c->F.z();
@@ -1074,6 +1135,7 @@ void solve_filter(chfsi_ctx c, SolveState& s) {
   const int64_t n = c->n, ka = s.k - s.cl;
   hipStream_t st = c->st;
   solve_filter_begin(s);
+  Range r_filter("chfsi.filter");
   CHFSI_HIP(hipEventRecord(s.ev[0], st));
   zc* Y = c->Y.z();
   zc* F = c->F.z();
@@ -1105,10 +1167,17 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   zc* Qb = c->Qb.z();
   double* mu_d = c->mu.d();
   double* rho_d = c->rho.d();
-  inf.qr_householder += c->orthonormalize_active(Y, F, cl, k, Qb, n) ? 1 : 0;
+  {
+    Range r_qr("chfsi.qr");
+    inf.qr_householder += c->orthonormalize_active(Y, F, cl, k, Qb, n) ? 1 : 0;
+  }
   CHFSI_HIP(hipEventRecord(s.ev[2], st));
-  c->rayleigh_ritz(c->A.z(), n, Qb + cl * n, n, ka, Y + cl * n, n, mu_d, c->Wk.z(), c->Wz.z(), 1e-3 * s.hs);
+  {
+    Range r_rr("chfsi.rayleigh_ritz");
+    c->rayleigh_ritz(c->A.z(), n, Qb + cl * n, n, ka, Y + cl * n, n, mu_d, c->Wk.z(), c->Wz.z(), 1e-3 * s.hs);
+  }
   CHFSI_HIP(hipEventRecord(s.ev[3], st));
+  Range r_lock("chfsi.residuals_lock");
   // residuals of the columns that can lock (at most nev - cl of them: the
   // extra columns never do); mixed precision reads every active column's
   // residual for its precision rules
@@ -1164,6 +1233,12 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   s.a = mu[ka - 1];
   s.a0 = std::min(s.a0, mu[0]);
   inf.converged = (int32_t)s.cl;
+  if (log_level() >= 2)
+    std::fprintf(stderr,
+                 "[chfsi] n=%lld it=%d locked=%lld/%lld active=%lld fp64_cols=%lld a=%.6g a0=%.6g b=%.6g "
+                 "rho_first=%.3e (x h_H)\n",
+                 (long long)n, s.it, (long long)s.cl, (long long)s.nev, (long long)ka, (long long)s.split, s.a, s.a0,
+                 s.b, nl < ka ? rho[nl] / inf.h_H : 0.0);
   if (s.cl >= s.nev) {
     s.converged = true;
     s.done = true;
@@ -1185,10 +1260,13 @@ void solve_finish(chfsi_ctx c, SolveState& s, chfsi_info* info) {
     if (j < nout) mx = std::max(mx, s.rho_lock[j] / inf.h_H);
   }
   inf.max_rel_residual = mx;
-  if (s.X && s.nev > 0)
-    c->gemm(OP_C, OP_N, n, s.nev, n, 1.0, c->Linv.z(), n, c->Y.z(), n, s.X, s.ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
-            GEMM_TRI_A_UPPER);
-  c->sync();
+  {
+    Range r_back("chfsi.backtransform");
+    if (s.X && s.nev > 0)
+      c->gemm(OP_C, OP_N, n, s.nev, n, 1.0, c->Linv.z(), n, c->Y.z(), n, s.X, s.ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
+              GEMM_TRI_A_UPPER);
+    c->sync();
+  }
   // warm state for the next problem of the sequence
   c->warm_valid = true;
   c->warm_k = s.k;
@@ -1201,6 +1279,14 @@ void solve_finish(chfsi_ctx c, SolveState& s, chfsi_info* info) {
   inf.filter_launches_fp32 = c->filt_launches[1];
   inf.filter_kernel_seconds_fp32 = c->filt_kernel_s[1];
   inf.t_total = secs_since(s.t_start);
+  if (log_level() >= 1)
+    std::fprintf(stderr,
+                 "[chfsi] solve n=%lld nev=%lld k=%lld precision=%d warm=%d iterations=%d (fp32 %d) locked=%d "
+                 "t_total=%.4f s (reduce %.4f lanczos %.4f filter %.4f qr %.4f rr %.4f resid %.4f) "
+                 "filter %.2f TFLOP max_rel_residual=%.3e\n",
+                 (long long)n, (long long)s.nev, (long long)s.k, c->opts.precision, inf.warm_start, inf.iterations,
+                 inf.iterations_fp32, inf.converged, inf.t_total, inf.t_reduce, inf.t_lanczos, inf.t_filter, inf.t_qr,
+                 inf.t_rr, inf.t_resid, inf.filter_flops * 1e-12, inf.max_rel_residual);
   if (info) *info = inf;
   if (!s.converged)
     throw Error(ST_ENOCONV, "not converged after " + std::to_string(c->opts.max_iter) + " iterations (" +
@@ -1239,6 +1325,11 @@ struct SeqState {
   DBuf X;  // n x k block of the last solve, generalized space
   double a0 = 0, a = 0;
   bool valid = false, busy = false;
+  // the overlap matrix of the sequence's last request that passed one (a
+  // request without S reuses it: the factor of a worker that still holds
+  // it, else a new factorization of this matrix)
+  const zc* S = nullptr;
+  int64_t lds = 0, S_n = 0;
 };
 
 struct Req {
@@ -1262,9 +1353,11 @@ struct Worker {
   std::thread th;
   hipStream_t st = nullptr;
   chfsi_ctx ctx = nullptr;
-  int64_t n = 0;
-  size_t bytes = 0;  // accounted footprint of ctx
+  int64_t cap_n = 0, cap_k = 0;  // largest problem the context's buffers were grown for
+  size_t bytes = 0;              // accounted footprint of ctx
   bool busy = false;
+  bool recreate = false;  // next request: a fresh context of that request's size
+  int64_t factor_seq = -1;  // sequence whose overlap factor the context holds
 };
 
 // Device bytes of a solver context for problems of size n with block k.
@@ -1303,16 +1396,29 @@ struct chfsi_server_s {
     return it->second->X.bytes >= want ? 0 : want - it->second->X.bytes;
   }
 
-  // Choose the next admissible request for worker w (lock held).
+  // Choose the next admissible request for worker w (lock held).  The
+  // worker's context serves any problem its buffers were grown for; a larger
+  // one grows it when the budget allows, else it is replaced by a context
+  // of the request's size.  A request that reuses its sequence's overlap
+  // factor goes to the idle worker holding that factor when there is one.
   Req* pick(Worker& w) {
     for (auto it = queue.begin(); it != queue.end(); ++it) {
       Req* r = *it;
       auto sq = seqs.find(r->seq);
       if (sq != seqs.end() && sq->second->busy) continue;  // one problem of a sequence at a time, in order
       const int64_t k = r->nev + r->nex;
+      if (!r->S && w.factor_seq != r->seq) {
+        bool holder_idle = false;
+        for (auto& o : workers)
+          if (o.get() != &w && !o->busy && o->factor_seq == r->seq && o->cap_n >= r->n && o->cap_k >= k)
+            holder_idle = true;
+        if (holder_idle) continue;
+      }
       const size_t ctx_need = ctx_footprint(r->n, k, cfg.opts.precision);
-      const size_t ctx_delta = (w.n == r->n && w.bytes >= ctx_need) ? 0 : ctx_need;
-      const size_t ctx_freed = (ctx_delta && w.ctx) ? w.bytes : 0;
+      const size_t grown = ctx_footprint(std::max(w.cap_n, r->n), std::max(w.cap_k, k), cfg.opts.precision);
+      size_t ctx_delta = w.ctx ? (grown > w.bytes ? grown - w.bytes : 0) : ctx_need;
+      size_t ctx_freed = 0;
+      bool recreate = false;
       size_t need = ctx_delta + seq_need(*r);
       if ((size_t)cfg.hbm_budget_bytes < ctx_need + (size_t)r->n * k * sizeof(zc)) {
         // can never fit
@@ -1324,7 +1430,7 @@ struct chfsi_server_s {
         cv_done.notify_all();
         return pick(w);
       }
-      if (used - ctx_freed + need > (size_t)cfg.hbm_budget_bytes) {
+      if (used + need > (size_t)cfg.hbm_budget_bytes) {
         // release idle workers' contexts and retry
         for (auto& o : workers)
           if (o.get() != &w && !o->busy && o->ctx) {
@@ -1332,16 +1438,30 @@ struct chfsi_server_s {
             o->ctx = nullptr;
             used -= o->bytes;
             o->bytes = 0;
-            o->n = 0;
+            o->cap_n = o->cap_k = 0;
+            o->factor_seq = -1;
           }
-        if (used - ctx_freed + need > (size_t)cfg.hbm_budget_bytes) continue;
       }
+      if (used + need > (size_t)cfg.hbm_budget_bytes && w.ctx && ctx_delta) {
+        // this worker's own context replaced by one of the request's size
+        recreate = true;
+        ctx_freed = w.bytes;
+        ctx_delta = ctx_need;
+        need = ctx_delta + seq_need(*r);
+      }
+      if (used - ctx_freed + need > (size_t)cfg.hbm_budget_bytes) continue;
       queue.erase(it);
       used = used - ctx_freed + need;
       peak = std::max(peak, used);
-      if (ctx_delta) {
+      if (recreate) {
+        w.recreate = true;
         w.bytes = ctx_need;
-        w.n = -r->n;  // context to be (re)created for n by the worker
+        w.cap_n = r->n;
+        w.cap_k = k;
+      } else if (ctx_delta || !w.ctx) {
+        w.bytes = w.ctx ? grown : ctx_need;
+        w.cap_n = std::max(w.cap_n, r->n);
+        w.cap_k = std::max(w.cap_k, k);
       }
       auto& st = seqs[r->seq];
       if (!st) st.reset(new SeqState());
@@ -1355,25 +1475,44 @@ struct chfsi_server_s {
 
   void run(Worker& w, Req& r, SeqState& q) {
     const int64_t k = r.nev + r.nex;
+    Range range("chfsi.server.request");
     try {
-      if (w.n < 0) {
+      if (w.recreate || !w.ctx) {
         if (w.ctx) chfsi_release(w.ctx);
         w.ctx = nullptr;
+        w.recreate = false;
+        w.factor_seq = -1;
         int st = chfsi_create(&w.ctx, r.n, &cfg.opts, w.st);
         if (st != CHFSI_OK) throw Error(st, "server: context creation failed");
-        w.n = r.n;
       }
       chfsi_ctx c = w.ctx;
+      c->resize(r.n);
       c->warm_valid = false;
+      // the overlap matrix: the request's, else the factor this worker holds
+      // for the sequence, else the sequence's remembered matrix
+      const zc* S = r.S;
+      int64_t lds = r.lds;
+      if (S) {
+        q.S = S;
+        q.lds = lds;
+        q.S_n = r.n;
+      } else if (!(w.factor_seq == r.seq && c->have_factors)) {
+        if (!q.S || q.S_n != r.n) throw Error(ST_EINVAL, "server: no overlap matrix for this sequence's request");
+        S = q.S;
+        lds = q.lds;
+      }
+      w.factor_seq = -1;  // until the reduction has run
       const bool warm = q.valid && q.n == r.n && q.k == k;
       const double bounds[2] = {q.a0, q.a};
       c->err.clear();
-      solve_impl(c, r.H, r.ldh, r.S, r.lds, r.nev, r.nex, warm ? q.X.z() : nullptr, r.n, warm ? k : 0, r.tol, r.evals,
+      solve_impl(c, r.H, r.ldh, S, lds, r.nev, r.nex, warm ? q.X.z() : nullptr, r.n, warm ? k : 0, r.tol, r.evals,
                  r.X, r.ldx, &r.info, warm ? bounds : nullptr);
+      if (c->have_factors) w.factor_seq = r.seq;
       r.status = CHFSI_OK;
     } catch (const Error& e) {
       r.status = e.code;
       r.err = e.what();
+      if (w.ctx && w.ctx->have_factors && e.code == ST_ENOCONV) w.factor_seq = r.seq;
     } catch (const std::exception& e) {
       r.status = CHFSI_EHIP;
       r.err = e.what();
@@ -2054,6 +2193,7 @@ chfsi_status chfsi_filter(chfsi_ctx c, const void* A, int64_t lda, void* Y, int6
       c->P.release();
       c->P.ensure(c->P_elems * sizeof(zc));
     }
+    c->P_cap = std::max(c->P_cap, std::min(c->P_elems, (size_t)c->opts.filter_splitk * c->n * k));
     const int64_t n = c->n;
     if (c->opts.precision == 1) {
       // mixed precision: the filter itself in complex FP32
@@ -2218,6 +2358,7 @@ chfsi_status chfsi_zgemm(chfsi_ctx c, int32_t opA, int32_t opB, int64_t M, int64
       c->P.ensure(need * sizeof(zc));
       c->P_elems = need;
     }
+    c->P_cap = c->P_elems;  // this product may use the whole scratch
     c->gemm(opA, opB, M, N, K, alpha, (const zc*)A, lda, (const zc*)B, ldb, (zc*)C, ldc, beta, (const zc*)X, ldx, gamma,
             (const zc*)Z, ldz, structure, true, false, cfg, nsplit);
     c->sync();
@@ -2293,7 +2434,7 @@ chfsi_status chfsi_server_submit(chfsi_server s, int64_t seq, int64_t n, const v
                                  int64_t lds, int64_t nev, int64_t nex, double tol, double* evals, void* X, int64_t ldx,
                                  int64_t* ticket) {
   if (!s || !ticket) return CHFSI_EINVAL;
-  if (n < 1 || !block_sizes_ok(n, nev, nex) || !(tol > 0.0) || !H || !S || !evals || ldh < n || lds < n ||
+  if (n < 1 || !block_sizes_ok(n, nev, nex) || !(tol > 0.0) || !H || !evals || ldh < n || (S && lds < n) ||
       (X && ldx < n))
     return CHFSI_EINVAL;
   std::unique_ptr<Req> r(new Req());
@@ -2381,6 +2522,8 @@ chfsi_status chfsi_server_release_sequence(chfsi_server s, int64_t seq) {
   s->used -= it->second->X.bytes;
   it->second->X.release();
   s->seqs.erase(it);
+  for (auto& w : s->workers)
+    if (w->factor_seq == seq) w->factor_seq = -1;  // a later sequence of this id brings its own S
   s->cv_work.notify_all();
   return CHFSI_OK;
 }

@@ -148,3 +148,64 @@ def test_server_at_configuration_sizes(lib):
     stats = srv.stats()
     assert stats["completed"] == 6 and stats["failed"] == 0
     srv.close()
+
+
+def test_server_reuses_the_overlap_factor(lib, sequences):
+    """Requests that pass S = None (the sequence's overlap matrix unchanged)
+    reuse the factor a worker holds, or factor the remembered matrix again:
+    the same bits as passing S every time, with one worker (always the
+    holder) and with three (the holder when idle, else a new factorization)."""
+    order = [(s, ell) for ell in range(STEPS) for s in SIZES]
+    ref, _ = _run(lib, sequences, order, workers=1)
+    for workers in (1, 3):
+        srv = lib.Server(workers=workers, hbm_budget_bytes=8 << 30, degree=10, seed=0)
+        tickets = {}
+        for s, ell in order:
+            p, H, S = sequences[s][ell]
+            nev, nex = _nev(p.n)
+            tickets[(s, ell)] = srv.submit(s, H, S if ell == 0 else None, nev, nex, tol=1e-10)
+        for key, t in tickets.items():
+            ev, X, info, lat, st = srv.wait(t)
+            assert st == 0, key
+            assert np.array_equal(ev, ref[key][0]), (workers, key)
+            assert np.array_equal(X.cpu().numpy(), ref[key][1]), (workers, key)
+        srv.close()
+
+
+def test_server_request_without_any_overlap_matrix_fails(lib, sequences):
+    p, H, S = sequences[0][0]
+    srv = lib.Server(workers=1, degree=10)
+    t = srv.submit(7, H, None, *_nev(p.n))
+    ev, X, info, lat, st = srv.wait(t, raise_on_error=False)
+    assert st == -1
+    srv.close()
+
+
+def test_server_context_reused_across_sizes(lib):
+    """One worker takes a large problem, then smaller and larger ones: its
+    context serves every size from the same buffers (growing for the larger
+    one), and each result is the same bits as on a fresh server (the split
+    choices do not depend on the sizes served before).  Sizes above 1024
+    rows take the split-K products."""
+    import torch
+    cases = [(2100, 30), (1100, 20), (2400, 24), (1100, 20)]
+    probs = [workloads.make_problem_torch(n, 900 + i, device="cuda", rng_kind="device") for i, (n, _) in
+             enumerate(cases)]
+    fresh = []
+    for (n, nev), p in zip(cases, probs):
+        srv = lib.Server(workers=1, hbm_budget_bytes=64 << 30, degree=10, seed=0)
+        ev, X, info, lat, st = srv.wait(srv.submit(0, p["H"], p["S"], nev, 12, tol=1e-10))
+        assert st == 0
+        fresh.append((ev, X.cpu().numpy()))
+        srv.close()
+    srv = lib.Server(workers=1, hbm_budget_bytes=64 << 30, degree=10, seed=0)
+    tickets = [srv.submit(i, p["H"], p["S"], nev, 12, tol=1e-10) for i, ((n, nev), p) in enumerate(zip(cases, probs))]
+    for i, t in enumerate(tickets):
+        ev, X, info, lat, st = srv.wait(t)
+        assert st == 0
+        assert np.array_equal(ev, fresh[i][0]), i
+        assert np.array_equal(X.cpu().numpy(), fresh[i][1]), i
+        ok, dmax = _checks.eig_ok(ev, np.sort(probs[i]["lam"])[:cases[i][1]],
+                                  float(torch.linalg.eigvalsh(probs[i]["H"]).abs().max()))
+        assert ok, (i, dmax)
+    srv.close()

@@ -115,3 +115,29 @@ def test_bench_refuses_several_gpus(capsys):
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The C oracle built with -fsanitize=address,undefined (host code, gcc)
+    runs its solve's paths (cold, warm with bounds, iteration limit, S not
+    positive definite, invalid sizes) with no sanitizer report, and the cold
+    solve finds the constructed smallest eigenvalues."""
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    here = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(here)
+    exe = str(tmp_path / "oracle_sanitize")
+    cmd = ["gcc", "-O1", "-g", "-std=c99", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-fno-sanitize-recover=all", "-ffp-contract=off", "-D_POSIX_C_SOURCE=200809L", "-o", exe,
+           os.path.join(here, "oracle_sanitize_main.c"), os.path.join(root, "oracle", "chfsi_oracle.c"), "-lm"]
+    b = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    assert b.returncode == 0, b.stdout
+    # (verify_asan_link_order=0: a library preloaded by the environment may
+    # come before the sanitizer runtime in the load order)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env, timeout=120)
+    assert r.returncode == 0 and "oracle sanitizer run ok" in r.stdout, r.stdout
