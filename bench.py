@@ -167,15 +167,17 @@ def measured_traffic(workload):
         return None
 
 
-def measured_mfma_busy(workload):
-    """Matrix-core busy fraction of the filter kernel from the committed
-    counter summary (SQ_VALU_MFMA_BUSY_CYCLES over the CUs' busy cycles), or
-    None."""
+def measured_mfma(workload):
+    """Matrix-core use of the filter kernel from the committed counter
+    summary of this workload: (busy fraction of the matrix pipes over the
+    CUs' busy cycles, executed matrix flops over the FP64 matrix peak), or
+    (None, None) when the summary is absent or was taken on a different
+    version of the kernel source."""
     vals = _current_summary(f"chebyshev_step_f64_{workload}_mfma.md")
     try:
-        return float(vals["mfma_busy_fraction"]) if vals else None
+        return (float(vals["mfma_busy_fraction"]), float(vals["matrix_core_flop_fraction"])) if vals else (None, None)
     except (KeyError, ValueError):
-        return None
+        return None, None
 
 
 CAL_N = 6000
@@ -819,6 +821,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="do not time filter launches with events")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision pass over the same problems (after the timed region)")
+    ap.add_argument("--save-inputs", default=None,
+                    help="write the generated problems (H, S, spectrum) to this file and exit")
+    ap.add_argument("--load-inputs", default=None, help="read the problems from a --save-inputs file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, run a device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -842,9 +847,29 @@ def main():
     dev = torch.device("cuda:0")
     cfg = WORKLOADS[args.workload]
     total = args.warmup + args.steps
-    log(f"[bench] workload {args.workload}: generating inputs")
-    probs = make_problems(cfg, total, dev)
+    if args.load_inputs:
+        # inputs written by an earlier --save-inputs run of this workload
+        # (profilers that intercept every launch need not see the generator)
+        saved = torch.load(args.load_inputs, map_location=dev, weights_only=True)
+        if saved["workload"] != args.workload or (cfg["sequence"] and len(saved["problems"]) < total):
+            sys.exit(f"{args.load_inputs} holds other inputs than this run needs")
+        probs = [{k: (v.cpu().numpy() if k == "lam" else v.mT.contiguous().mT) for k, v in p.items()}
+                 for p in saved["problems"][:total]]
+        if not cfg["sequence"]:
+            probs = probs[:1] * total  # one problem, solved cold at every step
+        log(f"[bench] workload {args.workload}: inputs loaded from {args.load_inputs}")
+    else:
+        log(f"[bench] workload {args.workload}: generating inputs")
+        probs = make_problems(cfg, total, dev)
     torch.cuda.synchronize()
+    if args.save_inputs:
+        keep = ("H", "S", "lam")
+        torch.save({"workload": args.workload,
+                    "problems": [{k: (v.cpu() if torch.is_tensor(v) else torch.as_tensor(v)) for k, v in p.items()
+                                  if k in keep} for p in (probs if cfg["sequence"] else probs[:1])]},
+                   args.save_inputs)
+        log(f"[bench] inputs saved to {args.save_inputs}")
+        return
 
     n, nev, nex = cfg["n"], cfg["nev"], cfg["nex"]
     ctx = chfsi.create(n, degree=cfg["degree"], seed=0, profile=0 if args.no_profile else 1)
@@ -888,7 +913,7 @@ def main():
     # written; 8 n^2 k_a flops per launch give the mean k_a
     mean_ka = (flops / launches) / (8.0 * n * n) if launches else 0.0
     alg_bytes = 16.0 * n * n + 48.0 * n * mean_ka
-    busy = measured_mfma_busy(args.workload)
+    busy, core_frac = measured_mfma(args.workload)
     out = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -915,6 +940,7 @@ def main():
                      "flop_count": FLOP_COUNT_NOTE,
                      "matrix_core_frac_from_flops": (GAUSS3_SHARE * achieved / PEAK_FP64_MFMA) if achieved else None,
                      "matrix_core_busy_counter": busy,
+                     "matrix_core_flop_frac_counter": core_frac,
                      "traffic": measured_traffic(args.workload),
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "algorithmic_flops_per_launch": flops / launches if launches else None},
