@@ -620,13 +620,15 @@ def theta_angles(prevX, X, S):
 
 
 def _standard_eigvals(H, S, count):
-    """The `count` smallest eigenvalues of the pencil (H, S) from a dense
-    library solver on the device (Cholesky, two triangular solves,
-    eigvalsh): the reference of the warm/cold study's checks."""
+    """The `count` smallest eigenvalues of the pencil (H, S) from dense
+    library eigensolvers on the device: S = V diag(s) V^H, then the
+    eigenvalues of S^{-1/2} H S^{-1/2} (a pencil similar to (H, S); S is
+    well conditioned here).  The reference of the warm/cold study's checks
+    (the library's triangular solve runs out of workspace at these sizes)."""
     import torch
-    Lc = torch.linalg.cholesky(S)
-    W = torch.linalg.solve_triangular(Lc, H, upper=False)
-    A = torch.linalg.solve_triangular(Lc, W.conj().T.contiguous(), upper=False)
+    s, V = torch.linalg.eigh(S)
+    Sih = (V * s.rsqrt().to(V.dtype)[None, :]) @ V.conj().T
+    A = Sih @ H @ Sih
     A = (A + A.conj().T) / 2
     return torch.linalg.eigvalsh(A)[:count].cpu().numpy()
 
