@@ -63,24 +63,27 @@ struct PF32 {
   static __device__ __forceinline__ E mk(R x, R y) { return make_float2(x, y); }
 };
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, int NW = 4>
 struct ZTile {
-  static constexpr int NT = 256;
+  static constexpr int NT = 64 * NW;  // threads: NW waves
   static constexpr int PAD = 1;
   static constexpr int LDA_S = BM + PAD;
   static constexpr int LDB_S = BN + PAD;
   static constexpr int EA = BM * BK / NT;  // A elements per thread per slab
   static constexpr int EB = BK * BN / NT;  // B elements per thread per slab
-  // waves along M: 2 (2x2 waves) where half the tile width is a whole
-  // number of 16-column fragments, else 4 (4x1, e.g. 48 columns)
-  static constexpr int WMW = (BN % 32 == 0) ? 2 : 4;
-  static constexpr int MI = BM / (16 * WMW);       // 16-row fragments per wave
-  static constexpr int NJ = BN / (16 * (4 / WMW)); // 16-col fragments per wave
+  // waves along M: with four waves 2 (2x2) where half the tile width is a
+  // whole number of 16-column fragments, else 4 (4x1, e.g. 48 columns);
+  // with eight waves 2 (2x4: 32 x 16 per wave for a 64 x 64 tile)
+  static constexpr int WMW = NW == 8 ? 2 : ((BN % 32 == 0) ? 2 : 4);
+  static constexpr int WN = NW / WMW;               // waves along N
+  static constexpr int MI = BM / (16 * WMW);        // 16-row fragments per wave
+  static constexpr int NJ = BN / (16 * WN);         // 16-col fragments per wave
   static constexpr int KS = BK / 4;        // MFMA depth steps per slab
-  static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
+  static_assert(NW == 4 || NW == 8, "four or eight waves");
+  static_assert(EA >= 1 && EB >= 1, "tile too small for the thread count");
   static_assert(BM * BK % NT == 0 && BK * BN % NT == 0, "tile/thread mismatch");
   static_assert(BK % 4 == 0, "BK multiple of the MFMA depth");
-  static_assert(MI >= 1 && NJ >= 1 && BM % (16 * WMW) == 0 && BN % (16 * (4 / WMW)) == 0, "wave fragments");
+  static_assert(MI >= 1 && NJ >= 1 && BM % (16 * WMW) == 0 && BN % (16 * WN) == 0, "wave fragments");
 };
 
 // Workgroup -> tile order with the XCD-aware remap (workgroup i runs on XCD
@@ -91,9 +94,9 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles) {
   return bid < full ? (bid % 8) * (ntiles / 8) + bid / 8 : bid;
 }
 
-template <class PT, int OPA, int OPB, int BM, int BN, int BK, bool G3 = false>
+template <class PT, int OPA, int OPB, int BM, int BN, int BK, bool G3 = false, int NW = 4>
 __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int batch, int split) {
-  using T = ZTile<BM, BN, BK>;
+  using T = ZTile<BM, BN, BK, NW>;
   using E = typename PT::E;
   using R = typename PT::R;
   using Acc = typename PT::Acc;
@@ -109,7 +112,7 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int wm0 = (wave % T::WMW) * (BM / T::WMW);
-  const int wn0 = (wave / T::WMW) * (BN / (4 / T::WMW));
+  const int wn0 = (wave / T::WMW) * (BN / T::WN);
 
   const int64_t mt = t / p.tiles_n, nt = t % p.tiles_n;
   const int64_t m0 = mt * BM, n0 = nt * BN;
@@ -222,11 +225,13 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
       for (int j = 0; j < T::NJ; j++) b[0][j] = Bs[buf][lk][wn0 + j * 16 + lr];
 #pragma unroll
       for (int ks = 0; ks < T::KS; ks++) {
-        // with three accumulator sets the registers for a second set of
-        // fragments are not there: read each step's fragments when it starts
-        // (the other resident waves cover the LDS latency)
-        const int c = G3 ? 0 : (ks & 1);
-        if (G3) {
+        // with three accumulator sets and four waves the registers for a
+        // second set of fragments are not there: read each step's fragments
+        // when it starts (the other resident waves cover the LDS latency);
+        // eight waves hold a quarter of the tile each and keep both sets
+        constexpr bool ONE_SET = G3 && NW == 4;
+        const int c = ONE_SET ? 0 : (ks & 1);
+        if (ONE_SET) {
           if (ks > 0) {
 #pragma unroll
             for (int i = 0; i < T::MI; i++) a[0][i] = As[buf][ks * 4 + lk][wm0 + i * 16 + lr];
@@ -384,25 +389,25 @@ __device__ __forceinline__ int64_t balanced_rows(const ZGemmParams& p, int64_t t
   return ((i & 1) ? light : heavy) * p.tiles_n + c;
 }
 
-template <int OPA, int OPB, int BM, int BN, int BK, int MINB>
-__global__ void __launch_bounds__(256, MINB) zgemm_kernel(ZGemmParams p) {
+template <int OPA, int OPB, int BM, int BN, int BK, int MINB, int NW = 4>
+__global__ void __launch_bounds__(64 * NW, MINB) zgemm_kernel(ZGemmParams p) {
   const int64_t t = balanced_rows(p, xcd_tile(blockIdx.x, (int64_t)p.tiles_m * p.tiles_n));
-  zgemm_body<PF64, OPA, OPB, BM, BN, BK, gauss3<PF64, BM, BN, MINB>()>(p, t, (int)(blockIdx.y / p.splitk),
-                                                                       (int)(blockIdx.y % p.splitk));
+  zgemm_body<PF64, OPA, OPB, BM, BN, BK, gauss3<PF64, BM, BN, MINB>(), NW>(p, t, (int)(blockIdx.y / p.splitk),
+                                                                           (int)(blockIdx.y % p.splitk));
 }
 
 // One degree step of the Chebyshev filter: the same body, launched under its
 // own symbol so that profiles separate the filter from the other products.
-template <int BM, int BN, int BK, int MINB>
-__global__ void __launch_bounds__(256, MINB) chebyshev_step_f64(ZGemmParams p) {
-  zgemm_body<PF64, OP_N, OP_N, BM, BN, BK, gauss3<PF64, BM, BN, MINB>()>(p, ZGEMM_TILE_ARGS(p));
+template <int BM, int BN, int BK, int MINB, int NW = 4>
+__global__ void __launch_bounds__(64 * NW, MINB) chebyshev_step_f64(ZGemmParams p) {
+  zgemm_body<PF64, OP_N, OP_N, BM, BN, BK, gauss3<PF64, BM, BN, MINB>(), NW>(p, ZGEMM_TILE_ARGS(p));
 }
 
 // The mixed-precision filter step: complex FP32 operands on the FP32 matrix
 // cores with FP32 accumulation.
-template <int BM, int BN, int BK, int MINB>
-__global__ void __launch_bounds__(256, MINB) chebyshev_step_f32(ZGemmParams p) {
-  zgemm_body<PF32, OP_N, OP_N, BM, BN, BK, gauss3<PF32, BM, BN, MINB>()>(p, ZGEMM_TILE_ARGS(p));
+template <int BM, int BN, int BK, int MINB, int NW = 4>
+__global__ void __launch_bounds__(64 * NW, MINB) chebyshev_step_f32(ZGemmParams p) {
+  zgemm_body<PF32, OP_N, OP_N, BM, BN, BK, gauss3<PF32, BM, BN, MINB>(), NW>(p, ZGEMM_TILE_ARGS(p));
 }
 
 // One degree step for a batch of problems of different sizes in one
@@ -559,27 +564,28 @@ constexpr Cfg CFGS[] = {
     {64, 64, 8, 4, 1.0},      // 8: as 3 with room for four workgroups per CU
     {64, 32, 16, 4, 0.8},     // 9: as 7 with room for four workgroups per CU
     {64, 48, 16, 2, 0.9},     // 10: 48 columns (4x1 waves) for active widths that pad 64 / 32
+    {64, 64, 16, 2, 1.0},     // 11: as 1 with eight waves (2x4, 32 x 16 per wave)
 };
 constexpr int NCFG = sizeof(CFGS) / sizeof(CFGS[0]);
 
-template <int OPA, int OPB, int BM, int BN, int BK, int MINB>
+template <int OPA, int OPB, int BM, int BN, int BK, int MINB, int NW = 4>
 void launch_one(ZGemmParams& p, int batch, bool filter_step, hipStream_t st) {
   p.tiles_m = (int)cdiv(p.M, BM);
   p.tiles_n = (int)cdiv(p.N, BN);
   dim3 grid((unsigned)((int64_t)p.tiles_m * p.tiles_n), (unsigned)(batch * p.splitk));
   if (OPA == OP_N && OPB == OP_N && filter_step)
-    hipLaunchKernelGGL((chebyshev_step_f64<BM, BN, BK, MINB>), grid, dim3(256), 0, st, p);
+    hipLaunchKernelGGL((chebyshev_step_f64<BM, BN, BK, MINB, NW>), grid, dim3(64 * NW), 0, st, p);
   else
-    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, BM, BN, BK, MINB>), grid, dim3(256), 0, st, p);
+    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, BM, BN, BK, MINB, NW>), grid, dim3(64 * NW), 0, st, p);
   CHFSI_CHECK_LAUNCH();
 }
 
-template <int BM, int BN, int BK, int MINB>
+template <int BM, int BN, int BK, int MINB, int NW = 4>
 void launch_one_f32(ZGemmParams& p, int batch, hipStream_t st) {
   p.tiles_m = (int)cdiv(p.M, BM);
   p.tiles_n = (int)cdiv(p.N, BN);
   dim3 grid((unsigned)((int64_t)p.tiles_m * p.tiles_n), (unsigned)(batch * p.splitk));
-  hipLaunchKernelGGL((chebyshev_step_f32<BM, BN, BK, MINB>), grid, dim3(256), 0, st, p);
+  hipLaunchKernelGGL((chebyshev_step_f32<BM, BN, BK, MINB, NW>), grid, dim3(64 * NW), 0, st, p);
   CHFSI_CHECK_LAUNCH();
 }
 
@@ -595,6 +601,7 @@ void launch_f32(int cfg, ZGemmParams& p, int batch, hipStream_t st) {
     case 8: launch_one_f32<64, 64, 8, 4>(p, batch, st); break;
     case 9: launch_one_f32<64, 32, 16, 4>(p, batch, st); break;
     case 10: launch_one_f32<64, 48, 16, 2>(p, batch, st); break;
+    case 11: launch_one_f32<64, 64, 16, 2, 8>(p, batch, st); break;
     default: throw Error(ST_EINVAL, "cgemm: bad tile configuration");
   }
 }
@@ -615,6 +622,7 @@ void launch_cfg(int cfg, ZGemmParams& p, int batch, bool filter_step, hipStream_
           case 8: launch_one<OPA, OPB, 64, 64, 8, 4>(p, batch, filter_step, st); return;
           case 9: launch_one<OPA, OPB, 64, 32, 16, 4>(p, batch, filter_step, st); return;
           case 10: launch_one<OPA, OPB, 64, 48, 16, 2>(p, batch, filter_step, st); return;
+          case 11: launch_one<OPA, OPB, 64, 64, 16, 2, 8>(p, batch, filter_step, st); return;
           default: break;
         }
       }
@@ -710,11 +718,13 @@ void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const i
 // throughput = per-tile efficiency x occupancy of the chip's workgroup slots
 // (256 CUs x workgroups per CU), charging split-K for its partial-tile traffic.
 // Cost per computed column of the 48- and 32-wide filter tiles relative to
-// the 64-wide tile's (FP64, tall deep products; a sweep of active widths 24
-// to 440 at n = 4000 on MI355X: the 48-wide tile's 4x1 waves read more LDS
-// per matrix-core product).  With these weights the rule picks the fastest
-// of the three at every width of the sweep.
-constexpr double W48_COST = 1.10, W32_COST = 1.08;
+// the 64-wide eight-wave tile's (FP64, tall deep products; sweeps of active
+// widths 16 to 660 at n = 4000 and 10000 on MI355X, every tile with its
+// best K split: the 64-wide tile with eight waves runs 3-5 % faster than
+// with four, and the 48-wide tile's 4x1 waves read more LDS per matrix-core
+// product).  With these weights the rule picks the fastest shape at every
+// width of the sweeps but one (within 3 % there).
+constexpr double W48_COST = 1.14, W32_COST = 1.12;
 // The same for the FP32 tiles (a sweep of active widths 40 to 440 at
 // n = 4000).
 constexpr double W48_COST_F32 = 1.07, W32_COST_F32 = 1.08;
@@ -724,9 +734,9 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   const bool nn = g.opA == OP_N && g.opB == OP_N;
   // Tall, deep products (the filter's A Y_i and the Rayleigh-Ritz A Q): rules
   // read off sweeps of the configurations and splits on MI355X (n = 2000,
-  // 4000 and 10000, k_a from 24 to 660).  The 64 x 64 x 16 tile leads unless
-  // its last column tile pads N clearly more than the 64 x 32 x 16 tile's
-  // does.  K is split so that each workgroup's range stays near 1000 (the A
+  // 4000 and 10000, k_a from 16 to 660).  The 64 x 64 x 16 tile (FP64 with
+  // eight waves) leads unless its last column tile pads N clearly more than
+  // the narrower tiles do.  K is split so that each workgroup's range stays near 1000 (the A
   // panels of the workgroups resident on one XCD then fit its 4 MB L2), and
   // further where the tiles alone would leave the CUs short of work (FP32
   // steps are shorter and want about twice as many workgroups).  The tile
@@ -740,7 +750,8 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
     const double pad48 = (double)(cdiv(g.N, (int64_t)48) * 48) / (double)g.N;
     const double cost64 = pad64, cost48 = (f32 ? W48_COST_F32 : W48_COST) * pad48,
                  cost32 = (f32 ? W32_COST_F32 : W32_COST) * pad32;
-    int c = cost64 <= cost48 && cost64 <= cost32 ? 1 : (cost48 <= cost32 ? 10 : 7);
+    // (FP64: the 64-wide tile with eight waves; FP32 keeps four)
+    int c = cost64 <= cost48 && cost64 <= cost32 ? (f32 ? 1 : 11) : (cost48 <= cost32 ? 10 : 7);
     // (FP32 blocks of 97-128 columns: the 64 x 128 x 8 tile, one column tile)
     if (f32 && g.N > 96 && g.N <= 128) c = 5;
     int sk = g.K < 1500 ? 1 : g.K < 3000 ? 2 : g.K < 7000 ? 4 : 8;

@@ -144,6 +144,36 @@ def test_zgemm_structured_products_many_tile_rows(lib, flag, tile, split):
         assert np.linalg.norm(C[low] - ref[low]) <= 1e-13 * np.linalg.norm(ref[low])
 
 
+@pytest.mark.parametrize("flag,split", [(0, 1), (0, 4), (1, 4), (2, 8), (16, 1)])
+def test_zgemm_eight_wave_tile(lib, flag, split):
+    """The 64 x 64 tile with eight waves (configuration 11) in the general
+    product: plain, lower- and upper-triangular op(A) with K splits, and the
+    lower-triangle output, with the three-term epilogue; ragged sizes over
+    several tiles."""
+    rng = _rng(1100 + flag + split)
+    if flag in (1, 2):  # square triangular op(A)
+        M = K = 1100
+        N = 141
+    else:
+        M, K = 333, 500
+        N = M if flag == 16 else 141
+    Am = _cg(rng, (M, K))
+    if flag == 1:
+        Am = np.tril(Am)
+    elif flag == 2:
+        Am = np.triu(Am)
+    B = _cg(rng, (K, N))
+    X, Z = _cg(rng, (M, N)), _cg(rng, (M, N))
+    ctx = lib.create(8)
+    C = _np(lib.zgemm(ctx, 0, 0, _t(Am), _t(B), alpha=0.7, beta=-0.3, X=_t(X), gamma=1.9, Z=_t(Z),
+                      flags=flag | (11 << 8) | (split << 16)))
+    ref = 0.7 * (Am @ B) - 0.3 * X + 1.9 * Z
+    if flag == 16:
+        low = np.tril_indices(M)
+        C, ref = C[low], ref[low]
+    assert _rel(C, ref) <= 1e-13
+
+
 @pytest.mark.parametrize("split", [0, 1, 4, 16])
 def test_zgemm_lower_gram_with_k_split(lib, split):
     """Gram matrices Y^H Y of a tall block (K = 4000, 200 x 200 output) with
@@ -198,7 +228,7 @@ def test_filter_matches_oracle(lib, n, k, m):
     assert _rel(_np(Yt), ref) <= 1e-12
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 8, 9, 10])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 8, 9, 10, 11])
 def test_filter_every_tile_shape_matches_oracle(lib, tile):
     """Every tile configuration of the filter step, those forming complex
     products with three real products (64 x 64 and smaller at two
@@ -259,7 +289,7 @@ def test_filter_fp32_against_oracle(lib, n, k, m):
     assert err >= 1e-9  # really computed in FP32
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 9, 10])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 9, 10, 11])
 def test_filter_fp32_every_tile_shape(lib, tile):
     """The FP32 filter step in every tile shape (64x48 with 4x1 waves among
     them), with and without a K split, to FP32 accuracy against the FP64
