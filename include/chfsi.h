@@ -214,8 +214,8 @@ chfsi_status chfsi_philox(chfsi_ctx ctx, const uint32_t* ctr, const uint32_t* ke
  * bits 8-15: tile configuration (0 = automatic choice; 1 64x64x16, 2 32x32x16,
  * 3 64x64x8, 4 128x64x8, 5 64x128x8, 6 128x128x8, 7 64x32x16, 8 64x64x8 and
  * 9 64x32x16 with room for four workgroups per CU, 10 64x48x16, 11 64x64x16
- * with eight waves per workgroup; 3-6 and 8-11 only with op = none on both
- * sides); bits 16-23: K split (0 = automatic, 1 = none). */
+ * with eight waves per workgroup, 12 64x80x16; 3-6, 8-10 and 12 only with
+ * op = none on both sides); bits 16-23: K split (0 = automatic, 1 = none). */
 chfsi_status chfsi_zgemm(chfsi_ctx ctx, int32_t opA, int32_t opB, int64_t M, int64_t N, int64_t K, double alpha,
                          const void* A, int64_t lda, const void* B, int64_t ldb, double beta, const void* X, int64_t ldx,
                          double gamma, const void* Z, int64_t ldz, void* C, int64_t ldc, int32_t flags);

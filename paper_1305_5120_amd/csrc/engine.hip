@@ -349,19 +349,25 @@ struct chfsi_ctx_s {
       chol_diag(src, lds, Lb, ld, Lib, ld, 0, m, info, st);
     } else {
       copy2d(src, lds, Wb, ld, m, m, st);
-      for (int64_t j0 = 0; j0 < m; j0 += NB) {
-        const int64_t nb = std::min(NB, m - j0), r = m - j0 - nb;
-        chol_diag(Wb, ld, Lb, ld, Lib, ld, j0, nb, info, st);
-        if (r > 0) {
-          // L21 = W21 L11^{-H}
-          gemm(OP_N, OP_C, r, nb, nb, 1.0, Wb + (j0 + nb) + j0 * ld, ld, Lib + j0 + j0 * ld, ld,
-               Lb + (j0 + nb) + j0 * ld, ld, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER, false);
-          // W22 -= L21 L21^H (lower tiles)
-          zc* W22 = Wb + (j0 + nb) + (j0 + nb) * ld;
-          const zc* L21 = Lb + (j0 + nb) + j0 * ld;
-          gemm(OP_N, OP_C, r, r, nb, -1.0, L21, ld, L21, ld, W22, ld, 1.0, W22, ld, 0.0, nullptr, 0, GEMM_OUT_LOWER,
-               false);
+      // two levels: outer blocks of CHOL_NB_OUTER columns, whose trailing
+      // updates are deep products (rank 256 instead of 64); each outer
+      // diagonal block is factored with the 64-column diagonal kernel and
+      // its own inner updates, and its inverse completed, before the outer
+      // panel below it is solved with that inverse
+      const int64_t NBO = m > CHOL_NB_OUTER ? CHOL_NB_OUTER : m;
+      for (int64_t b0 = 0; b0 < m; b0 += NBO) {
+        const int64_t bn = std::min(NBO, m - b0), r = m - b0 - bn;
+        for (int64_t j0 = b0; j0 < b0 + bn; j0 += NB) {
+          const int64_t nb = std::min(NB, b0 + bn - j0), ri = b0 + bn - j0 - nb;
+          chol_diag(Wb, ld, Lb, ld, Lib, ld, j0, nb, info, st);
+          if (ri > 0) chol_update(Wb, Lb, Lib, ld, j0, nb, ri);
         }
+        // the products below read the triangular blocks in whole tiles: the
+        // block's strict upper triangle must hold zeros (the diagonal kernel
+        // writes them inside its 64 x 64 blocks, nothing writes the rest)
+        zero_strict_upper(Lib + b0 + b0 * ld, ld, bn, st);
+        inverse_doubling(Lb, Lib, ld, b0, bn, NB, Wb);
+        if (r > 0) chol_update(Wb, Lb, Lib, ld, b0, bn, r);
       }
       zero_strict_upper(Lb, ld, m, st);
     }
@@ -373,22 +379,40 @@ struct chfsi_ctx_s {
       if (hinfo != INT_MAX) return hinfo;
     }
     if (m <= NB) return 0;
-    // Lib: off-diagonal blocks by recursive doubling,
-    //   inv([[L11, 0], [L21, L22]]) = [[X11, 0], [-X22 L21 X11, X22]]
-    for (int64_t s = NB; s < m; s *= 2) {
-      for (int64_t i0 = 0; i0 + s < m; i0 += 2 * s) {
-        const int64_t b = std::min(s, m - i0 - s);
+    // the diagonal blocks of Lib (CHOL_NB_OUTER wide) are complete: the rest
+    // by recursive doubling from there
+    inverse_doubling(Lb, Lib, ld, 0, m, std::min<int64_t>(m, CHOL_NB_OUTER), Wb);
+    zero_strict_upper(Lib, ld, m, st);
+    return 0;
+  }
+
+  // Below a factored diagonal block (columns j0 .. j0 + nb, inverse in Lib):
+  // the panel L21 = W21 L11^{-H} of the next r rows, then W22 -= L21 L21^H
+  // (lower tiles) over those rows.
+  void chol_update(zc* Wb, zc* Lb, const zc* Lib, int64_t ld, int64_t j0, int64_t nb, int64_t r) {
+    gemm(OP_N, OP_C, r, nb, nb, 1.0, Wb + (j0 + nb) + j0 * ld, ld, Lib + j0 + j0 * ld, ld, Lb + (j0 + nb) + j0 * ld, ld,
+         0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_UPPER, false);
+    zc* W22 = Wb + (j0 + nb) + (j0 + nb) * ld;
+    const zc* L21 = Lb + (j0 + nb) + j0 * ld;
+    gemm(OP_N, OP_C, r, r, nb, -1.0, L21, ld, L21, ld, W22, ld, 1.0, W22, ld, 0.0, nullptr, 0, GEMM_OUT_LOWER, false);
+  }
+
+  // Lib over rows / columns b0 .. b0 + bn from its complete diagonal blocks
+  // of s0 columns (aligned at b0) by recursive doubling,
+  //   inv([[L11, 0], [L21, L22]]) = [[X11, 0], [-X22 L21 X11, X22]];
+  // T (ld) is work.
+  void inverse_doubling(const zc* Lb, zc* Lib, int64_t ld, int64_t b0, int64_t bn, int64_t s0, zc* T) {
+    for (int64_t s = s0; s < bn; s *= 2) {
+      for (int64_t i0 = b0; i0 + s < b0 + bn; i0 += 2 * s) {
+        const int64_t b = std::min(s, b0 + bn - i0 - s);
         const zc* L21 = Lb + (i0 + s) + i0 * ld;
         const zc* X11 = Lib + i0 + i0 * ld;
         const zc* X22 = Lib + (i0 + s) + (i0 + s) * ld;
-        zc* T = Wb;
         gemm(OP_N, OP_N, b, s, s, 1.0, L21, ld, X11, ld, T, ld, 0.0, nullptr, 0, 0.0, nullptr, 0, GEMM_TRI_B_LOWER);
         gemm(OP_N, OP_N, b, s, b, -1.0, X22, ld, T, ld, Lib + (i0 + s) + i0 * ld, ld, 0.0, nullptr, 0, 0.0, nullptr, 0,
              GEMM_TRI_A_LOWER);
       }
     }
-    zero_strict_upper(Lib, ld, m, st);
-    return 0;
   }
 
   void cholesky(const zc* S, int64_t lds) {
@@ -578,7 +602,8 @@ struct chfsi_ctx_s {
     zc* Eb = Pb + kk;
     double* lam = rfl.d();
     // step s accumulates its largest correction in slot s % 2 and clears the
-    // other slot for step s + 1 (the host has read it by then)
+    // other slot for step s + 1 (in stream order; the host reads the slot of
+    // the last step of a run of steps)
     auto* corr = static_cast<unsigned long long*>(rfc.p);
     auto read_corr = [&](int step) {
       CHFSI_HIP(hipMemcpyAsync(hbuf, corr + (step & 1), sizeof(double), hipMemcpyDeviceToHost, st));
@@ -592,15 +617,24 @@ struct chfsi_ctx_s {
     refine_coeffs(Gm, nullptr, k, tau, Eb, X, lam, corr, corr + 1, st);
     double c = read_corr(0);
     if (!(c <= ETA)) return false;
-    for (int step = 1; !(c < DONE); step++) {
-      if (step > MAX_STEPS) return false;
-      gemm(OP_N, OP_N, k, k, k, 1.0, Gm, k, X, k, Wb, k);
-      gemm(OP_C, OP_N, k, k, k, 1.0, X, k, Wb, k, Sb, k);
-      gemm(OP_C, OP_N, k, k, k, 1.0, X, k, X, k, Pb, k);
-      refine_coeffs(Sb, Pb, k, tau, Eb, nullptr, lam, corr + (step & 1), corr + ((step + 1) & 1), st);
-      gemm(OP_N, OP_N, k, k, k, 1.0, X, k, Eb, k, Xn, k, 1.0, X, k);  // X + X E
-      std::swap(X, Xn);
-      c = read_corr(step);
+    int step = 1;
+    while (!(c < DONE)) {
+      // the steps that quadratic convergence (c' <= 8 c^2; measured factors
+      // 0.2-9) needs to bring the correction below DONE, at most 4, are
+      // issued back to back and the correction is read after the last: a
+      // step that diverged leaves the last correction above GROW (or NaN)
+      int ahead = 0;
+      for (double cp = c; ahead < 4 && (ahead == 0 || !(cp < DONE)); ahead++) cp = 8.0 * cp * cp;
+      for (int i = 0; i < ahead; i++, step++) {
+        if (step > MAX_STEPS) return false;
+        gemm(OP_N, OP_N, k, k, k, 1.0, Gm, k, X, k, Wb, k);
+        gemm(OP_C, OP_N, k, k, k, 1.0, X, k, Wb, k, Sb, k);
+        gemm(OP_C, OP_N, k, k, k, 1.0, X, k, X, k, Pb, k);
+        refine_coeffs(Sb, Pb, k, tau, Eb, nullptr, lam, corr + (step & 1), corr + ((step + 1) & 1), st);
+        gemm(OP_N, OP_N, k, k, k, 1.0, X, k, Eb, k, Xn, k, 1.0, X, k);  // X + X E
+        std::swap(X, Xn);
+      }
+      c = read_corr(step - 1);
       if (!(c <= GROW)) return false;
     }
     const zc* Zf = X;

@@ -44,6 +44,8 @@ void diag_ratio(const zc* L, int64_t ld, int64_t k, double* out, hipStream_t st)
 void chol_diag(const zc* W, int64_t ldw, zc* L, int64_t ldl, zc* Linv, int64_t ldi, int64_t j0, int64_t nb, int* info,
                hipStream_t st);
 constexpr int CHOL_NB = 64;
+// Outer block of the two-level blocked Cholesky (columns; a multiple of CHOL_NB).
+constexpr int CHOL_NB_OUTER = 256;
 
 // ---- Householder QR --------------------------------------------------------
 constexpr int HH_NB = 32;

@@ -358,11 +358,11 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
 
 // Whether a tile configuration forms its complex products with three real
 // products: wherever the third accumulator set fits the registers the
-// configuration's occupancy leaves (FP64: tiles up to 64 x 64 at two
+// configuration's occupancy leaves (FP64: tiles up to 64 x 80 at two
 // workgroups per CU; FP32 accumulators take half the registers).
 template <class PT, int BM, int BN, int MINB>
 constexpr bool gauss3() {
-  return sizeof(typename PT::E) == 8 || (BM * BN <= 64 * 64 && MINB <= 2);
+  return sizeof(typename PT::E) == 8 || (BM * BN <= 64 * 80 && MINB <= 2);
 }
 
 #define ZGEMM_TILE_ARGS(p) xcd_tile(blockIdx.x, (int64_t)(p).tiles_m * (p).tiles_n), \
@@ -564,7 +564,8 @@ constexpr Cfg CFGS[] = {
     {64, 64, 8, 4, 1.0},      // 8: as 3 with room for four workgroups per CU
     {64, 32, 16, 4, 0.8},     // 9: as 7 with room for four workgroups per CU
     {64, 48, 16, 2, 0.9},     // 10: 48 columns (4x1 waves) for active widths that pad 64 / 32
-    {64, 64, 16, 2, 1.0},     // 11: as 1 with eight waves (2x4, 32 x 16 per wave)
+    {64, 64, 16, 2, 1.04},    // 11: as 1 with eight waves (2x4, 32 x 16 per wave)
+    {64, 80, 16, 2, 1.0},     // 12: 80 columns (4x1 waves, 16 x 80 each)
 };
 constexpr int NCFG = sizeof(CFGS) / sizeof(CFGS[0]);
 
@@ -602,6 +603,7 @@ void launch_f32(int cfg, ZGemmParams& p, int batch, hipStream_t st) {
     case 9: launch_one_f32<64, 32, 16, 4>(p, batch, st); break;
     case 10: launch_one_f32<64, 48, 16, 2>(p, batch, st); break;
     case 11: launch_one_f32<64, 64, 16, 2, 8>(p, batch, st); break;
+    case 12: launch_one_f32<64, 80, 16, 2>(p, batch, st); break;
     default: throw Error(ST_EINVAL, "cgemm: bad tile configuration");
   }
 }
@@ -612,6 +614,7 @@ void launch_cfg(int cfg, ZGemmParams& p, int batch, bool filter_step, hipStream_
     case 1: launch_one<OPA, OPB, 64, 64, 16, 2>(p, batch, filter_step, st); break;
     case 2: launch_one<OPA, OPB, 32, 32, 16, 2>(p, batch, filter_step, st); break;
     case 7: launch_one<OPA, OPB, 64, 32, 16, 2>(p, batch, filter_step, st); break;
+    case 11: launch_one<OPA, OPB, 64, 64, 16, 2, 8>(p, batch, filter_step, st); break;
     default:
       if constexpr (OPA == OP_N && OPB == OP_N) {
         switch (cfg) {
@@ -622,7 +625,7 @@ void launch_cfg(int cfg, ZGemmParams& p, int batch, bool filter_step, hipStream_
           case 8: launch_one<OPA, OPB, 64, 64, 8, 4>(p, batch, filter_step, st); return;
           case 9: launch_one<OPA, OPB, 64, 32, 16, 4>(p, batch, filter_step, st); return;
           case 10: launch_one<OPA, OPB, 64, 48, 16, 2>(p, batch, filter_step, st); return;
-          case 11: launch_one<OPA, OPB, 64, 64, 16, 2, 8>(p, batch, filter_step, st); return;
+          case 12: launch_one<OPA, OPB, 64, 80, 16, 2>(p, batch, filter_step, st); return;
           default: break;
         }
       }
@@ -728,6 +731,10 @@ constexpr double W48_COST = 1.14, W32_COST = 1.12;
 // The same for the FP32 tiles (a sweep of active widths 40 to 440 at
 // n = 4000).
 constexpr double W48_COST_F32 = 1.07, W32_COST_F32 = 1.08;
+// The 80-wide tile (4x1 waves, 16 x 80 each), FP64 and FP32: from sweeps of
+// widths 70 to 640 at n = 4000 and 10000 against every other width at its
+// best K split (16-20 % faster at 65-80 columns, 4 % at 400).
+constexpr double W80_COST = 1.06, W80_COST_F32 = 1.03;
 
 void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   const int batch = g.batch > 0 ? g.batch : 1;
@@ -740,7 +747,7 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   // panels of the workgroups resident on one XCD then fit its 4 MB L2), and
   // further where the tiles alone would leave the CUs short of work (FP32
   // steps are shorter and want about twice as many workgroups).  The tile
-  // width (64, 48 or 32 columns) that computes the fewest padded columns,
+  // width (80, 64, 48 or 32 columns) that computes the fewest padded columns,
   // each width's columns weighted by its measured cost relative to the
   // 64-wide tile's (per precision).
   if (nn && batch == 1 && g.M >= 1024 && g.K >= 1024 && !(g.flags & GEMM_OUT_LOWER)) {
@@ -748,10 +755,12 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
     const double pad64 = (double)(cdiv(g.N, (int64_t)64) * 64) / (double)g.N;
     const double pad32 = (double)(cdiv(g.N, (int64_t)32) * 32) / (double)g.N;
     const double pad48 = (double)(cdiv(g.N, (int64_t)48) * 48) / (double)g.N;
+    const double pad80 = (double)(cdiv(g.N, (int64_t)80) * 80) / (double)g.N;
     const double cost64 = pad64, cost48 = (f32 ? W48_COST_F32 : W48_COST) * pad48,
-                 cost32 = (f32 ? W32_COST_F32 : W32_COST) * pad32;
+                 cost32 = (f32 ? W32_COST_F32 : W32_COST) * pad32, cost80 = (f32 ? W80_COST_F32 : W80_COST) * pad80;
     // (FP64: the 64-wide tile with eight waves; FP32 keeps four)
     int c = cost64 <= cost48 && cost64 <= cost32 ? (f32 ? 1 : 11) : (cost48 <= cost32 ? 10 : 7);
+    if (cost80 < std::min(cost64, std::min(cost48, cost32))) c = 12;
     // (FP32 blocks of 97-128 columns: the 64 x 128 x 8 tile, one column tile)
     if (f32 && g.N > 96 && g.N <= 128) c = 5;
     int sk = g.K < 1500 ? 1 : g.K < 3000 ? 2 : g.K < 7000 ? 4 : 8;
@@ -797,9 +806,9 @@ void zgemm_choose(const GemmOp& g, int64_t P_elems, int& cfg, int& splitk) {
   cfg = 1;
   splitk = 1;
   const int cands_nn[] = {1, 2, 4, 5, 7};
-  const int cands_other[] = {1, 2, 7};
+  const int cands_other[] = {1, 2, 7, 11};
   const int* cands = nn ? cands_nn : cands_other;
-  const int ncand = nn ? 5 : 3;
+  const int ncand = nn ? 5 : 4;
   for (int ci = 0; ci < ncand; ci++) {
     const Cfg& c = CFGS[cands[ci]];
     const int64_t tiles = cdiv(g.M, c.bm) * cdiv(g.N, c.bn) * batch;

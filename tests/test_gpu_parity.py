@@ -95,6 +95,26 @@ def test_zgemm_against_definition(lib, opA, opB, M, N, K):
     assert _rel(_np(C), ref) <= 1e-13
 
 
+@pytest.mark.parametrize("opA,opB", [(0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("split", [1, 4])
+def test_zgemm_eight_wave_tile_with_conjugate_operands(lib, opA, opB, split):
+    """The eight-wave 64 x 64 tile (configuration 11) with conjugate-
+    transposed operands and the three-term epilogue, ragged over several
+    tiles, with and without a K split."""
+    rng = _rng(1400 + 2 * opA + opB + split)
+    M, N, K = 333, 141, 500
+    A = _cg(rng, (M, K) if opA == 0 else (K, M))
+    B = _cg(rng, (K, N) if opB == 0 else (N, K))
+    X, Z = _cg(rng, (M, N)), _cg(rng, (M, N))
+    ctx = lib.create(8)
+    C = _np(lib.zgemm(ctx, opA, opB, _t(A), _t(B), alpha=0.7, beta=-0.3, X=_t(X), gamma=1.9, Z=_t(Z),
+                      flags=(11 << 8) | (split << 16)))
+    opa = A if opA == 0 else A.conj().T
+    opb = B if opB == 0 else B.conj().T
+    ref = 0.7 * (opa @ opb) - 0.3 * X + 1.9 * Z
+    assert np.abs(C - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
 def test_zgemm_triangular_structure_flags(lib):
     rng = _rng(9)
     n = 150
@@ -113,7 +133,7 @@ def test_zgemm_triangular_structure_flags(lib):
 
 
 @pytest.mark.parametrize("flag", [1, 2, 16, 8 | 16])
-@pytest.mark.parametrize("tile,split", [(0, 0), (1, 4), (7, 1), (2, 8)])
+@pytest.mark.parametrize("tile,split", [(0, 0), (1, 4), (7, 1), (2, 8), (11, 1), (11, 4)])
 def test_zgemm_structured_products_many_tile_rows(lib, flag, tile, split):
     """Triangular op(A) (lower, upper), lower-only output, and upper op(B)
     with lower-only output over 18 tile rows (an odd count: the products
@@ -228,7 +248,7 @@ def test_filter_matches_oracle(lib, n, k, m):
     assert _rel(_np(Yt), ref) <= 1e-12
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 12])
 def test_filter_every_tile_shape_matches_oracle(lib, tile):
     """Every tile configuration of the filter step, those forming complex
     products with three real products (64 x 64 and smaller at two
@@ -289,7 +309,7 @@ def test_filter_fp32_against_oracle(lib, n, k, m):
     assert err >= 1e-9  # really computed in FP32
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 9, 10, 11])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 7, 9, 10, 11, 12])
 def test_filter_fp32_every_tile_shape(lib, tile):
     """The FP32 filter step in every tile shape (64x48 with 4x1 waves among
     them), with and without a K split, to FP32 accuracy against the FP64
@@ -324,6 +344,28 @@ def test_filter_fp32_tall_rule_takes_48_wide_tile(lib):
     lib.filter(ctx, _t(p.A), Yt, m, a, b, a0)
     err = _rel(_np(Yt), ref)
     assert 1e-9 <= err <= 2e-5, err
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_filter_tall_rule_takes_80_wide_tile(lib, prec):
+    """n = 1100, 70 columns: the tall-product rule takes the 80-wide tile
+    (one column tile, 12.5 % padding, against 37 % and more for the 64-, 48-
+    and 32-wide ones); the result agrees with the oracle (FP64: 1e-12;
+    FP32: FP32 accuracy)."""
+    n, k, m = 1100, 70, 5
+    p = workloads.make_problem(n, 23)
+    Y = _cg(_rng(24), (n, k))
+    lam = np.sort(p.lam)
+    a, b, a0 = float(lam[k]), float(lam[-1] * 1.05), float(lam[0])
+    ref = oracle.chebyshev_filter(p.A, Y, m, a, b, a0)
+    ctx = lib.create(n, precision=prec)
+    Yt = _t(Y)
+    lib.filter(ctx, _t(p.A), Yt, m, a, b, a0)
+    err = _rel(_np(Yt), ref)
+    if prec == 0:
+        assert err <= 1e-12, err
+    else:
+        assert 1e-9 <= err <= 2e-5, err
 
 
 def test_filter_closed_form_on_diagonal(lib):
@@ -517,8 +559,11 @@ def test_eigh_nearly_diagonal_matches_oracle(lib, k, eps):
     assert np.all(np.abs(ov[sep] - 1) <= 1e-9)
 
 
-@pytest.mark.parametrize("n", [200, 64, 333])
+@pytest.mark.parametrize("n", [200, 64, 333, 777, 1100])
 def test_reduce_matches_oracle(lib, n):
+    """L, L^{-1} and A = L^{-1} H L^{-H} against the oracle; n above 256
+    takes the two-level factorization (outer blocks of 256 columns, the last
+    one ragged; the inverse completed by doubling across outer blocks)."""
     p = workloads.make_problem(n, 5 + n)
     L_ref, bad = oracle.cholesky(p.S)
     assert bad == 0
@@ -537,15 +582,18 @@ def test_reduce_matches_oracle(lib, n):
     assert _rel(A2, 2 * A_ref) <= 1e-13
 
 
-def test_reduce_reports_not_positive_definite(lib):
-    p = workloads.make_problem(150, 3)
+@pytest.mark.parametrize("n,bad", [(150, 100), (600, 400)])
+def test_reduce_reports_not_positive_definite(lib, n, bad):
+    """The first pivot that is not positive is reported by its column, also
+    in a later outer block of the two-level factorization."""
+    p = workloads.make_problem(n, 3)
     S = p.S.copy()
-    S[100, 100] = -5.0
-    ctx = lib.create(150)
+    S[bad, bad] = -5.0
+    ctx = lib.create(n)
     with pytest.raises(lib.ChfsiError) as e:
         lib.reduce(ctx, _t(p.H), _t(S))
     assert e.value.status == -2
-    assert "column" in str(e.value)
+    assert f"column {bad} " in str(e.value)
 
 
 @pytest.mark.parametrize("n,steps", [(256, 10), (8, 8), (500, 30)])
