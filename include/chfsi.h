@@ -271,7 +271,7 @@ typedef struct {
   double filter_flops;        /* algorithmic filter flops of this call, 8 n^2 k_a per member and step */
   double filter_seconds;      /* device time of the grouped steps (events around each iteration's steps) */
   double seconds;             /* wall time of the call */
-  double tile_rate[8];        /* measured filter TFLOP/s per tile configuration (0: not tried; FP64) */
+  double tile_rate[16];       /* measured filter TFLOP/s per tile configuration (0: not tried; FP64) */
 } chfsi_batch_report;
 
 /* Create `count` (1..1024) member solvers of sizes n[0..count-1] on the

@@ -571,7 +571,7 @@ class Server:
 class BatchReport(ctypes.Structure):
     _fields_ = [("tile_config", c_i32), ("tile_config_fp32", c_i32), ("graph", c_i32), ("outer_iterations", c_i32),
                 ("grouped_launches", c_i32), ("converged_members", c_i32), ("filter_flops", c_dbl),
-                ("filter_seconds", c_dbl), ("seconds", c_dbl), ("tile_rate", c_dbl * 8)]
+                ("filter_seconds", c_dbl), ("seconds", c_dbl), ("tile_rate", c_dbl * 16)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "tile_rate"}

@@ -1639,8 +1639,9 @@ void for_members(int count, int threads, int device, F&& fn) {
   for (auto& x : th) x.join();
 }
 
-// Tile configurations the online choice tries, in order.
-constexpr int BATCH_CANDIDATES[] = {3, 4, 5, 1, 7};
+// Tile configurations the online choice tries, in order (11: the 64 x 64 x 16
+// tile with eight waves, FP32 with four; 12: 64 x 80 x 16).
+constexpr int BATCH_CANDIDATES[] = {3, 4, 5, 11, 7, 12};
 constexpr int BATCH_NCAND = sizeof(BATCH_CANDIDATES) / sizeof(BATCH_CANDIDATES[0]);
 
 }  // namespace
@@ -1668,8 +1669,8 @@ struct chfsi_batch_s {
   // measured rates
   int cfg[2] = {0, 0};
   int trial[2] = {0, 0};
-  double rate[2][8] = {};
-  int grid[2][8] = {};
+  double rate[2][16] = {};
+  int grid[2][16] = {};
   // captured degree steps per precision, for configuration gexec_cfg
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gexec_cfg[2] = {0, 0};
@@ -2045,7 +2046,7 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
   CHFSI_HIP(hipStreamSynchronize(b->gst));
   rep.tile_config = b->cfg[0] ? b->cfg[0] : 0;
   rep.tile_config_fp32 = b->cfg[1] ? b->cfg[1] : 0;
-  for (int q = 0; q < 8; q++) rep.tile_rate[q] = b->rate[0][q];
+  for (int q = 0; q < 16; q++) rep.tile_rate[q] = b->rate[0][q];
   rep.seconds = secs_since(t_start);
   if (report) *report = rep;
   if (first_bad >= 0)

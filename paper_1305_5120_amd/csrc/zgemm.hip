@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) chebyshev_step_f32(ZGemmParams 
 // stays valid while the active widths shrink.
 constexpr int GROUP_TILES = 16;
 
-template <class PT, int BM, int BN, int BK, int MINB>
+template <class PT, int BM, int BN, int BK, int MINB, int NW>
 __device__ __forceinline__ void grouped_body(const ZGemmParams* __restrict__ gp, const int64_t* __restrict__ tile0,
                                              int G, int* __restrict__ ctr) {
   __shared__ int64_t next;
@@ -454,23 +454,23 @@ __device__ __forceinline__ void grouped_body(const ZGemmParams* __restrict__ gp,
     const int64_t nt = w % p.tiles_n, rest = w / p.tiles_n;
     const int split = (int)(rest % p.splitk);
     const int64_t mt = rest / p.splitk;
-    zgemm_body<PT, OP_N, OP_N, BM, BN, BK, gauss3<PT, BM, BN, MINB>()>(p, mt * p.tiles_n + nt, 0, split);
+    zgemm_body<PT, OP_N, OP_N, BM, BN, BK, gauss3<PT, BM, BN, MINB>(), NW>(p, mt * p.tiles_n + nt, 0, split);
     __syncthreads();  // LDS of this tile fully consumed before the next one
   }
 }
 
-template <int BM, int BN, int BK, int MINB>
-__global__ void __launch_bounds__(256, MINB) chebyshev_step_grouped_f64(const ZGemmParams* __restrict__ gp,
+template <int BM, int BN, int BK, int MINB, int NW = 4>
+__global__ void __launch_bounds__(64 * NW, MINB) chebyshev_step_grouped_f64(const ZGemmParams* __restrict__ gp,
                                                                        const int64_t* __restrict__ tile0, int G,
                                                                        int* __restrict__ ctr) {
-  grouped_body<PF64, BM, BN, BK, MINB>(gp, tile0, G, ctr);
+  grouped_body<PF64, BM, BN, BK, MINB, NW>(gp, tile0, G, ctr);
 }
 
-template <int BM, int BN, int BK, int MINB>
-__global__ void __launch_bounds__(256, MINB) chebyshev_step_grouped_f32(const ZGemmParams* __restrict__ gp,
+template <int BM, int BN, int BK, int MINB, int NW = 4>
+__global__ void __launch_bounds__(64 * NW, MINB) chebyshev_step_grouped_f32(const ZGemmParams* __restrict__ gp,
                                                                        const int64_t* __restrict__ tile0, int G,
                                                                        int* __restrict__ ctr) {
-  grouped_body<PF32, BM, BN, BK, MINB>(gp, tile0, G, ctr);
+  grouped_body<PF32, BM, BN, BK, MINB, NW>(gp, tile0, G, ctr);
 }
 
 // Combine split-K partial tiles and apply the epilogue (element e of batch
@@ -640,23 +640,27 @@ void launch_ops(int cfg, int opA, int opB, ZGemmParams& p, int batch, bool filte
   else launch_cfg<OP_C, OP_C>(cfg, p, batch, filter_step, st);
 }
 
-template <int BM, int BN, int BK, int MINB>
+template <int BM, int BN, int BK, int MINB, int NW = 4>
 void launch_grouped(int prec, const ZGemmParams* gp, const int64_t* tile0, int G, int* ctr, int grid, hipStream_t st) {
   if (prec == PREC_F32)
-    hipLaunchKernelGGL((chebyshev_step_grouped_f32<BM, BN, BK, MINB>), dim3(grid), dim3(256), 0, st, gp, tile0, G, ctr);
+    hipLaunchKernelGGL((chebyshev_step_grouped_f32<BM, BN, BK, MINB, NW>), dim3(grid), dim3(64 * NW), 0, st, gp, tile0,
+                       G, ctr);
   else
-    hipLaunchKernelGGL((chebyshev_step_grouped_f64<BM, BN, BK, MINB>), dim3(grid), dim3(256), 0, st, gp, tile0, G, ctr);
+    hipLaunchKernelGGL((chebyshev_step_grouped_f64<BM, BN, BK, MINB, NW>), dim3(grid), dim3(64 * NW), 0, st, gp, tile0,
+                       G, ctr);
   CHFSI_CHECK_LAUNCH();
 }
 
 // Resident workgroups per CU of the grouped kernel.
-template <int BM, int BN, int BK, int MINB>
+template <int BM, int BN, int BK, int MINB, int NW = 4>
 int grouped_occupancy(int prec) {
   int nb = 0;
   if (prec == PREC_F32)
-    CHFSI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, chebyshev_step_grouped_f32<BM, BN, BK, MINB>, 256, 0));
+    CHFSI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, chebyshev_step_grouped_f32<BM, BN, BK, MINB, NW>,
+                                                           64 * NW, 0));
   else
-    CHFSI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, chebyshev_step_grouped_f64<BM, BN, BK, MINB>, 256, 0));
+    CHFSI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, chebyshev_step_grouped_f64<BM, BN, BK, MINB, NW>,
+                                                           64 * NW, 0));
   return nb;
 }
 
@@ -682,7 +686,9 @@ void zgemm_grouped_reduce(int prec, const ZGemmParams* gp, const int64_t* elem0,
 
 int zgemm_config_bk(int cfg) { return (cfg >= 1 && cfg < NCFG) ? CFGS[cfg].bk : 0; }
 
-bool zgemm_grouped_config_ok(int cfg) { return cfg == 1 || cfg == 2 || cfg == 3 || cfg == 4 || cfg == 5 || cfg == 7; }
+bool zgemm_grouped_config_ok(int cfg) {
+  return cfg == 1 || cfg == 2 || cfg == 3 || cfg == 4 || cfg == 5 || cfg == 7 || cfg == 11 || cfg == 12;
+}
 
 int zgemm_grouped_grid(int prec, int cfg) {
   int nb = 0;
@@ -693,6 +699,8 @@ int zgemm_grouped_grid(int prec, int cfg) {
     case 4: nb = grouped_occupancy<128, 64, 8, 2>(prec); break;
     case 5: nb = grouped_occupancy<64, 128, 8, 2>(prec); break;
     case 7: nb = grouped_occupancy<64, 32, 16, 2>(prec); break;
+    case 11: nb = grouped_occupancy<64, 64, 16, 2, 8>(prec); break;
+    case 12: nb = grouped_occupancy<64, 80, 16, 2>(prec); break;
     default: throw Error(ST_EINVAL, "grouped filter: bad tile configuration");
   }
   int dev = 0, cus = 0;
@@ -713,6 +721,8 @@ void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const i
     case 4: launch_grouped<128, 64, 8, 2>(prec, gp, tile0, G, ctr, grid, st); break;
     case 5: launch_grouped<64, 128, 8, 2>(prec, gp, tile0, G, ctr, grid, st); break;
     case 7: launch_grouped<64, 32, 16, 2>(prec, gp, tile0, G, ctr, grid, st); break;
+    case 11: launch_grouped<64, 64, 16, 2, 8>(prec, gp, tile0, G, ctr, grid, st); break;
+    case 12: launch_grouped<64, 80, 16, 2>(prec, gp, tile0, G, ctr, grid, st); break;
     default: throw Error(ST_EINVAL, "grouped filter: bad tile configuration");
   }
 }

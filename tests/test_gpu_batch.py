@@ -58,14 +58,15 @@ def test_batch_cold_members_match_oracle_and_spectrum(lib):
         _check(p, ev[i], _np(X[i]), nevs[i])
         assert infos[i]["converged"] >= nevs[i]
         assert infos[i]["filter_flops"] > 0
-    # online choice: five candidate shapes tried, the fastest kept, or a
+    # online choice: six candidate shapes tried, the fastest kept, or a
     # narrower one within 2 % of it
-    assert rep["outer_iterations"] >= 5
-    assert rep["tile_config"] in (1, 3, 4, 5, 7)
+    assert rep["outer_iterations"] >= 6
+    assert rep["tile_config"] in (3, 4, 5, 7, 11, 12)
     rates = rep["tile_rate"]
-    tried = [c for c in (1, 3, 4, 5, 7) if rates[c] > 0]
-    assert len(tried) == 5
-    width = {1: 64, 3: 64, 4: 64, 5: 128, 7: 32}
+    assert len(rates) == 16
+    tried = [c for c in (3, 4, 5, 7, 11, 12) if rates[c] > 0]
+    assert len(tried) == 6
+    width = {3: 64, 4: 64, 5: 128, 7: 32, 11: 64, 12: 80}
     top = max(tried, key=lambda c: rates[c])
     chosen = rep["tile_config"]
     assert chosen == top or (rates[chosen] >= 0.98 * rates[top] and width[chosen] < width[top])
@@ -76,16 +77,18 @@ def test_batch_cold_members_match_oracle_and_spectrum(lib):
     b.close()
 
 
-def test_batch_graph_replay_equals_eager_along_sequences(lib):
+@pytest.mark.parametrize("tile", [3, 11, 12])
+def test_batch_graph_replay_equals_eager_along_sequences(lib, tile):
     """Three sequences of three correlated problems each (S fixed, warm
-    starts).  With a pinned tile shape the captured graph and the eager
-    launches must produce identical bits at every step (each iteration
-    replays the graph with the members' own eager work in between)."""
+    starts).  With a pinned tile shape (64 x 64 x 8; 64 x 64 x 16 with eight
+    waves; 64 x 80 x 16) the captured graph and the eager launches must
+    produce identical bits at every step (each iteration replays the graph
+    with the members' own eager work in between)."""
     sizes = [260, 180, 300]
     seqs = [list(workloads.make_sequence(n, 3, 70 + i)) for i, n in enumerate(sizes)]
     out = {}
     for use_graph in (False, True):
-        b = lib.Batch(sizes, use_graph=use_graph, degree=10, seed=2, filter_tile=3)
+        b = lib.Batch(sizes, use_graph=use_graph, degree=10, seed=2, filter_tile=tile)
         res = []
         for ell in range(3):
             H = [_t(s[ell].H) for s in seqs]
@@ -95,7 +98,7 @@ def test_batch_graph_replay_equals_eager_along_sequences(lib):
             ev, X, infos, st, rep = b.solve(H, S, nev, nex, tol=1e-10)
             assert st == [0, 0, 0]
             assert rep["graph"] == (1 if use_graph else 0)
-            assert rep["tile_config"] == 3
+            assert rep["tile_config"] == tile
             for i in range(3):
                 assert infos[i]["warm_start"] == (1 if ell > 0 else 0)
                 _check(seqs[i][ell], ev[i], _np(X[i]), nev[i])
