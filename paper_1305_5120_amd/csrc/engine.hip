@@ -271,7 +271,7 @@ struct chfsi_ctx_s {
 
   void ensure_small() {
     norms.ensure(8 * sizeof(double));
-    rfc.ensure(sizeof(unsigned long long));
+    rfc.ensure(4 * sizeof(unsigned long long));
     flags.ensure(8 * sizeof(int));
     const int steps = std::max(1, opts.lanczos_steps);
     LV.ensure((size_t)n * (steps + 1) * sizeof(zc));
@@ -589,6 +589,8 @@ struct chfsi_ctx_s {
   // (e.g. 0.2, 9e-3, 7e-4, 1e-6, 1e-13), so after a step whose largest
   // correction is below DONE the remaining error is at rounding level.
   static constexpr double REF_ETA = 0.25;
+  static constexpr int REF_SPECULATE = 2;  // steps issued before the first read (see refine)
+  bool refine_ok_last = false;             // the last first attempt of refine succeeded
   static constexpr int64_t SMALL_REFINE_MIN = 24;
   bool refine(const zc* Gm, const zc* Zpre, int64_t k, double* w, zc* Zo, int64_t ldz, double tau) {
     const double ETA = REF_ETA, GROW = 0.5, DONE = 1e-8;
@@ -601,23 +603,59 @@ struct chfsi_ctx_s {
     zc* Pb = Sb + kk;
     zc* Eb = Pb + kk;
     double* lam = rfl.d();
-    // step s accumulates its largest correction in slot s % 2 and clears the
-    // other slot for step s + 1 (in stream order; the host reads the slot of
-    // the last step of a run of steps)
+    // step 0 puts its largest correction in slot 2; step s >= 1 accumulates
+    // in slot s % 2 and clears the other slot for step s + 1 (in stream
+    // order; the host reads the slot of the last step of a run of steps)
     auto* corr = static_cast<unsigned long long*>(rfc.p);
     auto read_corr = [&](int step) {
-      CHFSI_HIP(hipMemcpyAsync(hbuf, corr + (step & 1), sizeof(double), hipMemcpyDeviceToHost, st));
+      CHFSI_HIP(hipMemcpyAsync(hbuf, corr + (step == 0 ? 2 : (step & 1)), sizeof(double), hipMemcpyDeviceToHost, st));
       sync();
       double c;
       std::memcpy(&c, hbuf, sizeof(double));
       return c;
     };
+    auto run_step = [&](int step) {
+      gemm(OP_N, OP_N, k, k, k, 1.0, Gm, k, X, k, Wb, k);
+      gemm(OP_C, OP_N, k, k, k, 1.0, X, k, Wb, k, Sb, k);
+      gemm(OP_C, OP_N, k, k, k, 1.0, X, k, X, k, Pb, k);
+      refine_coeffs(Sb, Pb, k, tau, Eb, nullptr, lam, corr + (step & 1), corr + ((step + 1) & 1), st);
+      gemm(OP_N, OP_N, k, k, k, 1.0, X, k, Eb, k, Xn, k, 1.0, X, k);  // X + X E
+      std::swap(X, Xn);
+    };
     // step 0: X = I, S = Gm, P = I
-    CHFSI_HIP(hipMemsetAsync(corr, 0, sizeof(unsigned long long), st));
-    refine_coeffs(Gm, nullptr, k, tau, Eb, X, lam, corr, corr + 1, st);
-    double c = read_corr(0);
-    if (!(c <= ETA)) return false;
+    CHFSI_HIP(hipMemsetAsync(corr + 2, 0, sizeof(unsigned long long), st));
+    refine_coeffs(Gm, nullptr, k, tau, Eb, X, lam, corr + 2, corr + 1, st);
     int step = 1;
+    double c;
+    // a first attempt after the context's previous one succeeded (the
+    // projected matrices of consecutive iterations are alike): the usual
+    // first steps run before the first read, which then checks step 0's
+    // correction against ETA and the last one against GROW in one wait
+    const bool speculate = !Zpre && refine_ok_last;
+    if (speculate) {
+      for (int i = 0; i < REF_SPECULATE; i++, step++) run_step(step);
+      CHFSI_HIP(hipMemcpyAsync(hbuf, corr + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      CHFSI_HIP(hipMemcpyAsync(hbuf + 1, corr + ((step - 1) & 1), sizeof(double), hipMemcpyDeviceToHost, st));
+      sync();
+      double c0;
+      std::memcpy(&c0, hbuf, sizeof(double));
+      std::memcpy(&c, hbuf + 1, sizeof(double));
+      if (!(c0 <= ETA) || !(c <= GROW)) {
+        refine_ok_last = false;
+        return false;
+      }
+    } else {
+      c = read_corr(0);
+      if (!(c <= ETA)) {
+        if (!Zpre) refine_ok_last = false;
+        return false;
+      }
+    }
+    // a first attempt records its outcome for the next one
+    auto fail = [&]() {
+      if (!Zpre) refine_ok_last = false;
+      return false;
+    };
     while (!(c < DONE)) {
       // the steps that quadratic convergence (c' <= 8 c^2; measured factors
       // 0.2-9) needs to bring the correction below DONE, at most 4, are
@@ -626,17 +664,13 @@ struct chfsi_ctx_s {
       int ahead = 0;
       for (double cp = c; ahead < 4 && (ahead == 0 || !(cp < DONE)); ahead++) cp = 8.0 * cp * cp;
       for (int i = 0; i < ahead; i++, step++) {
-        if (step > MAX_STEPS) return false;
-        gemm(OP_N, OP_N, k, k, k, 1.0, Gm, k, X, k, Wb, k);
-        gemm(OP_C, OP_N, k, k, k, 1.0, X, k, Wb, k, Sb, k);
-        gemm(OP_C, OP_N, k, k, k, 1.0, X, k, X, k, Pb, k);
-        refine_coeffs(Sb, Pb, k, tau, Eb, nullptr, lam, corr + (step & 1), corr + ((step + 1) & 1), st);
-        gemm(OP_N, OP_N, k, k, k, 1.0, X, k, Eb, k, Xn, k, 1.0, X, k);  // X + X E
-        std::swap(X, Xn);
+        if (step > MAX_STEPS) return fail();
+        run_step(step);
       }
       c = read_corr(step - 1);
-      if (!(c <= GROW)) return false;
+      if (!(c <= GROW)) return fail();
     }
+    if (!Zpre) refine_ok_last = true;
     const zc* Zf = X;
     if (Zpre) {
       gemm(OP_N, OP_N, k, k, k, 1.0, Zpre, k, X, k, Wb, k);
@@ -1029,6 +1063,9 @@ double secs_since(std::chrono::steady_clock::time_point a) {
 void solve_begin(chfsi_ctx c, SolveState& s) {
   const int64_t n = c->n;
   s.k = s.nev + s.nex;
+  // the refinement's speculation starts afresh, so that a solve's steps (and
+  // bits) do not depend on what the context solved before
+  c->refine_ok_last = false;
   const int64_t k = s.k;
   if (!block_sizes_ok(n, s.nev, s.nex)) throw Error(ST_EINVAL, BLOCK_SIZES_RULE);
   if (!(s.tol > 0.0)) throw Error(ST_EINVAL, "tol must be positive");
@@ -2287,6 +2324,7 @@ chfsi_status chfsi_eigh(chfsi_ctx c, const void* G, int64_t ldg, int64_t k, doub
     if (k > c->n) throw Error(ST_EINVAL, "eigh: k > n of the context");
     c->ensure_small();
     c->ensure_k(k);
+    c->refine_ok_last = false;  // no speculation across separate calls
     c->eigh((const zc*)G, ldg, k, c->mu.d(), (zc*)Z, ldz);
     c->ensure_host((size_t)k + 16);
     CHFSI_HIP(hipMemcpyAsync(c->hbuf, c->mu.p, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -2306,6 +2344,7 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_ctx c, const void* A, int64_t lda, void* 
     c->ensure_small();
     c->ensure_k(k);
     copy2d((zc*)Y, ldy, c->Qb.z(), c->n, c->n, k, c->st);
+    c->refine_ok_last = false;  // no speculation across separate calls
     c->rayleigh_ritz((const zc*)A, lda, c->Qb.z(), c->n, k, (zc*)Y, ldy, c->mu.d(), c->Wk.z(), nullptr);
     CHFSI_HIP(hipMemcpyAsync(c->hbuf, c->mu.p, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
     c->sync();
