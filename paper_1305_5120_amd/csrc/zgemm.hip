@@ -209,13 +209,19 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
     }
   };
 
+  // eight-wave FP64 tiles issue the global loads of slab s + 2 right after
+  // storing slab s + 1 (mid-slab, see below) instead of at the start of
+  // slab s + 1: the loads get one and a half slabs to arrive (0.5-0.8 % at
+  // widths 256-660, none at narrower four-wave tiles)
+  constexpr bool EARLY = sizeof(E) == 16 && T::KS > 1 && NW == 8;
   if (nslab > 0) {
     load_slab(kbeg);
     store_slab(0);
     __syncthreads();
+    if (EARLY && nslab > 1) load_slab(kbeg + BK);
     for (int64_t s = 0; s < nslab; s++) {
       const int buf = (int)(s & 1);
-      if (s + 1 < nslab) load_slab(kbeg + (s + 1) * BK);
+      if (!EARLY && s + 1 < nslab) load_slab(kbeg + (s + 1) * BK);
       // fragments of depth step 0; the next step's are read while the
       // current step's products run
       E a[2][T::MI], b[2][T::NJ];
@@ -300,6 +306,7 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
         // (earlier was 2-4 % slower there)
         constexpr int STORE_AT = sizeof(E) == 16 && T::KS > 1 ? 1 : T::KS - 1;
         if (ks == STORE_AT && s + 1 < nslab) store_slab(buf ^ 1);
+        if (EARLY && ks == STORE_AT && s + 2 < nslab) load_slab(kbeg + (s + 2) * BK);
       }
       __syncthreads();
     }
