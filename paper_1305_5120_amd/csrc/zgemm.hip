@@ -210,8 +210,8 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
   };
 
   // eight-wave FP64 tiles issue the global loads of slab s + 2 right after
-  // storing slab s + 1 (mid-slab, see below) instead of at the start of
-  // slab s + 1: the loads get one and a half slabs to arrive (0.5-0.8 % at
+  // storing slab s + 1 (early in slab s, see below) instead of at the start
+  // of slab s + 1: the loads get more than a slab to arrive (0.5-0.8 % at
   // widths 256-660, none at narrower four-wave tiles)
   constexpr bool EARLY = sizeof(E) == 16 && T::KS > 1 && NW == 8;
   if (nslab > 0) {
@@ -302,9 +302,10 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
         // the next slab into the other LDS buffer (its last reads were in
         // the previous slab, before the last barrier): FP64 after the second
         // depth step, so that its stores are done before the barrier instead
-        // of leading up to it (1-1.5 % per step); FP32 after the last step
-        // (earlier was 2-4 % slower there)
-        constexpr int STORE_AT = sizeof(E) == 16 && T::KS > 1 ? 1 : T::KS - 1;
+        // of leading up to it (1-1.5 % per step), the eight-wave tile, whose
+        // loads were issued a slab earlier, after the first (another
+        // 0.7 %); FP32 after the last step (earlier was 2-4 % slower there)
+        constexpr int STORE_AT = sizeof(E) == 16 && T::KS > 1 ? (NW == 8 ? 0 : 1) : T::KS - 1;
         if (ks == STORE_AT && s + 1 < nslab) store_slab(buf ^ 1);
         if (EARLY && ks == STORE_AT && s + 2 < nslab) load_slab(kbeg + (s + 2) * BK);
       }
