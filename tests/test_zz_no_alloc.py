@@ -41,6 +41,7 @@ def _zeros(M, N):
 EXPLICIT = [
     [(0, 0, 1000, 300, 3000, 1, 4, 0), (1, 0, 500, 130, 1500, 7, 2, 0)],
     [(0, 1, 900, 900, 700, 2, 4, 16), (0, 0, 333, 77, 1200, 3, 3, 0)],
+    [(0, 0, 1100, 150, 2500, 12, 4, 0), (1, 0, 600, 200, 1800, 11, 2, 0)],
 ]
 
 
