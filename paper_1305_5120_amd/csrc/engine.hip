@@ -1055,6 +1055,8 @@ struct SolveState {
 // accepted pairs meet the same tolerance.
 constexpr double MIXED_SWITCH = 1e-6;
 constexpr int64_t MIXED_MIN_COLS = 64;
+// Lockable columns whose residuals an FP64 iteration forms first.
+constexpr int64_t RESID_FIRST = 64;
 
 double secs_since(std::chrono::steady_clock::time_point a) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
@@ -1253,11 +1255,17 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   // extra columns never do); mixed precision reads every active column's
   // residual for its precision rules
   const int64_t kr = s.mixed ? ka : std::min(ka, s.nev - cl);
-  c->residual_norms(c->L.z(), n, c->Wz.z(), Y + cl * n, n, kr, mu_d, c->Wk.z(), F, rho_d);
+  // FP64: the residuals of the first RESID_FIRST of those columns, and of
+  // the rest only when all of these lock (the lock takes a contiguous
+  // prefix, so no column after the first one above the tolerance can lock
+  // this iteration; until the first columns converge, most of the
+  // triangular product L R is skipped)
+  const int64_t kr1 = s.mixed ? kr : std::min(kr, RESID_FIRST);
+  c->residual_norms(c->L.z(), n, c->Wz.z(), Y + cl * n, n, kr1, mu_d, c->Wk.z(), F, rho_d);
   s.wz_first = cl;  // Wz = A Y(:, cl:k) until the next Rayleigh-Ritz step
   double* hb = c->hbuf;
   CHFSI_HIP(hipMemcpyAsync(hb, mu_d, ka * sizeof(double), hipMemcpyDeviceToHost, st));
-  CHFSI_HIP(hipMemcpyAsync(hb + ka, rho_d, kr * sizeof(double), hipMemcpyDeviceToHost, st));
+  CHFSI_HIP(hipMemcpyAsync(hb + ka, rho_d, kr1 * sizeof(double), hipMemcpyDeviceToHost, st));
   CHFSI_HIP(hipEventRecord(s.ev[4], st));
   c->sync();
   float ms[4];
@@ -1270,14 +1278,27 @@ void solve_post(chfsi_ctx c, SolveState& s) {
   const double* mu = hb;
   double* rho = hb + ka;
   for (int64_t j = 0; j < ka; j++)
-    if (!std::isfinite(mu[j]) || (j < kr && !std::isfinite(rho[j])))
+    if (!std::isfinite(mu[j]) || (j < kr1 && !std::isfinite(rho[j])))
       throw Error(ST_ENAN, "non-finite Ritz value or residual at iteration " + std::to_string(s.it));
-  for (int64_t j = kr; j < ka; j++) rho[j] = INFINITY;  // not formed
+  for (int64_t j = kr1; j < ka; j++) rho[j] = INFINITY;  // not formed
   int64_t nl = 0;
-  while (cl + nl < s.nev && nl < ka && rho[nl] <= s.hs) {
-    s.lam[cl + nl] = mu[nl];
-    s.rho_lock[cl + nl] = rho[nl];
-    nl++;
+  while (cl + nl < s.nev && nl < ka && rho[nl] <= s.hs) nl++;
+  if (nl == kr1 && kr1 < kr) {
+    // every column of the first part locks: the residuals of the rest
+    const auto t1 = std::chrono::steady_clock::now();
+    c->residual_norms(c->L.z(), n, c->Wz.z() + kr1 * n, Y + (cl + kr1) * n, n, kr - kr1, mu_d + kr1, c->Wk.z(), F,
+                      rho_d + kr1);
+    CHFSI_HIP(hipMemcpyAsync(rho + kr1, rho_d + kr1, (kr - kr1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    c->sync();
+    inf.t_resid += secs_since(t1);
+    for (int64_t j = kr1; j < kr; j++)
+      if (!std::isfinite(rho[j]))
+        throw Error(ST_ENAN, "non-finite residual at iteration " + std::to_string(s.it));
+    while (cl + nl < s.nev && nl < ka && rho[nl] <= s.hs) nl++;
+  }
+  for (int64_t j = 0; j < nl; j++) {
+    s.lam[cl + j] = mu[j];
+    s.rho_lock[cl + j] = rho[j];
   }
   for (int64_t j = nl; j < ka; j++) {
     s.lam[cl + j] = mu[j];
