@@ -8,9 +8,10 @@ the matrices already resident in device memory.
 Default workload: a single complex Hermitian DGEVP with n = 10000,
 nev = 600, nex = 60, Chebyshev degree 20, tol 1e-10, solved cold (random
 start block) at every step, FP64 throughout (`value`); the same problem is
-then solved with the mixed-precision filter (complex FP32 degree steps, FP64
-everything else and FP64 final sweeps), reported beside it with the error of
-every eigenpair against the constructed spectrum and the FP64 path.  The
+then solved with the two mixed-precision filters (complex FP32 degree steps,
+FP64 everything else and FP64 final sweeps; and every degree step in complex
+FP32 on the Ritz residual, no FP64 sweeps), reported beside it with the error
+of every eigenpair against the constructed spectrum and the FP64 path.  The
 inputs are synthetic FLAPW-shaped problems (the paper's FLEUR matrices are
 not available).  Prints one JSON line.  `--workload seq4000` runs the
 correlated n = 4000 sequence (warm starts) instead.
@@ -725,15 +726,17 @@ def run_warmcold(args):
     print(json.dumps(out), flush=True)
 
 
-def run_mixed_same_workload(args, cfg, probs, fp64_rate):
+def run_mixed_same_workload(args, cfg, probs, fp64_rate, precision=1):
     """After the FP64 timed region: the same problems, in the same order and
-    with the same warm starts, solved with the mixed-precision filter (complex
-    FP32 degree steps for columns whose residual is above the switch, FP64
-    final sweeps to the same tolerance), timed the same way."""
+    with the same warm starts, solved with a mixed-precision filter, timed
+    the same way.  precision 1: complex FP32 degree steps for columns whose
+    residual is above the switch, FP64 final sweeps to the same tolerance;
+    precision 2: every degree step in complex FP32 on the Ritz residual (the
+    recurrence split by linearity), no FP64 sweeps, the same tolerance."""
     import torch
     from paper_1305_5120_amd import chfsi
     n, nev, nex = cfg["n"], cfg["nev"], cfg["nex"]
-    ctx = chfsi.create(n, degree=cfg["degree"], seed=0, precision=1, profile=0 if args.no_profile else 1)
+    ctx = chfsi.create(n, degree=cfg["degree"], seed=0, precision=precision, profile=0 if args.no_profile else 1)
     S0 = probs[0]["S"]
     # a bounded pass: the timed FP64 region above is the benchmark's value
     warmup = min(args.warmup, 1)
@@ -763,7 +766,7 @@ def run_mixed_same_workload(args, cfg, probs, fp64_rate):
     f32s = sum(i["filter_kernel_seconds_fp32"] for i in infos)
     f32f = sum(i["filter_flops_fp32"] for i in infos)
     rate = steps / elapsed
-    log(f"[bench] mixed precision, same problems: {rate:.3f} solves/s ({rate / fp64_rate:.2f}x FP64), "
+    log(f"[bench] precision {precision}, same problems: {rate:.3f} solves/s ({rate / fp64_rate:.2f}x FP64), "
         f"iterations {[i['iterations'] for i in infos]}, residual {rel_res:.2e}")
     f64s = sum(i["filter_kernel_seconds"] for i in infos) - f32s
     f64f = sum(i["filter_flops"] for i in infos) - f32f
@@ -780,9 +783,10 @@ def run_mixed_same_workload(args, cfg, probs, fp64_rate):
             "phase_seconds_per_solve": phase}
 
 
-def _eig_report(lam_exact, ev64, ev_mixed, anorm):
+def _eig_report(lam_exact, ev64, others, anorm):
     """Per-eigenpair errors (3 significant digits) relative to ||A||_2: FP64
-    and mixed against the constructed spectrum, mixed against FP64."""
+    and each mixed form (others: name -> eigenvalues) against the constructed
+    spectrum, each mixed form against FP64."""
     import numpy as np
     ex = np.sort(np.asarray(lam_exact))[:len(ev64)]
 
@@ -790,12 +794,16 @@ def _eig_report(lam_exact, ev64, ev_mixed, anorm):
         return [float(f"{x:.3g}") for x in np.asarray(d)]
 
     d64 = np.abs(np.asarray(ev64) - ex) / anorm
-    dmx = np.abs(np.asarray(ev_mixed) - ex) / anorm
-    dmf = np.abs(np.asarray(ev_mixed) - np.asarray(ev64)) / anorm
-    return {"norm": "|dlambda_i| / ||A||_2, i = 1..nev ascending",
-            "max": {"fp64_vs_exact": float(d64.max()), "mixed_vs_exact": float(dmx.max()),
-                    "mixed_vs_fp64": float(dmf.max())},
-            "fp64_vs_exact": vec(d64), "mixed_vs_exact": vec(dmx), "mixed_vs_fp64": vec(dmf)}
+    out = {"norm": "|dlambda_i| / ||A||_2, i = 1..nev ascending", "max": {"fp64_vs_exact": float(d64.max())},
+           "fp64_vs_exact": vec(d64)}
+    for name, ev in others.items():
+        dx = np.abs(np.asarray(ev) - ex) / anorm
+        df = np.abs(np.asarray(ev) - np.asarray(ev64)) / anorm
+        out["max"][f"{name}_vs_exact"] = float(dx.max())
+        out["max"][f"{name}_vs_fp64"] = float(df.max())
+        out[f"{name}_vs_exact"] = vec(dx)
+        out[f"{name}_vs_fp64"] = vec(df)
+    return out
 
 
 def main():
@@ -948,12 +956,15 @@ def main():
                      "algorithmic_flops_per_launch": flops / launches if launches else None},
     }
     if not args.no_mixed:
-        mixed = run_mixed_same_workload(args, cfg, probs, out["value"])
+        mixed = run_mixed_same_workload(args, cfg, probs, out["value"], precision=1)
         ev_mixed = mixed.pop("evals")
         out["mixed_precision"] = mixed
+        ritz = run_mixed_same_workload(args, cfg, probs, out["value"], precision=2)
+        ev_ritz = ritz.pop("evals")
+        out["mixed_precision_ritz"] = ritz
         if not cfg["sequence"]:
             anorm = float(abs(probs[0]["lam"]).max())
-            out["eigenpair_errors"] = _eig_report(probs[0]["lam"], ev64, ev_mixed, anorm)
+            out["eigenpair_errors"] = _eig_report(probs[0]["lam"], ev64, {"mixed": ev_mixed, "ritz32": ev_ritz}, anorm)
     if args.calibrate_copy:
         calibrate_copy()
     if not args.no_cpu_baseline:

@@ -62,7 +62,15 @@ typedef struct {
                             (FP32 matrix cores, FP32 accumulation) for the active columns after the
                             leading ones whose generalized residuals are below the switch (see
                             mixed_switch_digits), FP64 for those, for everything else and for the
-                            final sweeps; accepted pairs meet the same FP64 tolerance */
+                            final sweeps; accepted pairs meet the same FP64 tolerance;
+                            2: every filter product in complex FP32 on the Ritz residual: the
+                            recurrence of eq. (2) is linear, so with Y_0 the Ritz vectors of the last
+                            Rayleigh-Ritz step (values mu, residual R = A Y_0 - Y_0 diag(mu) in FP64)
+                            its iterates are Y_0 diag(t_i(mu)) + D_i, t_i the scalar recurrence (FP64)
+                            and D_i the recurrence on R (FP32 products, errors relative to |D|, which
+                            falls with the residual): no FP64 filter sweeps, the same FP64 tolerance;
+                            the first iteration after a start block that is not a Ritz basis runs the
+                            plain FP32 filter; not accepted by chfsi_batch_create */
   uint64_t seed;         /* Philox4x32-10 seed of the random start vectors (default 0) */
   int32_t profile;       /* 1: time the filter with device events (one pair around each filter call's degree steps) */
   int32_t qr_mode;       /* re-orthonormalization: 0 = CholeskyQR2, Householder when a Gram
@@ -90,7 +98,7 @@ typedef struct {
   double h_H;              /* Lanczos estimate of ||H||_2 (lower bound); scale of the lock test */
   double a0, a;            /* filter scale point and lower end of the damped interval at exit */
   double max_rel_residual; /* max_j ||H x_j - lambda_j S x_j||_2 / h_H over returned pairs */
-  int32_t iterations_fp32;      /* outer iterations whose filter ran in FP32 (precision = 1) */
+  int32_t iterations_fp32;      /* outer iterations whose filter ran in FP32 (precision 1 or 2) */
   int32_t filter_launches_fp32; /* of filter_launches, those in FP32 */
   double filter_flops_fp32;     /* of filter_flops, the FP32 part */
   double filter_kernel_seconds_fp32; /* of filter_kernel_seconds, the FP32 part */
@@ -157,10 +165,24 @@ chfsi_status chfsi_copy_factors(chfsi_ctx ctx, void* A, int64_t lda, void* L, in
 /* Chebyshev filter (eq. (2), scaled and shifted): Y (device n x k) is
  * overwritten with p(A) Y, p(t) = C_m((t - c)/e) / C_m((a0 - c)/e),
  * c = (a + b)/2, e = (b - a)/2.  Requires b > a, m >= 1.  With the context's
- * precision = 1 the recurrence runs in complex FP32 (A and Y rounded to FP32,
- * the result widened back to FP64). */
+ * precision 1 or 2 the recurrence runs in complex FP32 (A and Y rounded to
+ * FP32, the result widened back to FP64; Y carries no Ritz values here, so
+ * precision 2 filters like 1). */
 chfsi_status chfsi_filter(chfsi_ctx ctx, const void* A, int64_t lda, void* Y, int64_t ldy, int64_t k, int32_t m, double a,
                           double b, double a0);
+
+/* The same filter as the solver's precision 2 computes it (eq. (2) split by
+ * linearity): Y (device n x k) holds Ritz vectors of A with Ritz values mu
+ * (host, k FP64 values) and AY = A Y (device n x k, FP64, leading dimension
+ * lday).  Y is overwritten with p(A) Y = Y diag(t_m(mu)) + D_m, where t_i is
+ * the filter's recurrence on the scalars mu_j (FP64) and D_i the recurrence
+ * on the Ritz residual A Y - Y diag(mu) (D_0 = 0), its products in complex
+ * FP32 (A rounded to FP32).  Exact for any mu in exact arithmetic; the FP32
+ * rounding errors are relative to |D|, so they shrink as the residual does.
+ * Requires b > a, m >= 1, 1 <= k <= n; the context need not have
+ * precision 2. */
+chfsi_status chfsi_filter_ritz(chfsi_ctx ctx, const void* A, int64_t lda, void* Y, int64_t ldy, const void* AY,
+                               int64_t lday, const double* mu, int64_t k, int32_t m, double a, double b, double a0);
 
 /* Householder QR: Y (device n x k, k <= n) is overwritten with the explicit
  * orthonormal factor Q; R has a real diagonal with the sign opposite to the

@@ -76,6 +76,8 @@ def load():
                               ctypes.POINTER(Info)]
     L.chfsi_copy_factors.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64]
     L.chfsi_filter.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_i32, c_dbl, c_dbl, c_dbl]
+    L.chfsi_filter_ritz.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_i32, c_dbl, c_dbl,
+                                    c_dbl]
     L.chfsi_qr.argtypes = [c_vp, c_vp, c_i64, c_i64]
     L.chfsi_orthonormalize.argtypes = [c_vp, c_vp, c_i64, c_i64, ctypes.POINTER(c_i32)]
     L.chfsi_eigh.argtypes = [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64]
@@ -89,6 +91,7 @@ def load():
     L.chfsi_zgemm_static.argtypes = [c_vp, c_i32, c_i32, c_i64, c_i64, c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_dbl,
                                      c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp, c_i64, c_i32]
     for name in ("chfsi_create", "chfsi_reset", "chfsi_reduce", "chfsi_solve", "chfsi_copy_factors", "chfsi_filter",
+                 "chfsi_filter_ritz",
                  "chfsi_qr", "chfsi_orthonormalize", "chfsi_eigh", "chfsi_rayleigh_ritz", "chfsi_residuals", "chfsi_lanczos",
                  "chfsi_random_block", "chfsi_philox", "chfsi_zgemm", "chfsi_zgemm_static"):
         getattr(L, name).restype = ctypes.c_int
@@ -264,6 +267,29 @@ def filter(ctx, A, Y, m, a, b, a0):
     Yc, ldy = colmajor(Y)
     ctx._raise(ctx.lib.chfsi_filter(ctx.h, Ac.data_ptr(), lda, Yc.data_ptr(), ldy, Y.shape[1], int(m), float(a),
                                     float(b), float(a0)))
+    if Yc.data_ptr() != Y.data_ptr():
+        Y.copy_(Yc)
+    return Y
+
+
+def filter_ritz(ctx, A, Y, AY, mu, m, a, b, a0):
+    """Y <- p(A) Y in place, Y holding Ritz vectors of A with values mu
+    (host array) and AY = A Y: the FP32 filter on the Ritz residual."""
+    _check_dev(A, "A")
+    _check_dev(Y, "Y")
+    _check_dev(AY, "AY")
+    k = Y.shape[1]
+    _check_shape(A, ctx.n, ctx.n, "A")
+    _check_shape(Y, ctx.n, k, "Y")
+    _check_shape(AY, ctx.n, k, "AY")
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    if mu.shape != (k,):
+        raise ValueError(f"mu must hold {k} values, got shape {mu.shape}")
+    Ac, lda = colmajor(A)
+    Yc, ldy = colmajor(Y)
+    AYc, lday = colmajor(AY)
+    ctx._raise(ctx.lib.chfsi_filter_ritz(ctx.h, Ac.data_ptr(), lda, Yc.data_ptr(), ldy, AYc.data_ptr(), lday,
+                                         mu.ctypes.data_as(c_vp), k, int(m), float(a), float(b), float(a0)))
     if Yc.data_ptr() != Y.data_ptr():
         Y.copy_(Yc)
     return Y

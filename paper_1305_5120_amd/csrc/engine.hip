@@ -135,8 +135,9 @@ struct chfsi_ctx_s {
 
   // n x n: standard form, Cholesky factor, its inverse, work; FP32 copy of A
   DBuf A, L, Linv, W, A32;
-  // FP32 filter blocks (mixed precision)
-  DBuf Y32, Y32b;
+  // FP32 filter blocks (mixed precision); the FP32 filter on the Ritz
+  // residual: its forcing R (n x k, FP32) and the scalar recurrence's table
+  DBuf Y32, Y32b, R32, ctab;
   bool have_factors = false;
   // n x k blocks
   DBuf Y, Yb, F, Qb, Wk, Wz;
@@ -157,6 +158,8 @@ struct chfsi_ctx_s {
   // host staging (pinned)
   double* hbuf = nullptr;
   size_t hbuf_elems = 0;
+  double* htab = nullptr;  // the Ritz-residual filter's table on its way up
+  size_t htab_elems = 0;
 
   // warm state (Y holds the block)
   bool warm_valid = false;
@@ -199,6 +202,18 @@ struct chfsi_ctx_s {
     hbuf_elems = 0;
     CHFSI_HIP(hipHostMalloc((void**)&hbuf, elems * sizeof(double), hipHostMallocDefault));
     hbuf_elems = elems;
+  }
+
+  void ensure_htab(size_t elems) {
+    if (htab_elems >= elems) return;
+    if (htab) {
+      CHFSI_HIP(hipStreamSynchronize(st));
+      (void)hipHostFree(htab);
+    }
+    htab = nullptr;
+    htab_elems = 0;
+    CHFSI_HIP(hipHostMalloc((void**)&htab, elems * sizeof(double), hipHostMallocDefault));
+    htab_elems = elems;
   }
 
   void ensure_nn() {
@@ -290,12 +305,15 @@ struct chfsi_ctx_s {
   void sync() { CHFSI_HIP(hipStreamSynchronize(st)); }
 
   void free_all() {
-    for (DBuf* b : {&A32, &Y32, &Y32b, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
+    for (DBuf* b : {&A32, &Y32, &Y32b, &R32, &ctab, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
                     &flags, &P, &hpart, &htop, &tau, &Tall, &gram, &Vp, &Wt, &W2, &LV, &Lw, &Lh, &Lab, &mvpart, &Tsm,
                     &Tz, &Tz2, &Tw, &npart, &jint, &jrot, &bjv, &rf, &rfl, &rfc})
       b->release();
     if (hbuf) (void)hipHostFree(hbuf);
     hbuf = nullptr;
+    if (htab) (void)hipHostFree(htab);
+    htab = nullptr;
+    htab_elems = 0;
     for (auto& v : fev) {
       for (auto& e : v) {
         if (e.a) (void)hipEventDestroy(e.a);
@@ -876,6 +894,77 @@ struct chfsi_ctx_s {
     return cur;
   }
 
+  // The filter of Y_0 (n x ka, FP64 Ritz vectors of A with Ritz values mu,
+  // AY0 = A Y_0 in FP64) with its matrix products in complex FP32, result F
+  // (FP64).  The recurrence of eq. (2) is linear, so its iterates split as
+  // Y_i = Y_0 diag(t_i(mu)) + D_i, with t_i the same recurrence on the
+  // scalars mu_j (FP64, on the host) and D_i the recurrence on the Ritz
+  // residual R = A Y_0 - Y_0 diag(mu):
+  //   D_0 = 0, D_1 = alpha_0 R,
+  //   D_{i+1} = alpha_i A D_i + beta_i D_i + gamma_i D_{i-1} + alpha_i t_i(mu) R.
+  // Only D runs in FP32 (A rounded to FP32 in A32); its rounding errors are
+  // relative to |D|, which shrinks with the residual, so the filtered block
+  // keeps FP64 accuracy where Y_0 has converged (the plain FP32 filter's
+  // errors are relative to |Y_i| and stop convergence near 1e-7 ||A||).
+  // mu_d (device) and mu_h (host) hold the same ka values.
+  void filter_ritz32(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu_d, const double* mu_h,
+                     int64_t ka, int m, double a, double b, double a0, zc* F, int64_t ldf) {
+    if (ka < 1) return;
+    const bool prof = opts.profile != 0;
+    std::vector<EventPair>& ev = fev[PREC_F32];
+    if (prof && ev.empty()) {
+      EventPair ep;
+      CHFSI_HIP(hipEventCreate(&ep.a));
+      CHFSI_HIP(hipEventCreate(&ep.b));
+      ev.push_back(ep);
+    }
+    const std::vector<ChebStep> cs = cheb_schedule(m, a, b, a0);
+    // table rows 1..m-1: the forcing scale alpha_i t_i(mu_j) of step i;
+    // row m: t_m(mu_j)
+    const size_t tab_elems = (size_t)(m + 1) * ka;
+    ensure_htab(tab_elems);
+    ctab.ensure(tab_elems * sizeof(double));
+    double* tab = htab;
+    for (int64_t j = 0; j < ka; j++) {
+      const double mj = mu_h[j];
+      double tp = 1.0, t = fma(cs[0].alpha, mj, cs[0].beta);
+      for (int i = 1; i < m; i++) {
+        tab[(size_t)i * ka + j] = cs[i].alpha * t;
+        const double tn = cs[i].alpha * mj * t + cs[i].beta * t + cs[i].gamma * tp;
+        tp = t;
+        t = tn;
+      }
+      tab[(size_t)m * ka + j] = t;
+    }
+    CHFSI_HIP(hipMemcpyAsync(ctab.p, tab, tab_elems * sizeof(double), hipMemcpyHostToDevice, st));
+    cc* R = (cc*)R32.p;
+    cc* cur = (cc*)Y32b.p;
+    cc* prev = (cc*)Y32.p;
+    ritz_forcing(Y0, ldy, AY0, lday, mu_d, cs[0].alpha, R, n, cur, n, n, ka, st);
+    if (prof) CHFSI_HIP(hipEventRecord(ev[0].a, st));
+    for (int i = 1; i < m; i++) {
+      GemmOp g;
+      g.prec = PREC_F32;
+      g.M = n; g.N = ka; g.K = n;
+      g.A = A32.p; g.lda = n; g.B = cur; g.ldb = n; g.C = prev; g.ldc = n;
+      g.X = cur; g.ldx = n;
+      g.Z = i == 1 ? nullptr : prev;  // D_0 = 0
+      g.ldz = n;
+      g.alpha = cs[i].alpha; g.beta = cs[i].beta; g.gamma = cs[i].gamma;
+      g.R = R; g.ldr = n; g.rs = ctab.d() + (size_t)i * ka;
+      g.filter_step = true;
+      g.cfg = opts.filter_tile;
+      g.splitk = opts.filter_splitk;
+      zgemm(g, gw(), st);
+      std::swap(cur, prev);
+    }
+    if (prof) CHFSI_HIP(hipEventRecord(ev[0].b, st));
+    ritz_combine(Y0, ldy, ctab.d() + (size_t)m * ka, cur, n, F, ldf, n, ka, st);
+    filt_launches[PREC_F32] += m - 1;
+    filt_flops[PREC_F32] += 8.0 * (double)n * (double)n * (double)ka * (double)(m - 1);
+    if (prof && m > 1) filt_pending[PREC_F32] = true;
+  }
+
   // Add the event time of the filter run since the last call in each
   // precision (the stream must have passed it).
   void collect_filter_events() {
@@ -1024,6 +1113,7 @@ struct SolveState {
   int64_t cl = 0;
   int it = 0;
   bool converged = false, done = false, mixed = false;
+  bool ritz32 = false;  // precision 2: the filter in FP32 on the Ritz residual
   double mixed_switch = 0.0;  // relative residual below which a column's filter is FP64
   std::vector<double> lam, rho_lock;
   std::vector<hipEvent_t> ev;
@@ -1103,11 +1193,13 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
     throw;
   }
   s.mixed = o.precision == 1;
+  s.ritz32 = o.precision == 2;
   s.mixed_switch = o.mixed_switch_digits > 0 ? std::pow(10.0, -o.mixed_switch_digits) : MIXED_SWITCH;
-  if (s.mixed) {
+  if (s.mixed || s.ritz32) {
     c->A32.ensure((size_t)n * n * sizeof(cc));
     c->Y32.ensure((size_t)n * k * sizeof(cc));
     c->Y32b.ensure((size_t)n * k * sizeof(cc));
+    if (s.ritz32) c->R32.ensure((size_t)n * k * sizeof(cc));
     to_f32(c->A.z(), n, (cc*)c->A32.p, n, n, n, st);
   }
   c->sync();
@@ -1189,6 +1281,10 @@ void solve_filter_begin(SolveState& s) {
   // zero by zero.  Raising b by a relative 1e-8 changes nothing elsewhere.
   s.b = std::max(s.b, s.a + 1e-8 * std::max(std::max(std::fabs(s.a), std::fabs(s.b)),
                                              std::max(s.inf.h_H, 1e-300)));
+  if (s.ritz32) {
+    s.split = 0;  // every active column in FP32
+    return;
+  }
   if (!s.mixed) {
     s.split = ka;
     return;
@@ -1213,13 +1309,20 @@ void solve_filter(chfsi_ctx c, SolveState& s) {
   zc* Y = c->Y.z();
   zc* F = c->F.z();
   const int64_t p = s.split, c32 = s.cl + p;
+  // A Y_0 of the active columns is the last Rayleigh-Ritz step's W Z (and
+  // their Ritz values are in mu from the same offset)
+  const bool have_wz = s.wz_first >= 0 && s.cl >= s.wz_first;
+  const zc* ay0 = have_wz ? c->Wz.z() + (s.cl - s.wz_first) * n : nullptr;
   if (p > 0) {
-    // A Y_0 of the active columns is the last Rayleigh-Ritz step's W Z
-    const zc* ay0 = s.wz_first >= 0 && s.cl >= s.wz_first ? c->Wz.z() + (s.cl - s.wz_first) * n : nullptr;
     zc* res = c->filter(c->A.z(), n, Y + s.cl * n, n, c->Yb.z() + s.cl * n, n, p, c->opts.degree, s.a, s.b, s.a0, ay0, n);
     copy2d(res, n, F + s.cl * n, n, n, p, st);
   }
-  if (p < ka) {
+  if (p < ka && s.ritz32 && have_wz) {
+    // the active columns are Ritz vectors: the FP32 filter on their residual
+    c->filter_ritz32(Y + s.cl * n, n, ay0, n, c->mu.d() + (s.cl - s.wz_first), s.lam.data() + s.cl, ka,
+                     c->opts.degree, s.a, s.b, s.a0, F + s.cl * n, n);
+    s.inf.iterations_fp32++;
+  } else if (p < ka) {
     cc* y32 = (cc*)c->Y32.p;
     cc* y32b = (cc*)c->Y32b.p;
     to_f32(Y + c32 * n, n, y32, n, n, ka - p, st);
@@ -1453,11 +1556,12 @@ struct Worker {
 };
 
 // Device bytes of a solver context for problems of size n with block k.
-size_t ctx_footprint(int64_t n, int64_t k, int precision) {
+size_t ctx_footprint(int64_t n, int64_t k, int precision, int degree) {
   size_t z = sizeof(zc);
   size_t b = z * ((size_t)4 * n * n + (size_t)6 * n * k + (size_t)13 * k * k + (size_t)n * splitk_columns(k) +
                   (size_t)64 * n);
-  if (precision == 1) b += sizeof(cc) * ((size_t)n * n + (size_t)2 * n * k);
+  if (precision >= 1) b += sizeof(cc) * ((size_t)n * n + (size_t)2 * n * k);
+  if (precision == 2) b += sizeof(cc) * (size_t)n * k + sizeof(double) * (size_t)(degree + 1) * k;
   return b;
 }
 
@@ -1506,8 +1610,9 @@ struct chfsi_server_s {
             holder_idle = true;
         if (holder_idle) continue;
       }
-      const size_t ctx_need = ctx_footprint(r->n, k, cfg.opts.precision);
-      const size_t grown = ctx_footprint(std::max(w.cap_n, r->n), std::max(w.cap_k, k), cfg.opts.precision);
+      const size_t ctx_need = ctx_footprint(r->n, k, cfg.opts.precision, cfg.opts.degree);
+      const size_t grown =
+          ctx_footprint(std::max(w.cap_n, r->n), std::max(w.cap_k, k), cfg.opts.precision, cfg.opts.degree);
       size_t ctx_delta = w.ctx ? (grown > w.bytes ? grown - w.bytes : 0) : ctx_need;
       size_t ctx_freed = 0;
       bool recreate = false;
@@ -2211,7 +2316,7 @@ chfsi_status chfsi_create(chfsi_ctx* out, int64_t n, const chfsi_opts* opts, voi
   chfsi_opts o;
   chfsi_default_opts(&o);
   if (opts) o = *opts;
-  if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX || (o.precision != 0 && o.precision != 1) ||
+  if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX || o.precision < 0 || o.precision > 2 ||
       (o.qr_mode != 0 && o.qr_mode != 1) || o.filter_tile < 0 || o.filter_tile >= zgemm_num_configs() ||
       o.filter_splitk < 0 || o.filter_splitk > 16 || o.mixed_switch_digits < 0 || o.mixed_switch_digits > 12)
     return CHFSI_EINVAL;
@@ -2288,8 +2393,9 @@ chfsi_status chfsi_filter(chfsi_ctx c, const void* A, int64_t lda, void* Y, int6
     }
     c->P_cap = std::max(c->P_cap, std::min(c->P_elems, (size_t)c->opts.filter_splitk * c->n * k));
     const int64_t n = c->n;
-    if (c->opts.precision == 1) {
-      // mixed precision: the filter itself in complex FP32
+    if (c->opts.precision >= 1) {
+      // mixed precision: the filter itself in complex FP32 (no Ritz values
+      // here: the plain recurrence)
       c->A32.ensure((size_t)n * n * sizeof(cc));
       c->Y32.ensure((size_t)n * k * sizeof(cc));
       c->Y32b.ensure((size_t)n * k * sizeof(cc));
@@ -2301,6 +2407,41 @@ chfsi_status chfsi_filter(chfsi_ctx c, const void* A, int64_t lda, void* Y, int6
       zc* res = c->filter((const zc*)A, lda, (zc*)Y, ldy, c->Yb.z(), n, k, m, a, b, a0);
       if (res != (zc*)Y) copy2d(res, n, (zc*)Y, ldy, n, k, c->st);
     }
+    c->sync();
+    c->collect_filter_events();
+  });
+}
+
+chfsi_status chfsi_filter_ritz(chfsi_ctx c, const void* A, int64_t lda, void* Y, int64_t ldy, const void* AY,
+                               int64_t lday, const double* mu, int64_t k, int32_t m, double a, double b, double a0) {
+  return guarded(c, [&] {
+    check_ptr(A, "A");
+    check_ptr(Y, "Y");
+    check_ptr(AY, "AY");
+    check_ptr(mu, "mu");
+    check_ld(lda, c->n, "lda");
+    check_ld(ldy, c->n, "ldy");
+    check_ld(lday, c->n, "lday");
+    if (k < 1 || k > c->n || m < 1 || !(b > a)) throw Error(ST_EINVAL, "filter: need 1 <= k <= n, m >= 1, b > a");
+    c->ensure_small();
+    c->ensure_k(k);
+    c->reset_filter_stats();
+    if (c->opts.filter_splitk > 1 && c->P_elems < (size_t)c->opts.filter_splitk * c->n * k) {
+      c->P_elems = (size_t)c->opts.filter_splitk * c->n * k;
+      c->P.release();
+      c->P.ensure(c->P_elems * sizeof(zc));
+    }
+    c->P_cap = std::max(c->P_cap, std::min(c->P_elems, (size_t)c->opts.filter_splitk * c->n * k));
+    const int64_t n = c->n;
+    c->A32.ensure((size_t)n * n * sizeof(cc));
+    c->Y32.ensure((size_t)n * k * sizeof(cc));
+    c->Y32b.ensure((size_t)n * k * sizeof(cc));
+    c->R32.ensure((size_t)n * k * sizeof(cc));
+    to_f32((const zc*)A, lda, (cc*)c->A32.p, n, n, n, c->st);
+    std::vector<double> mu_h(mu, mu + k);
+    CHFSI_HIP(hipMemcpyAsync(c->mu.p, mu_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
+    c->filter_ritz32((const zc*)Y, ldy, (const zc*)AY, lday, c->mu.d(), mu_h.data(), k, m, a, b, a0, c->F.z(), n);
+    copy2d(c->F.z(), n, (zc*)Y, ldy, n, k, c->st);
     c->sync();
     c->collect_filter_events();
   });
@@ -2503,7 +2644,7 @@ chfsi_status chfsi_server_create(chfsi_server* out, const chfsi_server_config* c
   if (cfg->workers < 1 || cfg->workers > 64 || cfg->hbm_budget_bytes <= 0) return CHFSI_EINVAL;
   chfsi_opts o = cfg->opts;
   if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX ||
-      (o.precision != 0 && o.precision != 1) || (o.qr_mode != 0 && o.qr_mode != 1))
+      o.precision < 0 || o.precision > 2 || (o.qr_mode != 0 && o.qr_mode != 1))
     return CHFSI_EINVAL;
   chfsi_server s = new (std::nothrow) chfsi_server_s();
   if (!s) return CHFSI_ENOMEM;
@@ -2665,6 +2806,8 @@ chfsi_status chfsi_batch_create(chfsi_batch* out, int32_t count, const int64_t* 
   if (opts) o = *opts;
   o.profile = 0;
   if (o.filter_tile != 0 && !zgemm_grouped_config_ok(o.filter_tile)) return CHFSI_EINVAL;
+  // the grouped filter steps run the plain recurrence only (precision 0 or 1)
+  if (o.precision == 2) return CHFSI_EINVAL;
   chfsi_batch b = new (std::nothrow) chfsi_batch_s();
   if (!b) return CHFSI_ENOMEM;
   try {

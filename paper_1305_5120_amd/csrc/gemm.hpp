@@ -44,6 +44,11 @@ struct GemmOp {
   bool filter_step = false;  // launch under the Chebyshev-step kernel symbol
   int cfg = 0;              // tile configuration (0: chosen automatically)
   int splitk = 0;           // K split (0: chosen automatically, 1: none)
+  // FP32 only, batch 1: out(:, j) += rs[j] R(:, j) (R complex FP32, M x N
+  // with leading dimension ldr; rs device FP64, N entries), the forcing term
+  // of the filter's Ritz-residual recurrence
+  const void* R = nullptr; int64_t ldr = 0;
+  const double* rs = nullptr;
 };
 
 // Scratch for split-K partial tiles (P_elems complex FP64 elements; an FP32
@@ -66,6 +71,8 @@ struct ZGemmParams {
   int64_t kchunk;
   void* P;
   int tiles_m, tiles_n;
+  const void* R; int64_t ldr;  // FP32 only: out(:, j) += rs[j] R(:, j) (null: none)
+  const double* rs;
 };
 
 void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st);

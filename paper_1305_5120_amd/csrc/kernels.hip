@@ -94,6 +94,34 @@ __global__ void k_c2z(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t 
   dst[i + j * ldd] = make_double2((double)v.x, (double)v.y);
 }
 
+// The FP32 filter on the Ritz residual: with Y_0 Ritz vectors (values mu),
+// R = A Y_0 - Y_0 diag(mu) formed in FP64 and rounded to FP32 (the forcing of
+// the residual part's recurrence) and that part's first iterate
+// D_1 = alpha0 R (the first degree step of eq. (2) applied to Y_0).
+__global__ void k_ritz_forcing(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu, double alpha0,
+                               cc* R, int64_t ldr, cc* D1, int64_t ldd, int64_t m, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  const int64_t i = e % m, j = e / m;
+  const zc y = Y0[i + j * ldy], w = AY0[i + j * lday];
+  const double mj = mu[j];
+  const double rx = fma(-mj, y.x, w.x), ry = fma(-mj, y.y, w.y);
+  R[i + j * ldr] = make_float2((float)rx, (float)ry);
+  D1[i + j * ldd] = make_float2((float)(alpha0 * rx), (float)(alpha0 * ry));
+}
+
+// The filtered block from its two parts: F = Y_0 diag(t) + D (D widened).
+__global__ void k_ritz_combine(const zc* Y0, int64_t ldy, const double* t, const cc* D, int64_t ldd, zc* F, int64_t ldf,
+                               int64_t m, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  const int64_t i = e % m, j = e / m;
+  const zc y = Y0[i + j * ldy];
+  const cc d = D[i + j * ldd];
+  const double tj = t[j];
+  F[i + j * ldf] = zmk(fma(tj, y.x, (double)d.x), fma(tj, y.y, (double)d.y));
+}
+
 __global__ void k_set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * n) return;
@@ -1312,6 +1340,18 @@ void to_f32(const zc* src, int64_t lds, cc* dst, int64_t ldd, int64_t m, int64_t
 void to_f64(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st) {
   if (m * n == 0) return;
   LAUNCH(k_c2z, grid1(m * n), dim3(NT), 0, st, src, lds, dst, ldd, m, n);
+}
+
+void ritz_forcing(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu, double alpha0, cc* R,
+                  int64_t ldr, cc* D1, int64_t ldd, int64_t m, int64_t n, hipStream_t st) {
+  if (m * n == 0) return;
+  LAUNCH(k_ritz_forcing, grid1(m * n), dim3(NT), 0, st, Y0, ldy, AY0, lday, mu, alpha0, R, ldr, D1, ldd, m, n);
+}
+
+void ritz_combine(const zc* Y0, int64_t ldy, const double* t, const cc* D, int64_t ldd, zc* F, int64_t ldf, int64_t m,
+                  int64_t n, hipStream_t st) {
+  if (m * n == 0) return;
+  LAUNCH(k_ritz_combine, grid1(m * n), dim3(NT), 0, st, Y0, ldy, t, D, ldd, F, ldf, m, n);
 }
 
 void set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st) {

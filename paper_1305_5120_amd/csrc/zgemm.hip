@@ -32,7 +32,9 @@
 //     one XCD (consecutive tiles share the A panel in that XCD's L2);
 //   * optional triangular structure of op(A) / op(B) trims each tile's K range;
 //     optional split-K writes partial tiles that a reduction kernel combines
-//     with the epilogue (small, deep products: Gram matrices, projections).
+//     with the epilogue (small, deep products: Gram matrices, projections);
+//   * FP32 steps may add a column-scaled fourth term rs[j] R(:, j): the
+//     forcing of the recurrence the FP32 filter runs on the Ritz residual.
 #include "gemm.hpp"
 
 namespace chfsi {
@@ -365,6 +367,14 @@ __device__ __forceinline__ void zgemm_body(const ZGemmParams& p, int64_t t, int 
             vx += ga * z.x;
             vy += ga * z.y;
           }
+          if constexpr (sizeof(E) == 8) {
+            if (p.R) {
+              const E rv = static_cast<const E*>(p.R)[m + n * p.ldr];
+              const R sc = (R)p.rs[n];
+              vx += sc * rv.x;
+              vy += sc * rv.y;
+            }
+          }
           C[m + n * p.ldc] = PT::mk(vx, vy);
         }
       }
@@ -516,6 +526,14 @@ __device__ __forceinline__ void splitk_reduce_elem(const ZGemmParams& p, int64_t
     const E z = static_cast<const E*>(p.Z)[(int64_t)batch * p.sZ + m + n * p.ldz];
     vx += (R)p.gamma * z.x;
     vy += (R)p.gamma * z.y;
+  }
+  if constexpr (sizeof(E) == 8) {
+    if (p.R) {
+      const E rv = static_cast<const E*>(p.R)[m + n * p.ldr];
+      const R sc = (R)p.rs[n];
+      vx += sc * rv.x;
+      vy += sc * rv.y;
+    }
   }
   static_cast<E*>(p.C)[(int64_t)batch * p.sC + m + n * p.ldc] = PT::mk(vx, vy);
 }
@@ -884,6 +902,9 @@ void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st) {
   const bool f32 = g.prec == PREC_F32;
   if (f32 && (g.opA != OP_N || g.opB != OP_N || g.flags))
     throw Error(ST_EINVAL, "zgemm: FP32 products support op = N and no structure flags only");
+  if (g.R && (!f32 || batch != 1 || !g.rs || g.ldr < g.M))
+    throw Error(ST_EINVAL, "zgemm: the column-scaled term needs an FP32 product, batch 1, rs and ldr >= M");
+  p.R = g.R; p.ldr = g.ldr; p.rs = g.rs;
   if (sk > 1) {
     const size_t cap = f32 ? 2 * w.P_elems : w.P_elems;
     if (!w.P || (size_t)sk * g.M * g.N * batch > cap)

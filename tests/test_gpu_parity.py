@@ -945,12 +945,13 @@ def _subspace_full_size(p, X, ev, nev):
     return worst
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_solve_precision_configuration_full_size(lib, precision_problem, precision):
-    """n=10000, nev=600, nex=60, degree 20, FP64 throughout and mixed
-    precision (the filter in complex FP32 until columns approach the
-    tolerance, everything else FP64): every eigenvalue against the spectrum
-    known by construction, the generalized residuals of the returned pairs,
+    """n=10000, nev=600, nex=60, degree 20, FP64 throughout, mixed precision
+    (the filter in complex FP32 until columns approach the tolerance,
+    everything else FP64) and the FP32 filter on the Ritz residual (every
+    filter product in FP32): every eigenvalue against the spectrum known by
+    construction, the generalized residuals of the returned pairs,
     S-orthonormality and subspace angles against the constructed vectors."""
     import torch
     n, nev, nex = 10000, 600, 60
@@ -958,7 +959,9 @@ def test_solve_precision_configuration_full_size(lib, precision_problem, precisi
     ctx = lib.create(n, degree=20, seed=0, precision=precision)
     ev, X, info, st = lib.solve(ctx, p["H"], p["S"], nev, nex, tol=1e-10)
     assert st == 0
-    assert (info["iterations_fp32"] > 0) == (precision == 1)
+    assert (info["iterations_fp32"] > 0) == (precision >= 1)
+    if precision == 2:
+        assert info["filter_launches_fp32"] == info["filter_launches"]
     lam = np.sort(p["lam"])[:nev]
     H, S = p["H"], p["S"]
     v = torch.ones(n, dtype=torch.complex128, device="cuda")
@@ -978,7 +981,7 @@ def test_solve_precision_configuration_full_size(lib, precision_problem, precisi
     ctx.release()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_solve_full_size_first_problem_of_sequence(lib, precision):
     """n=4000, nev=400, nex=40, degree 20 (the benchmark's sequence, first
     problem: spectrum known by construction)."""
@@ -986,7 +989,7 @@ def test_solve_full_size_first_problem_of_sequence(lib, precision):
     p = workloads.make_problem_torch(4000, 1, device="cuda")
     ctx = lib.create(4000, degree=20, seed=0, precision=precision)
     ev, X, info, st = lib.solve(ctx, p["H"], p["S"], 400, 40, tol=1e-10)
-    assert (info["iterations_fp32"] > 0) == (precision == 1)
+    assert (info["iterations_fp32"] > 0) == (precision >= 1)
     assert st == 0
     lam = np.sort(p["lam"])[:400]
     H, S = p["H"], p["S"]

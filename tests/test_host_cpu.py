@@ -100,11 +100,14 @@ def test_eigenpair_report():
     lam = np.array([3.0, -1.0, 0.5, 7.0])
     ev64 = np.array([-1.0 + 1e-14, 0.5, 3.0])
     evm = np.array([-1.0, 0.5 + 2e-13, 3.0])
-    r = bench._eig_report(lam, ev64, evm, 7.0)
+    evr = np.array([-1.0, 0.5, 3.0 - 3e-13])
+    r = bench._eig_report(lam, ev64, {"mixed": evm, "ritz32": evr}, 7.0)
     assert len(r["fp64_vs_exact"]) == 3
     assert r["max"]["fp64_vs_exact"] == pytest.approx(1e-14 / 7.0, rel=1e-2)
     assert r["max"]["mixed_vs_exact"] == pytest.approx(2e-13 / 7.0, rel=1e-2)
     assert r["mixed_vs_fp64"][0] == pytest.approx(1e-14 / 7.0, rel=1e-2)
+    assert r["max"]["ritz32_vs_exact"] == pytest.approx(3e-13 / 7.0, rel=1e-2)
+    assert r["ritz32_vs_fp64"][2] == pytest.approx(3e-13 / 7.0, rel=1e-2)
 
 
 def test_bench_refuses_several_gpus(capsys):
