@@ -754,12 +754,14 @@ def run_mixed_same_workload(args, cfg, probs, fp64_rate, precision=1):
         one(i)
     torch.cuda.synchronize()
     infos = []
+    MARKER.push(f"bench.mixed_region_p{precision}")
     t0 = time.perf_counter()
     for i in range(warmup, total):
         ev, X, info, st = one(i)
         infos.append(info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    MARKER.pop()
     rel_res = residual_check(probs[total - 1], ev, X)
     del X
     ctx.release()
@@ -776,6 +778,8 @@ def run_mixed_same_workload(args, cfg, probs, fp64_rate, precision=1):
             "steps": steps, "warmup": warmup,
             "iterations": [i["iterations"] for i in infos], "iterations_fp32": [i["iterations_fp32"] for i in infos],
             "max_rel_residual": rel_res, "filter_tflops_fp32": f32f / f32s / 1e12 if f32s else None,
+            "filter_flops_fp32": f32f, "filter_event_seconds_fp32": f32s,
+            "filter_launches_fp32": sum(i["filter_launches_fp32"] for i in infos),
             "filter_tflops_fp64_part": f64f / f64s / 1e12 if f64s > 0 else None,
             "filter_flops_fp32_share": f32f / max(1.0, sum(i["filter_flops"] for i in infos)),
             "fp32_roofline": {"bound": "mfma", "achieved": f32f / f32s / 1e12 if f32s else None, "peak": 157.3,

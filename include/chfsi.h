@@ -70,7 +70,7 @@ typedef struct {
                             and D_i the recurrence on R (FP32 products, errors relative to |D|, which
                             falls with the residual): no FP64 filter sweeps, the same FP64 tolerance;
                             the first iteration after a start block that is not a Ritz basis runs the
-                            plain FP32 filter; not accepted by chfsi_batch_create */
+                            plain FP32 filter */
   uint64_t seed;         /* Philox4x32-10 seed of the random start vectors (default 0) */
   int32_t profile;       /* 1: time the filter with device events (one pair around each filter call's degree steps) */
   int32_t qr_mode;       /* re-orthonormalization: 0 = CholeskyQR2, Householder when a Gram

@@ -919,8 +919,40 @@ struct chfsi_ctx_s {
       ev.push_back(ep);
     }
     const std::vector<ChebStep> cs = cheb_schedule(m, a, b, a0);
-    // table rows 1..m-1: the forcing scale alpha_i t_i(mu_j) of step i;
-    // row m: t_m(mu_j)
+    cc* cur = (cc*)Y32b.p;
+    cc* prev = (cc*)Y32.p;
+    ritz_prepare(Y0, ldy, AY0, lday, mu_d, mu_h, ka, cs, cur);
+    if (prof) CHFSI_HIP(hipEventRecord(ev[0].a, st));
+    for (int i = 1; i < m; i++) {
+      GemmOp g;
+      g.prec = PREC_F32;
+      g.M = n; g.N = ka; g.K = n;
+      g.A = A32.p; g.lda = n; g.B = cur; g.ldb = n; g.C = prev; g.ldc = n;
+      g.X = cur; g.ldx = n;
+      g.Z = i == 1 ? nullptr : prev;  // D_0 = 0
+      g.ldz = n;
+      g.alpha = cs[i].alpha; g.beta = cs[i].beta; g.gamma = cs[i].gamma;
+      g.R = R32.p; g.ldr = n; g.rs = ctab.d() + (size_t)i * ka;
+      g.filter_step = true;
+      g.cfg = opts.filter_tile;
+      g.splitk = opts.filter_splitk;
+      zgemm(g, gw(), st);
+      std::swap(cur, prev);
+    }
+    if (prof) CHFSI_HIP(hipEventRecord(ev[0].b, st));
+    ritz_finish(Y0, ldy, cur, m, ka, F, ldf);
+    filt_launches[PREC_F32] += m - 1;
+    filt_flops[PREC_F32] += 8.0 * (double)n * (double)n * (double)ka * (double)(m - 1);
+    if (prof && m > 1) filt_pending[PREC_F32] = true;
+  }
+
+  // The parts of the Ritz-residual filter around its products: the scalar
+  // recurrence's table on the device (rows 1..m-1: the forcing scale
+  // alpha_i t_i(mu_j) of step i; row m: t_m(mu_j)), R into R32 and D_1 into
+  // D1 (n x ka, FP32); then F = Y_0 diag(t_m) + D_m.
+  void ritz_prepare(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu_d, const double* mu_h,
+                    int64_t ka, const std::vector<ChebStep>& cs, cc* D1) {
+    const int m = (int)cs.size();
     const size_t tab_elems = (size_t)(m + 1) * ka;
     ensure_htab(tab_elems);
     ctab.ensure(tab_elems * sizeof(double));
@@ -937,32 +969,11 @@ struct chfsi_ctx_s {
       tab[(size_t)m * ka + j] = t;
     }
     CHFSI_HIP(hipMemcpyAsync(ctab.p, tab, tab_elems * sizeof(double), hipMemcpyHostToDevice, st));
-    cc* R = (cc*)R32.p;
-    cc* cur = (cc*)Y32b.p;
-    cc* prev = (cc*)Y32.p;
-    ritz_forcing(Y0, ldy, AY0, lday, mu_d, cs[0].alpha, R, n, cur, n, n, ka, st);
-    if (prof) CHFSI_HIP(hipEventRecord(ev[0].a, st));
-    for (int i = 1; i < m; i++) {
-      GemmOp g;
-      g.prec = PREC_F32;
-      g.M = n; g.N = ka; g.K = n;
-      g.A = A32.p; g.lda = n; g.B = cur; g.ldb = n; g.C = prev; g.ldc = n;
-      g.X = cur; g.ldx = n;
-      g.Z = i == 1 ? nullptr : prev;  // D_0 = 0
-      g.ldz = n;
-      g.alpha = cs[i].alpha; g.beta = cs[i].beta; g.gamma = cs[i].gamma;
-      g.R = R; g.ldr = n; g.rs = ctab.d() + (size_t)i * ka;
-      g.filter_step = true;
-      g.cfg = opts.filter_tile;
-      g.splitk = opts.filter_splitk;
-      zgemm(g, gw(), st);
-      std::swap(cur, prev);
-    }
-    if (prof) CHFSI_HIP(hipEventRecord(ev[0].b, st));
-    ritz_combine(Y0, ldy, ctab.d() + (size_t)m * ka, cur, n, F, ldf, n, ka, st);
-    filt_launches[PREC_F32] += m - 1;
-    filt_flops[PREC_F32] += 8.0 * (double)n * (double)n * (double)ka * (double)(m - 1);
-    if (prof && m > 1) filt_pending[PREC_F32] = true;
+    ritz_forcing(Y0, ldy, AY0, lday, mu_d, cs[0].alpha, (cc*)R32.p, n, D1, n, n, ka, st);
+  }
+
+  void ritz_finish(const zc* Y0, int64_t ldy, const cc* Dm, int m, int64_t ka, zc* F, int64_t ldf) {
+    ritz_combine(Y0, ldy, ctab.d() + (size_t)m * ka, Dm, n, F, ldf, n, ka, st);
   }
 
   // Add the event time of the filter run since the last call in each
@@ -1924,6 +1935,7 @@ struct BatchMember {
   bool active = false;     // taking part in the current iteration
   double iter_flops[2] = {0, 0};  // its filter flops per precision in the current iteration
   bool reuse = false;             // its FP64 first step came from W Z this iteration
+  bool ritz = false;              // its FP32 range runs on the Ritz residual this iteration
 };
 
 void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, const void* const* S,
@@ -2025,7 +2037,15 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
       int64_t c32, w32;
       range(j, 1, c32, w32);
       CHFSI_HIP(hipEventRecord(s.ev[0], c->st));
-      if (w32 > 0) to_f32(c->Y.z() + c32 * n, n, (cc*)c->Y32.p, n, n, w32, c->st);
+      // precision 2 with Ritz vectors at hand: the Ritz-residual form (its
+      // first step needs no product), else the block rounded to FP32
+      mb[j]->ritz = s.ritz32 && w32 > 0 && s.wz_first >= 0 && s.cl >= s.wz_first;
+      if (mb[j]->ritz)
+        c->ritz_prepare(c->Y.z() + c32 * n, n, c->Wz.z() + (c32 - s.wz_first) * n, n,
+                        c->mu.d() + (c32 - s.wz_first), s.lam.data() + c32, w32, cheb_schedule(m, s.a, s.b, s.a0),
+                        (cc*)c->Y32b.p);
+      else if (w32 > 0)
+        to_f32(c->Y.z() + c32 * n, n, (cc*)c->Y32.p, n, n, w32, c->st);
       // the FP64 range's first step from the last Rayleigh-Ritz product W Z = A Y
       mb[j]->reuse = s.split > 0 && s.wz_first >= 0 && s.cl >= s.wz_first;
       if (mb[j]->reuse) {
@@ -2075,6 +2095,7 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
           char* y0 = p ? (char*)c->Y32.p : (char*)(c->Y.z() + c0 * n);
           char* y1 = p ? (char*)c->Y32b.p : (char*)(c->Yb.z() + c0 * n);
           const std::vector<ChebStep> cs = cheb_schedule(m, s.a, s.b, s.a0);
+          const bool ritz = p == 1 && mb[j]->ritz;  // D_1 already in y1, D_0 = 0
           void *cur = y0, *out = y1;
           for (int i = 0; i < m; i++) {
             ZGemmParams q{};
@@ -2083,14 +2104,18 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
             q.B = cur; q.ldb = n;
             q.C = out; q.ldc = n;
             q.X = cur; q.ldx = n;
-            q.Z = i ? out : nullptr; q.ldz = n;
+            q.Z = i && !(ritz && i == 1) ? out : nullptr; q.ldz = n;
+            if (ritz && i > 0) {
+              q.R = c->R32.p; q.ldr = n;
+              q.rs = c->ctab.d() + (size_t)i * w;
+            }
             q.alpha = cs[i].alpha; q.beta = cs[i].beta; q.gamma = cs[i].gamma;
             q.flags = 0; q.splitk = sk; q.kchunk = sk > 1 ? kchunk : n; q.P = sk > 1 ? c->P.p : nullptr;
             q.tiles_m = (int)tm; q.tiles_n = (int)tn;
             hp[(int64_t)i * G + j] = q;
             std::swap(cur, out);
           }
-          skip0 = p == 0 && mb[j]->reuse;
+          skip0 = (p == 0 && mb[j]->reuse) || ritz;
           const int products = skip0 ? m - 1 : m;
           const double f = 8.0 * (double)n * (double)n * (double)w * (double)products;
           mb[j]->iter_flops[p] = f;
@@ -2140,7 +2165,8 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
       range(j, 1, c0, w);
       if (w > 0) {
         const cc* r = (const cc*)((m & 1) ? c->Y32b.p : c->Y32.p);
-        to_f64(r, n, c->F.z() + c0 * n, n, n, w, c->st);
+        if (mb[j]->ritz) c->ritz_finish(c->Y.z() + c0 * n, n, r, m, w, c->F.z() + c0 * n, n);
+        else to_f64(r, n, c->F.z() + c0 * n, n, n, w, c->st);
         s.inf.iterations_fp32++;
       }
       CHFSI_HIP(hipEventRecord(s.ev[1], c->st));
@@ -2806,8 +2832,6 @@ chfsi_status chfsi_batch_create(chfsi_batch* out, int32_t count, const int64_t* 
   if (opts) o = *opts;
   o.profile = 0;
   if (o.filter_tile != 0 && !zgemm_grouped_config_ok(o.filter_tile)) return CHFSI_EINVAL;
-  // the grouped filter steps run the plain recurrence only (precision 0 or 1)
-  if (o.precision == 2) return CHFSI_EINVAL;
   chfsi_batch b = new (std::nothrow) chfsi_batch_s();
   if (!b) return CHFSI_ENOMEM;
   try {

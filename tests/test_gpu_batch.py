@@ -77,18 +77,20 @@ def test_batch_cold_members_match_oracle_and_spectrum(lib):
     b.close()
 
 
-@pytest.mark.parametrize("tile", [3, 11, 12])
-def test_batch_graph_replay_equals_eager_along_sequences(lib, tile):
+@pytest.mark.parametrize("tile,precision", [(3, 0), (11, 0), (12, 0), (12, 2)])
+def test_batch_graph_replay_equals_eager_along_sequences(lib, tile, precision):
     """Three sequences of three correlated problems each (S fixed, warm
     starts).  With a pinned tile shape (64 x 64 x 8; 64 x 64 x 16 with eight
     waves; 64 x 80 x 16) the captured graph and the eager launches must
     produce identical bits at every step (each iteration replays the graph
-    with the members' own eager work in between)."""
+    with the members' own eager work in between); in FP64 and with the FP32
+    filter on the Ritz residual (whose grouped steps carry the forcing term
+    and skip the first product)."""
     sizes = [260, 180, 300]
     seqs = [list(workloads.make_sequence(n, 3, 70 + i)) for i, n in enumerate(sizes)]
     out = {}
     for use_graph in (False, True):
-        b = lib.Batch(sizes, use_graph=use_graph, degree=10, seed=2, filter_tile=tile)
+        b = lib.Batch(sizes, use_graph=use_graph, degree=10, seed=2, filter_tile=tile, precision=precision)
         res = []
         for ell in range(3):
             H = [_t(s[ell].H) for s in seqs]
@@ -101,6 +103,7 @@ def test_batch_graph_replay_equals_eager_along_sequences(lib, tile):
             assert rep["tile_config"] == tile
             for i in range(3):
                 assert infos[i]["warm_start"] == (1 if ell > 0 else 0)
+                assert (infos[i]["iterations_fp32"] == infos[i]["iterations"]) == (precision == 2)
                 _check(seqs[i][ell], ev[i], _np(X[i]), nev[i])
             res.append(([e.copy() for e in ev], [_np(x) for x in X], [i["iterations"] for i in infos]))
         out[use_graph] = res
@@ -114,14 +117,18 @@ def test_batch_graph_replay_equals_eager_along_sequences(lib, tile):
             assert np.array_equal(x0[i], x1[i])
 
 
-def test_batch_mixed_precision_reaches_fp64_tolerance(lib):
+@pytest.mark.parametrize("precision", [1, 2])
+def test_batch_mixed_precision_reaches_fp64_tolerance(lib, precision):
     probs = [workloads.make_problem(400, 3), workloads.make_problem(256, 9)]
     nevs, nexs = [40, 26], [8, 6]
-    b = lib.Batch([p.n for p in probs], use_graph=True, degree=10, seed=0, precision=1)
+    b = lib.Batch([p.n for p in probs], use_graph=True, degree=10, seed=0, precision=precision)
     ev, X, infos, st, rep = b.solve([_t(p.H) for p in probs], [_t(p.S) for p in probs], nevs, nexs, tol=1e-10)
     assert st == [0, 0]
     for i, p in enumerate(probs):
         assert infos[i]["iterations_fp32"] > 0
+        if precision == 2:
+            assert infos[i]["iterations_fp32"] == infos[i]["iterations"]
+            assert infos[i]["filter_launches_fp32"] == infos[i]["filter_launches"]
         _check(p, ev[i], _np(X[i]), nevs[i])
     b.close()
 

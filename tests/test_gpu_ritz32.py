@@ -171,8 +171,3 @@ def test_solve_fp32_ritz_filter_warm_sequence(lib):
         ref = sl.eigh(p.H, p.S, eigvals_only=True)[:nev]
         assert _checks.eig_ok(ev, ref, hn)[0]
         assert _checks.gen_residuals(p.H, p.S, _np(X), ev).max() <= 1e-10 * hn
-
-
-def test_batch_rejects_the_ritz_filter(lib):
-    with pytest.raises(lib.ChfsiError):
-        lib.Batch([64, 80], use_graph=False, degree=4, seed=0, precision=2)
