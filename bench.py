@@ -326,7 +326,8 @@ def _exact_errors(p, evals):
 
 
 def run_precision(args):
-    """One n = 10000 problem solved cold in FP64 and with the mixed filter."""
+    """One n = 10000 problem solved cold in FP64 and with the two mixed filters
+    (precision 1: FP64 final sweeps; precision 2: FP32 on the Ritz residual)."""
     import torch
     from paper_1305_5120_amd import chfsi
     import workloads
@@ -334,7 +335,7 @@ def run_precision(args):
     p = workloads.make_problem_torch(n, 2, device="cuda")
     torch.cuda.synchronize()
     res = {}
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
         ctx = chfsi.create(n, degree=m, seed=0, precision=prec, profile=1)
         times = []
         for i in range(args.warmup + args.steps):
@@ -355,8 +356,9 @@ def run_precision(args):
             f"; filter kernels FP64 {info['filter_kernel_seconds'] - info['filter_kernel_seconds_fp32']:.2f} s, "
             f"FP32 {info['filter_kernel_seconds_fp32']:.2f} s")
         ctx.release()
-    i64, i32 = res[0]["info"], res[1]["info"]
+    i64, i32, ir = res[0]["info"], res[1]["info"], res[2]["info"]
     f32 = i32["filter_flops_fp32"] / i32["filter_kernel_seconds_fp32"] / 1e12 if i32["filter_kernel_seconds_fp32"] else None
+    fr = ir["filter_flops_fp32"] / ir["filter_kernel_seconds_fp32"] / 1e12 if ir["filter_kernel_seconds_fp32"] else None
     f64 = i64["filter_flops"] / i64["filter_kernel_seconds"] / 1e12 if i64["filter_kernel_seconds"] else None
     out = _base("eigensolves/s, mixed-precision filter (FP32 MFMA) with FP64 final sweeps, residual <=1e-10",
                 1.0 / res[1]["t"], "solves/s", args.steps, args.warmup, 1e3 * res[1]["t"], "complex64 filter + f64",
@@ -369,6 +371,11 @@ def run_precision(args):
                           "max_eig_error_rel": res[1]["err"], "max_rel_residual": res[1]["res"],
                           "filter_tflops_fp32": f32, "phase_seconds": res[1]["phases"],
                           "filter_flops_fp32_share": i32["filter_flops_fp32"] / i32["filter_flops"]},
+                "ritz32": {"solves_per_s": 1.0 / res[2]["t"], "speedup_vs_fp64": res[0]["t"] / res[2]["t"],
+                           "iterations": ir["iterations"], "iterations_fp32": ir["iterations_fp32"],
+                           "max_eig_error_rel": res[2]["err"], "max_rel_residual": res[2]["res"],
+                           "filter_tflops_fp32": fr, "phase_seconds": res[2]["phases"],
+                           "filter_flops_fp32_share": ir["filter_flops_fp32"] / ir["filter_flops"]},
                 "roofline": {"bound": "mfma", "achieved": f32, "peak": 157.3, "unit": "TFLOP/s",
                              "frac": f32 / 157.3 if f32 else None, "flop_count": FLOP_COUNT_NOTE,
                              "matrix_core_frac": GAUSS3_SHARE * f32 / 157.3 if f32 else None, "traffic": None}})
@@ -383,7 +390,7 @@ def _batch_sizes(count, seed):
 
 def run_batch(args):
     """k-point sequences in lockstep (grouped filter launches, captured
-    graphs, online tile choice, mixed precision) against the same problems
+    graphs, online tile choice, a mixed-precision filter) against the same problems
     solved one after another with one context per sequence.  The sequences
     advance together: only the current step's matrices are resident (the
     one-after-another pass draws the same sequences again)."""
@@ -394,7 +401,7 @@ def run_batch(args):
     sizes = _batch_sizes(G, 3)
     nevs = [n // 10 for n in sizes]
     nexs = [max(1, v // 10) for v in nevs]
-    prec = 1
+    prec = args.batch_precision
     sample = list(range(0, G, max(1, G // 4)))
 
     def sequences():
@@ -463,8 +470,8 @@ def run_batch(args):
                 solves / tb, "solves/s", steps - 1, 1, 1e3 * tb / (steps - 1), "complex64 filter + f64",
                 {"workload": "independent k-point sequences of correlated complex Hermitian DGEVPs",
                  "sequences": G, "n": f"uniform integers in [2000, 6000] (seed 3): {sizes}",
-                 "nev": "n/10", "nex": "nev/10", "degree": 20, "tol": 1e-10, "precision": "mixed",
-                 "warm_start": True, "sequence_steps_timed": steps - 1, "generator_draws": args.gen_rng})
+                 "nev": "n/10", "nex": "nev/10", "degree": 20, "tol": 1e-10,
+                 "precision": {1: "mixed", 2: "FP32 filter on the Ritz residual"}[prec], "warm_start": True, "sequence_steps_timed": steps - 1, "generator_draws": args.gen_rng})
     out.update({"sequential_solves_per_s": solves / ts, "speedup_vs_sequential": ts / tb,
                 "grouped_filter_tflops": ff / fs / 1e12 if fs else None,
                 "tile_config": rep0["tile_config"], "tile_config_fp32": rep0["tile_config_fp32"],
@@ -580,22 +587,24 @@ def run_serve(args):
                            for s, ell in order],
               "nev": "uniform 3-20% of n", "nex": "nev/10", "arrival_rate_per_s": rate,
               "workers": args.workers, "hbm_budget_gb": args.budget_gb, "degree": 20, "tol": 1e-10}
+    sp = args.serve_precision
+    pname = {1: "mixed precision", 2: "FP32 filter on the Ritz residual"}[sp]
     if args.serve_paths != "both":
         plain_only = args.serve_paths == "plain"
         st, elapsed, res = (serve(1, 0, "plain FP64, one worker") if plain_only else
-                            serve(args.workers, 1, f"server, {args.workers} workers, mixed precision"))
+                            serve(args.workers, sp, f"server, {args.workers} workers, {pname}"))
         out = _base("eigensolves/s and p50/p99 latency under Poisson arrivals, residual <=1e-10",
                     st["solves_per_second"], "solves/s", len(order), 0, 1e3 * elapsed / len(order),
                     "complex128 (f64)" if plain_only else "complex64 filter + f64",
-                    dict(config, path="plain FP64, one worker" if plain_only else "server, mixed precision"))
+                    dict(config, path="plain FP64, one worker" if plain_only else f"server, {pname}"))
         out.update(path_report(st, res))
         print(json.dumps(out), flush=True)
         return
     plain, _, plain_res = serve(1, 0, "plain FP64, one worker")
-    stats, elapsed, res = serve(args.workers, 1, f"server, {args.workers} workers, mixed precision")
+    stats, elapsed, res = serve(args.workers, sp, f"server, {args.workers} workers, {pname}")
     out = _base("eigensolves/s and p50/p99 latency under Poisson arrivals, residual <=1e-10",
                 stats["solves_per_second"], "solves/s", len(order), 0, 1e3 * elapsed / len(order),
-                "complex64 filter + f64", dict(config, precision="mixed"))
+                "complex64 filter + f64", dict(config, precision=pname))
     out.update({"p50_latency_s": stats["p50_latency"], "p99_latency_s": stats["p99_latency"],
                 "mean_latency_s": stats["mean_latency"], "completed": stats["completed"], "failed": stats["failed"],
                 "peak_bytes": stats["peak_bytes"], "max_rel_residual": res,
@@ -827,6 +836,10 @@ def main():
     ap.add_argument("--serve-paths", choices=["both", "plain", "server"], default="both",
                     help="serve form: run both paths or one of them on the trace")
     ap.add_argument("--workers", type=int, default=4, help="serving workers")
+    ap.add_argument("--batch-precision", type=int, choices=[1, 2], default=2,
+                    help="batch form: the filter of both passes (1: FP32 with FP64 final sweeps, 2: FP32 on the Ritz residual)")
+    ap.add_argument("--serve-precision", type=int, choices=[1, 2], default=2,
+                    help="serve form: the server's filter (1: FP32 with FP64 final sweeps, 2: FP32 on the Ritz residual)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving device-memory budget")
     ap.add_argument("--wc-n", type=int, default=4000, help="problem size of the warm/cold study")
     ap.add_argument("--gen-rng", choices=["host", "device"], default="host",

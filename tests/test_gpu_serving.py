@@ -114,10 +114,11 @@ def test_server_rejects_invalid_block_sizes(lib, sequences):
     srv.close()
 
 
-def test_server_at_configuration_sizes(lib):
+@pytest.mark.parametrize("precision", [1, 2])
+def test_server_at_configuration_sizes(lib, precision):
     """Three sequences with n in the serving configuration's range (2000,
     4500, 8000; nev 3 %, 10 % and 5 % of n, nex = nev/10), two steps each,
-    mixed precision, two workers under the 200 GB budget, submitted
+    both mixed-precision forms, two workers under the 200 GB budget, submitted
     interleaved: every result against a library eigensolver (rocSOLVER
     through torch) on its step's standard-form matrix, with generalized
     residuals.  Gaussian draws on the device."""
@@ -125,7 +126,7 @@ def test_server_at_configuration_sizes(lib):
     cases = [(2000, 0.03), (4500, 0.10), (8000, 0.05)]
     seqs = [list(workloads.make_sequence_torch(n, 2, 700 + i, device="cuda", rng_kind="device"))
             for i, (n, _) in enumerate(cases)]
-    srv = lib.Server(workers=2, hbm_budget_bytes=200 << 30, degree=20, seed=0, precision=1)
+    srv = lib.Server(workers=2, hbm_budget_bytes=200 << 30, degree=20, seed=0, precision=precision)
     tickets = {}
     for ell in range(2):
         for s, (n, f) in enumerate(cases):
