@@ -9,8 +9,9 @@ Default workload: a single complex Hermitian DGEVP with n = 10000,
 nev = 600, nex = 60, Chebyshev degree 20, tol 1e-10, solved cold (random
 start block) at every step, FP64 throughout (`value`); the same problem is
 then solved with the two mixed-precision filters (complex FP32 degree steps,
-FP64 everything else and FP64 final sweeps; and every degree step in complex
-FP32 on the Ritz residual, no FP64 sweeps), reported beside it with the error
+FP64 everything else and FP64 final sweeps; every degree step in complex
+FP32 on the Ritz residual, no FP64 sweeps; the same with FP16 operands),
+reported beside it with the error
 of every eigenpair against the constructed spectrum and the FP64 path.  The
 inputs are synthetic FLAPW-shaped problems (the paper's FLEUR matrices are
 not available).  Prints one JSON line.  `--workload seq4000` runs the
@@ -741,7 +742,8 @@ def run_mixed_same_workload(args, cfg, probs, fp64_rate, precision=1):
     the same way.  precision 1: complex FP32 degree steps for columns whose
     residual is above the switch, FP64 final sweeps to the same tolerance;
     precision 2: every degree step in complex FP32 on the Ritz residual (the
-    recurrence split by linearity), no FP64 sweeps, the same tolerance."""
+    recurrence split by linearity), no FP64 sweeps, the same tolerance;
+    precision 3: as 2 with FP16 operands (FP32 accumulation)."""
     import torch
     from paper_1305_5120_amd import chfsi
     n, nev, nex = cfg["n"], cfg["nev"], cfg["nex"]
@@ -979,9 +981,13 @@ def main():
         ritz = run_mixed_same_workload(args, cfg, probs, out["value"], precision=2)
         ev_ritz = ritz.pop("evals")
         out["mixed_precision_ritz"] = ritz
+        ritz16 = run_mixed_same_workload(args, cfg, probs, out["value"], precision=3)
+        ev_ritz16 = ritz16.pop("evals")
+        out["mixed_precision_ritz_fp16"] = ritz16
         if not cfg["sequence"]:
             anorm = float(abs(probs[0]["lam"]).max())
-            out["eigenpair_errors"] = _eig_report(probs[0]["lam"], ev64, {"mixed": ev_mixed, "ritz32": ev_ritz}, anorm)
+            out["eigenpair_errors"] = _eig_report(probs[0]["lam"], ev64, {"mixed": ev_mixed, "ritz32": ev_ritz,
+                                                                          "ritz16": ev_ritz16}, anorm)
     if args.calibrate_copy:
         calibrate_copy()
     if not args.no_cpu_baseline:

@@ -70,7 +70,11 @@ typedef struct {
                             and D_i the recurrence on R (FP32 products, errors relative to |D|, which
                             falls with the residual): no FP64 filter sweeps, the same FP64 tolerance;
                             the first iteration after a start block that is not a Ritz basis runs the
-                            plain FP32 filter */
+                            plain FP32 filter;
+                            3: as 2 with the products' operands in FP16 (FP32 accumulation; A kept
+                            as FP16 planes, each column of D scaled by a power of two to unit size),
+                            errors relative to |D| at FP16's level; not accepted by
+                            chfsi_batch_create */
   uint64_t seed;         /* Philox4x32-10 seed of the random start vectors (default 0) */
   int32_t profile;       /* 1: time the filter with device events (one pair around each filter call's degree steps) */
   int32_t qr_mode;       /* re-orthonormalization: 0 = CholeskyQR2, Householder when a Gram
@@ -98,7 +102,8 @@ typedef struct {
   double h_H;              /* Lanczos estimate of ||H||_2 (lower bound); scale of the lock test */
   double a0, a;            /* filter scale point and lower end of the damped interval at exit */
   double max_rel_residual; /* max_j ||H x_j - lambda_j S x_j||_2 / h_H over returned pairs */
-  int32_t iterations_fp32;      /* outer iterations whose filter ran in FP32 (precision 1 or 2) */
+  int32_t iterations_fp32;      /* outer iterations whose filter ran in lower precision (FP32; FP16
+                                   operands with precision 3) */
   int32_t filter_launches_fp32; /* of filter_launches, those in FP32 */
   double filter_flops_fp32;     /* of filter_flops, the FP32 part */
   double filter_kernel_seconds_fp32; /* of filter_kernel_seconds, the FP32 part */
@@ -176,11 +181,13 @@ chfsi_status chfsi_filter(chfsi_ctx ctx, const void* A, int64_t lda, void* Y, in
  * (host, k FP64 values) and AY = A Y (device n x k, FP64, leading dimension
  * lday).  Y is overwritten with p(A) Y = Y diag(t_m(mu)) + D_m, where t_i is
  * the filter's recurrence on the scalars mu_j (FP64) and D_i the recurrence
- * on the Ritz residual A Y - Y diag(mu) (D_0 = 0), its products in complex
- * FP32 (A rounded to FP32).  Exact for any mu in exact arithmetic; the FP32
- * rounding errors are relative to |D|, so they shrink as the residual does.
- * Requires b > a, m >= 1, 1 <= k <= n; the context need not have
- * precision 2. */
+ * on the Ritz residual A Y - Y diag(mu) (D_0 = 0), each column scaled by a
+ * power of two to unit size, its products in complex FP32 (A rounded to
+ * FP32) or, when the context has precision 3, with FP16 operands and FP32
+ * accumulation (A Hermitian: its FP16 copy takes row m as the conjugate of
+ * column m).  Exact for any mu in exact arithmetic; the rounding errors are
+ * relative to |D|, so they shrink as the residual does.  Requires b > a,
+ * m >= 1, 1 <= k <= n. */
 chfsi_status chfsi_filter_ritz(chfsi_ctx ctx, const void* A, int64_t lda, void* Y, int64_t ldy, const void* AY,
                                int64_t lday, const double* mu, int64_t k, int32_t m, double a, double b, double a0);
 

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libchfsi.so")
-SOURCES = ["zgemm.hip", "kernels.hip", "engine.hip"]
+SOURCES = ["zgemm.hip", "zgemm_f16.hip", "kernels.hip", "engine.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

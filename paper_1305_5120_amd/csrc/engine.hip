@@ -135,6 +135,8 @@ struct chfsi_ctx_s {
 
   // n x n: standard form, Cholesky factor, its inverse, work; FP32 copy of A
   DBuf A, L, Linv, W, A32;
+  // FP16 planes of A (precision 3: two planes of n rows, f16_plane_ld(n) halves each)
+  DBuf A16;
   // FP32 filter blocks (mixed precision); the FP32 filter on the Ritz
   // residual: its forcing R (n x k, FP32) and the scalar recurrence's table
   DBuf Y32, Y32b, R32, ctab;
@@ -305,7 +307,7 @@ struct chfsi_ctx_s {
   void sync() { CHFSI_HIP(hipStreamSynchronize(st)); }
 
   void free_all() {
-    for (DBuf* b : {&A32, &Y32, &Y32b, &R32, &ctab, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
+    for (DBuf* b : {&A32, &A16, &Y32, &Y32b, &R32, &ctab, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
                     &flags, &P, &hpart, &htop, &tau, &Tall, &gram, &Vp, &Wt, &W2, &LV, &Lw, &Lh, &Lab, &mvpart, &Tsm,
                     &Tz, &Tz2, &Tw, &npart, &jint, &jrot, &bjv, &rf, &rfl, &rfc})
       b->release();
@@ -895,20 +897,22 @@ struct chfsi_ctx_s {
   }
 
   // The filter of Y_0 (n x ka, FP64 Ritz vectors of A with Ritz values mu,
-  // AY0 = A Y_0 in FP64) with its matrix products in complex FP32, result F
-  // (FP64).  The recurrence of eq. (2) is linear, so its iterates split as
+  // AY0 = A Y_0 in FP64) with its matrix products in complex FP32 (or, with
+  // half, FP16 operands and FP32 accumulation), result F (FP64).  The
+  // recurrence of eq. (2) is linear, so its iterates split as
   // Y_i = Y_0 diag(t_i(mu)) + D_i, with t_i the same recurrence on the
   // scalars mu_j (FP64, on the host) and D_i the recurrence on the Ritz
   // residual R = A Y_0 - Y_0 diag(mu):
   //   D_0 = 0, D_1 = alpha_0 R,
   //   D_{i+1} = alpha_i A D_i + beta_i D_i + gamma_i D_{i-1} + alpha_i t_i(mu) R.
-  // Only D runs in FP32 (A rounded to FP32 in A32); its rounding errors are
-  // relative to |D|, which shrinks with the residual, so the filtered block
-  // keeps FP64 accuracy where Y_0 has converged (the plain FP32 filter's
-  // errors are relative to |Y_i| and stop convergence near 1e-7 ||A||).
-  // mu_d (device) and mu_h (host) hold the same ka values.
-  void filter_ritz32(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu_d, const double* mu_h,
-                     int64_t ka, int m, double a, double b, double a0, zc* F, int64_t ldf) {
+  // Only D runs in the lower precision (A rounded to it in A32 / A16, each
+  // column of D scaled by a power of two to unit size); its rounding errors
+  // are relative to |D|, which shrinks with the residual, so the filtered
+  // block keeps FP64 accuracy where Y_0 has converged (the plain FP32
+  // filter's errors are relative to |Y_i| and stop convergence near
+  // 1e-7 ||A||).  mu_d (device) and mu_h (host) hold the same ka values.
+  void filter_ritz(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu_d, const double* mu_h,
+                   int64_t ka, int m, double a, double b, double a0, zc* F, int64_t ldf, bool half) {
     if (ka < 1) return;
     const bool prof = opts.profile != 0;
     std::vector<EventPair>& ev = fev[PREC_F32];
@@ -927,16 +931,23 @@ struct chfsi_ctx_s {
       GemmOp g;
       g.prec = PREC_F32;
       g.M = n; g.N = ka; g.K = n;
-      g.A = A32.p; g.lda = n; g.B = cur; g.ldb = n; g.C = prev; g.ldc = n;
+      g.A = half ? A16.p : A32.p;
+      g.lda = half ? f16_plane_ld(n) : n;
+      g.B = cur; g.ldb = n; g.C = prev; g.ldc = n;
       g.X = cur; g.ldx = n;
       g.Z = i == 1 ? nullptr : prev;  // D_0 = 0
       g.ldz = n;
       g.alpha = cs[i].alpha; g.beta = cs[i].beta; g.gamma = cs[i].gamma;
       g.R = R32.p; g.ldr = n; g.rs = ctab.d() + (size_t)i * ka;
       g.filter_step = true;
-      g.cfg = opts.filter_tile;
-      g.splitk = opts.filter_splitk;
-      zgemm(g, gw(), st);
+      if (half) {
+        g.splitk = opts.filter_splitk;
+        zgemm_f16_step(g, gw(), st);
+      } else {
+        g.cfg = opts.filter_tile;
+        g.splitk = opts.filter_splitk;
+        zgemm(g, gw(), st);
+      }
       std::swap(cur, prev);
     }
     if (prof) CHFSI_HIP(hipEventRecord(ev[0].b, st));
@@ -948,14 +959,16 @@ struct chfsi_ctx_s {
 
   // The parts of the Ritz-residual filter around its products: the scalar
   // recurrence's table on the device (rows 1..m-1: the forcing scale
-  // alpha_i t_i(mu_j) of step i; row m: t_m(mu_j)), R into R32 and D_1 into
-  // D1 (n x ka, FP32); then F = Y_0 diag(t_m) + D_m.
+  // alpha_i t_i(mu_j) of step i; row m: t_m(mu_j); row m + 1: the columns'
+  // scales, written by the device), R into R32 and D_1 into D1 (n x ka,
+  // FP32, both divided by the column scales); then
+  // F = Y_0 diag(t_m) + D_m diag(scale).
   void ritz_prepare(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu_d, const double* mu_h,
                     int64_t ka, const std::vector<ChebStep>& cs, cc* D1) {
     const int m = (int)cs.size();
     const size_t tab_elems = (size_t)(m + 1) * ka;
     ensure_htab(tab_elems);
-    ctab.ensure(tab_elems * sizeof(double));
+    ctab.ensure((tab_elems + ka) * sizeof(double));
     double* tab = htab;
     for (int64_t j = 0; j < ka; j++) {
       const double mj = mu_h[j];
@@ -969,11 +982,12 @@ struct chfsi_ctx_s {
       tab[(size_t)m * ka + j] = t;
     }
     CHFSI_HIP(hipMemcpyAsync(ctab.p, tab, tab_elems * sizeof(double), hipMemcpyHostToDevice, st));
-    ritz_forcing(Y0, ldy, AY0, lday, mu_d, cs[0].alpha, (cc*)R32.p, n, D1, n, n, ka, st);
+    ritz_forcing(Y0, ldy, AY0, lday, mu_d, cs[0].alpha, (cc*)R32.p, n, D1, n, ctab.d() + tab_elems, n, ka, st);
   }
 
   void ritz_finish(const zc* Y0, int64_t ldy, const cc* Dm, int m, int64_t ka, zc* F, int64_t ldf) {
-    ritz_combine(Y0, ldy, ctab.d() + (size_t)m * ka, Dm, n, F, ldf, n, ka, st);
+    const size_t tab_elems = (size_t)(m + 1) * ka;
+    ritz_combine(Y0, ldy, ctab.d() + (size_t)m * ka, ctab.d() + tab_elems, Dm, n, F, ldf, n, ka, st);
   }
 
   // Add the event time of the filter run since the last call in each
@@ -1124,7 +1138,8 @@ struct SolveState {
   int64_t cl = 0;
   int it = 0;
   bool converged = false, done = false, mixed = false;
-  bool ritz32 = false;  // precision 2: the filter in FP32 on the Ritz residual
+  bool ritz = false;    // precision 2 or 3: the filter on the Ritz residual
+  bool ritz16 = false;  // precision 3: its products with FP16 operands
   double mixed_switch = 0.0;  // relative residual below which a column's filter is FP64
   std::vector<double> lam, rho_lock;
   std::vector<hipEvent_t> ev;
@@ -1204,14 +1219,19 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
     throw;
   }
   s.mixed = o.precision == 1;
-  s.ritz32 = o.precision == 2;
+  s.ritz = o.precision >= 2;
+  s.ritz16 = o.precision == 3;
   s.mixed_switch = o.mixed_switch_digits > 0 ? std::pow(10.0, -o.mixed_switch_digits) : MIXED_SWITCH;
-  if (s.mixed || s.ritz32) {
+  if (s.mixed || s.ritz) {
     c->A32.ensure((size_t)n * n * sizeof(cc));
     c->Y32.ensure((size_t)n * k * sizeof(cc));
     c->Y32b.ensure((size_t)n * k * sizeof(cc));
-    if (s.ritz32) c->R32.ensure((size_t)n * k * sizeof(cc));
+    if (s.ritz) c->R32.ensure((size_t)n * k * sizeof(cc));
     to_f32(c->A.z(), n, (cc*)c->A32.p, n, n, n, st);
+    if (s.ritz16) {
+      c->A16.ensure((size_t)2 * n * f16_plane_ld(n) * sizeof(_Float16));
+      to_f16_planes(c->A.z(), n, n, c->A16.p, st);
+    }
   }
   c->sync();
   roctxRangePop();
@@ -1292,8 +1312,8 @@ void solve_filter_begin(SolveState& s) {
   // zero by zero.  Raising b by a relative 1e-8 changes nothing elsewhere.
   s.b = std::max(s.b, s.a + 1e-8 * std::max(std::max(std::fabs(s.a), std::fabs(s.b)),
                                              std::max(s.inf.h_H, 1e-300)));
-  if (s.ritz32) {
-    s.split = 0;  // every active column in FP32
+  if (s.ritz) {
+    s.split = 0;  // every active column in the lower precision
     return;
   }
   if (!s.mixed) {
@@ -1328,10 +1348,10 @@ void solve_filter(chfsi_ctx c, SolveState& s) {
     zc* res = c->filter(c->A.z(), n, Y + s.cl * n, n, c->Yb.z() + s.cl * n, n, p, c->opts.degree, s.a, s.b, s.a0, ay0, n);
     copy2d(res, n, F + s.cl * n, n, n, p, st);
   }
-  if (p < ka && s.ritz32 && have_wz) {
-    // the active columns are Ritz vectors: the FP32 filter on their residual
-    c->filter_ritz32(Y + s.cl * n, n, ay0, n, c->mu.d() + (s.cl - s.wz_first), s.lam.data() + s.cl, ka,
-                     c->opts.degree, s.a, s.b, s.a0, F + s.cl * n, n);
+  if (p < ka && s.ritz && have_wz) {
+    // the active columns are Ritz vectors: the filter on their residual
+    c->filter_ritz(Y + s.cl * n, n, ay0, n, c->mu.d() + (s.cl - s.wz_first), s.lam.data() + s.cl, ka,
+                   c->opts.degree, s.a, s.b, s.a0, F + s.cl * n, n, s.ritz16);
     s.inf.iterations_fp32++;
   } else if (p < ka) {
     cc* y32 = (cc*)c->Y32.p;
@@ -1572,7 +1592,8 @@ size_t ctx_footprint(int64_t n, int64_t k, int precision, int degree) {
   size_t b = z * ((size_t)4 * n * n + (size_t)6 * n * k + (size_t)13 * k * k + (size_t)n * splitk_columns(k) +
                   (size_t)64 * n);
   if (precision >= 1) b += sizeof(cc) * ((size_t)n * n + (size_t)2 * n * k);
-  if (precision == 2) b += sizeof(cc) * (size_t)n * k + sizeof(double) * (size_t)(degree + 1) * k;
+  if (precision >= 2) b += sizeof(cc) * (size_t)n * k + sizeof(double) * (size_t)(degree + 2) * k;
+  if (precision == 3) b += (size_t)4 * n * f16_plane_ld(n);
   return b;
 }
 
@@ -2039,7 +2060,7 @@ void batch_solve_impl(chfsi_batch b, const void* const* H, const int64_t* ldh, c
       CHFSI_HIP(hipEventRecord(s.ev[0], c->st));
       // precision 2 with Ritz vectors at hand: the Ritz-residual form (its
       // first step needs no product), else the block rounded to FP32
-      mb[j]->ritz = s.ritz32 && w32 > 0 && s.wz_first >= 0 && s.cl >= s.wz_first;
+      mb[j]->ritz = s.ritz && w32 > 0 && s.wz_first >= 0 && s.cl >= s.wz_first;
       if (mb[j]->ritz)
         c->ritz_prepare(c->Y.z() + c32 * n, n, c->Wz.z() + (c32 - s.wz_first) * n, n,
                         c->mu.d() + (c32 - s.wz_first), s.lam.data() + c32, w32, cheb_schedule(m, s.a, s.b, s.a0),
@@ -2342,7 +2363,7 @@ chfsi_status chfsi_create(chfsi_ctx* out, int64_t n, const chfsi_opts* opts, voi
   chfsi_opts o;
   chfsi_default_opts(&o);
   if (opts) o = *opts;
-  if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX || o.precision < 0 || o.precision > 2 ||
+  if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX || o.precision < 0 || o.precision > 3 ||
       (o.qr_mode != 0 && o.qr_mode != 1) || o.filter_tile < 0 || o.filter_tile >= zgemm_num_configs() ||
       o.filter_splitk < 0 || o.filter_splitk > 16 || o.mixed_switch_digits < 0 || o.mixed_switch_digits > 12)
     return CHFSI_EINVAL;
@@ -2463,10 +2484,16 @@ chfsi_status chfsi_filter_ritz(chfsi_ctx c, const void* A, int64_t lda, void* Y,
     c->Y32.ensure((size_t)n * k * sizeof(cc));
     c->Y32b.ensure((size_t)n * k * sizeof(cc));
     c->R32.ensure((size_t)n * k * sizeof(cc));
-    to_f32((const zc*)A, lda, (cc*)c->A32.p, n, n, n, c->st);
+    const bool half = c->opts.precision == 3;
+    if (half) {
+      c->A16.ensure((size_t)2 * n * f16_plane_ld(n) * sizeof(_Float16));
+      to_f16_planes((const zc*)A, lda, n, c->A16.p, c->st);
+    } else {
+      to_f32((const zc*)A, lda, (cc*)c->A32.p, n, n, n, c->st);
+    }
     std::vector<double> mu_h(mu, mu + k);
     CHFSI_HIP(hipMemcpyAsync(c->mu.p, mu_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
-    c->filter_ritz32((const zc*)Y, ldy, (const zc*)AY, lday, c->mu.d(), mu_h.data(), k, m, a, b, a0, c->F.z(), n);
+    c->filter_ritz((const zc*)Y, ldy, (const zc*)AY, lday, c->mu.d(), mu_h.data(), k, m, a, b, a0, c->F.z(), n, half);
     copy2d(c->F.z(), n, (zc*)Y, ldy, n, k, c->st);
     c->sync();
     c->collect_filter_events();
@@ -2670,7 +2697,7 @@ chfsi_status chfsi_server_create(chfsi_server* out, const chfsi_server_config* c
   if (cfg->workers < 1 || cfg->workers > 64 || cfg->hbm_budget_bytes <= 0) return CHFSI_EINVAL;
   chfsi_opts o = cfg->opts;
   if (o.degree < 1 || o.max_iter < 1 || o.lanczos_steps < 1 || o.lanczos_steps > JACOBI_LDS_MAX ||
-      o.precision < 0 || o.precision > 2 || (o.qr_mode != 0 && o.qr_mode != 1))
+      o.precision < 0 || o.precision > 3 || (o.qr_mode != 0 && o.qr_mode != 1))
     return CHFSI_EINVAL;
   chfsi_server s = new (std::nothrow) chfsi_server_s();
   if (!s) return CHFSI_ENOMEM;
@@ -2832,6 +2859,8 @@ chfsi_status chfsi_batch_create(chfsi_batch* out, int32_t count, const int64_t* 
   if (opts) o = *opts;
   o.profile = 0;
   if (o.filter_tile != 0 && !zgemm_grouped_config_ok(o.filter_tile)) return CHFSI_EINVAL;
+  // the grouped filter steps have FP64 and FP32 forms only
+  if (o.precision == 3) return CHFSI_EINVAL;
   chfsi_batch b = new (std::nothrow) chfsi_batch_s();
   if (!b) return CHFSI_ENOMEM;
   try {

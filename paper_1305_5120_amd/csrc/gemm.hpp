@@ -93,6 +93,12 @@ void zgemm_grouped_filter_step(int prec, int cfg, const ZGemmParams* gp, const i
 // work items are counted in tile0 as tiles_m * tiles_n * splitk, with
 // kchunk the K range of one split.
 void zgemm_grouped_reduce(int prec, const ZGemmParams* gp, const int64_t* elem0, int G, int grid, hipStream_t st);
+// The FP16 degree step (precision 3 of the solver): A in two FP16 planes
+// made by to_f16_planes (row length f16_plane_ld(n), zero padded), B, X, Z,
+// R and C complex FP32; op = N, batch 1, no flags; splitk 0 = automatic.
+int64_t f16_plane_ld(int64_t n);
+void to_f16_planes(const zc* A, int64_t lda, int64_t n, void* out, hipStream_t st);
+void zgemm_f16_step(const GemmOp& g, const GemmWork& w, hipStream_t st);
 // K slab depth of a tile configuration (0 if cfg is not one).
 int zgemm_config_bk(int cfg);
 // Whether cfg can run the grouped step; the grid that fills the device with it.

@@ -94,32 +94,54 @@ __global__ void k_c2z(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t 
   dst[i + j * ldd] = make_double2((double)v.x, (double)v.y);
 }
 
-// The FP32 filter on the Ritz residual: with Y_0 Ritz vectors (values mu),
-// R = A Y_0 - Y_0 diag(mu) formed in FP64 and rounded to FP32 (the forcing of
-// the residual part's recurrence) and that part's first iterate
-// D_1 = alpha0 R (the first degree step of eq. (2) applied to Y_0).
-__global__ void k_ritz_forcing(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu, double alpha0,
-                               cc* R, int64_t ldr, cc* D1, int64_t ldd, int64_t m, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m * n) return;
-  const int64_t i = e % m, j = e / m;
-  const zc y = Y0[i + j * ldy], w = AY0[i + j * lday];
+// The filter on the Ritz residual: with Y_0 Ritz vectors (values mu), the
+// residual R = A Y_0 - Y_0 diag(mu) of column j (one workgroup) formed in
+// FP64, scaled by the power of two s_j at or above its largest entry (1 for
+// a zero column; the scaling is exact) and rounded to FP32, with the residual
+// part's first iterate D_1 = alpha0 R / s_j (the first degree step of eq. (2)
+// applied to Y_0); scale[j] = s_j.
+__global__ void __launch_bounds__(256) k_ritz_forcing(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday,
+                                                      const double* mu, double alpha0, cc* R, int64_t ldr, cc* D1,
+                                                      int64_t ldd, double* scale, int64_t m) {
+  __shared__ double red[4];
+  const int64_t j = blockIdx.x;
+  const zc* y = Y0 + j * ldy;
+  const zc* w = AY0 + j * lday;
   const double mj = mu[j];
-  const double rx = fma(-mj, y.x, w.x), ry = fma(-mj, y.y, w.y);
-  R[i + j * ldr] = make_float2((float)rx, (float)ry);
-  D1[i + j * ldd] = make_float2((float)(alpha0 * rx), (float)(alpha0 * ry));
+  double mx = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += 256) {
+    const zc yv = y[i], wv = w[i];
+    mx = fmax(mx, fmax(fabs(fma(-mj, yv.x, wv.x)), fabs(fma(-mj, yv.y, wv.y))));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  int ex = 0;
+  (void)frexp(mx, &ex);
+  const double sc = mx > 0.0 ? ldexp(1.0, ex) : 1.0;
+  const double inv = 1.0 / sc;
+  if (threadIdx.x == 0) scale[j] = sc;
+  for (int64_t i = threadIdx.x; i < m; i += 256) {
+    const zc yv = y[i], wv = w[i];
+    const double rx = fma(-mj, yv.x, wv.x) * inv, ry = fma(-mj, yv.y, wv.y) * inv;
+    R[i + j * ldr] = make_float2((float)rx, (float)ry);
+    D1[i + j * ldd] = make_float2((float)(alpha0 * rx), (float)(alpha0 * ry));
+  }
 }
 
-// The filtered block from its two parts: F = Y_0 diag(t) + D (D widened).
-__global__ void k_ritz_combine(const zc* Y0, int64_t ldy, const double* t, const cc* D, int64_t ldd, zc* F, int64_t ldf,
-                               int64_t m, int64_t n) {
+// The filtered block from its two parts: F = Y_0 diag(t) + D diag(scale)
+// (D widened).
+__global__ void k_ritz_combine(const zc* Y0, int64_t ldy, const double* t, const double* scale, const cc* D,
+                               int64_t ldd, zc* F, int64_t ldf, int64_t m, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * n) return;
   const int64_t i = e % m, j = e / m;
   const zc y = Y0[i + j * ldy];
   const cc d = D[i + j * ldd];
-  const double tj = t[j];
-  F[i + j * ldf] = zmk(fma(tj, y.x, (double)d.x), fma(tj, y.y, (double)d.y));
+  const double tj = t[j], sj = scale[j];
+  F[i + j * ldf] = zmk(fma(tj, y.x, sj * (double)d.x), fma(tj, y.y, sj * (double)d.y));
 }
 
 __global__ void k_set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n) {
@@ -1343,15 +1365,15 @@ void to_f64(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t
 }
 
 void ritz_forcing(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu, double alpha0, cc* R,
-                  int64_t ldr, cc* D1, int64_t ldd, int64_t m, int64_t n, hipStream_t st) {
+                  int64_t ldr, cc* D1, int64_t ldd, double* scale, int64_t m, int64_t n, hipStream_t st) {
   if (m * n == 0) return;
-  LAUNCH(k_ritz_forcing, grid1(m * n), dim3(NT), 0, st, Y0, ldy, AY0, lday, mu, alpha0, R, ldr, D1, ldd, m, n);
+  LAUNCH(k_ritz_forcing, dim3((unsigned)n), dim3(256), 0, st, Y0, ldy, AY0, lday, mu, alpha0, R, ldr, D1, ldd, scale, m);
 }
 
-void ritz_combine(const zc* Y0, int64_t ldy, const double* t, const cc* D, int64_t ldd, zc* F, int64_t ldf, int64_t m,
-                  int64_t n, hipStream_t st) {
+void ritz_combine(const zc* Y0, int64_t ldy, const double* t, const double* scale, const cc* D, int64_t ldd, zc* F,
+                  int64_t ldf, int64_t m, int64_t n, hipStream_t st) {
   if (m * n == 0) return;
-  LAUNCH(k_ritz_combine, grid1(m * n), dim3(NT), 0, st, Y0, ldy, t, D, ldd, F, ldf, m, n);
+  LAUNCH(k_ritz_combine, grid1(m * n), dim3(NT), 0, st, Y0, ldy, t, scale, D, ldd, F, ldf, m, n);
 }
 
 void set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st) {

@@ -21,13 +21,15 @@ void lincomb2d(double a, const zc* X, int64_t ldx, double b, const zc* Y, int64_
 // precision conversions of an m x n block (round to nearest / exact widening)
 void to_f32(const zc* src, int64_t lds, cc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st);
 void to_f64(const cc* src, int64_t lds, zc* dst, int64_t ldd, int64_t m, int64_t n, hipStream_t st);
-// The FP32 filter on the Ritz residual (m x n blocks, mu device FP64):
-// R = (FP32) (AY0 - Y0 diag(mu)), D1 = (FP32) (alpha0 (AY0 - Y0 diag(mu)));
-// then F = Y0 diag(t) + D (t device FP64, n entries)
+// The filter on the Ritz residual (m x n blocks, mu device FP64): per
+// column j, s_j = the power of two at or above max |AY0 - Y0 mu| (1 for a
+// zero column) into scale[j], R = (FP32) ((AY0 - Y0 diag(mu)) / s_j) and
+// D1 = (FP32) (alpha0 (AY0 - Y0 diag(mu)) / s_j); then
+// F = Y0 diag(t) + D diag(scale) (t, scale device FP64, n entries)
 void ritz_forcing(const zc* Y0, int64_t ldy, const zc* AY0, int64_t lday, const double* mu, double alpha0, cc* R,
-                  int64_t ldr, cc* D1, int64_t ldd, int64_t m, int64_t n, hipStream_t st);
-void ritz_combine(const zc* Y0, int64_t ldy, const double* t, const cc* D, int64_t ldd, zc* F, int64_t ldf, int64_t m,
-                  int64_t n, hipStream_t st);
+                  int64_t ldr, cc* D1, int64_t ldd, double* scale, int64_t m, int64_t n, hipStream_t st);
+void ritz_combine(const zc* Y0, int64_t ldy, const double* t, const double* scale, const cc* D, int64_t ldd, zc* F,
+                  int64_t ldf, int64_t m, int64_t n, hipStream_t st);
 void set_identity(zc* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st);
 void zero_strict_upper(zc* A, int64_t lda, int64_t n, hipStream_t st);
 // A <- the Hermitian matrix whose lower triangle A holds (upper triangle

@@ -945,7 +945,7 @@ def _subspace_full_size(p, X, ev, nev):
     return worst
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
 def test_solve_precision_configuration_full_size(lib, precision_problem, precision):
     """n=10000, nev=600, nex=60, degree 20, FP64 throughout, mixed precision
     (the filter in complex FP32 until columns approach the tolerance,
@@ -960,7 +960,7 @@ def test_solve_precision_configuration_full_size(lib, precision_problem, precisi
     ev, X, info, st = lib.solve(ctx, p["H"], p["S"], nev, nex, tol=1e-10)
     assert st == 0
     assert (info["iterations_fp32"] > 0) == (precision >= 1)
-    if precision == 2:
+    if precision >= 2:
         assert info["filter_launches_fp32"] == info["filter_launches"]
     lam = np.sort(p["lam"])[:nev]
     H, S = p["H"], p["S"]
@@ -981,7 +981,7 @@ def test_solve_precision_configuration_full_size(lib, precision_problem, precisi
     ctx.release()
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
 def test_solve_full_size_first_problem_of_sequence(lib, precision):
     """n=4000, nev=400, nex=40, degree 20 (the benchmark's sequence, first
     problem: spectrum known by construction)."""

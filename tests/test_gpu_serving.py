@@ -114,7 +114,7 @@ def test_server_rejects_invalid_block_sizes(lib, sequences):
     srv.close()
 
 
-@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("precision", [1, 2, 3])
 def test_server_at_configuration_sizes(lib, precision):
     """Three sequences with n in the serving configuration's range (2000,
     4500, 8000; nev 3 %, 10 % and 5 % of n, nex = nev/10), two steps each,
