@@ -941,6 +941,7 @@ struct chfsi_ctx_s {
       g.R = R32.p; g.ldr = n; g.rs = ctab.d() + (size_t)i * ka;
       g.filter_step = true;
       if (half) {
+        g.cfg = opts.filter_tile;
         g.splitk = opts.filter_splitk;
         zgemm_f16_step(g, gw(), st);
       } else {

@@ -15,12 +15,15 @@
 // D, the partial tiles and the output in complex FP32 (interleaved, column
 // major).  One step computes
 //   C = alpha A B + beta X + gamma Z + R diag(rs)
-// over a 64 x 64 output tile per workgroup of four waves (2 x 2, 32 x 32
-// each as 2 x 2 fragments of 16 x 16), K in slabs of 32 staged through LDS
-// and double buffered; each complex product is four real products.  As in
+// over a 128 x 64 output tile per workgroup of four waves (2 x 2, 64 x 32
+// each as 4 x 2 fragments of 16 x 16; 64 x 64 and 128 x 128 tiles can be
+// asked for), K in slabs of 32 staged through LDS and double buffered; each
+// complex product is four real products.  As in
 // the FP64 and FP32 steps, the product is formed transposed inside the
 // matrix instruction (the B fragment first), so a wave's result lanes run
 // down an output column.
+#include <mutex>
+
 #include "gemm.hpp"
 
 namespace chfsi {
@@ -29,10 +32,8 @@ namespace {
 
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 
-constexpr int HB = 64;          // tile rows and columns
 constexpr int HK = 32;          // slab depth (one matrix instruction per fragment pair and real product)
 constexpr int HLD = HK + 8;     // LDS row stride in halves: 80 bytes, so 16 lanes' 16-byte reads hit distinct banks
-constexpr int HNT = 256;        // threads
 
 __device__ __forceinline__ int64_t xcd_tile_h(int64_t bid, int64_t ntiles) {
   const int64_t full = (ntiles / 8) * 8;
@@ -43,16 +44,25 @@ __device__ __forceinline__ f4v mfma_h(h8v a, h8v b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-__global__ void __launch_bounds__(HNT, 2) chebyshev_step_f16(ZGemmParams p) {
-  __shared__ __attribute__((aligned(16))) _Float16 As[2][2][HB][HLD];  // [buffer][re, im][row m][k]
-  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][2][HB][HLD];  // [buffer][re, im][column n][k]
+// One step over a BM x BN output tile per workgroup of WM x WN waves, each
+// wave (BM / WM) x (BN / WN) as 16 x 16 fragments.  LDS (dynamic):
+// [buffer][re, im][row m][k] for A, then [buffer][re, im][column n][k] for B.
+template <int BM, int BN, int WM, int WN, int MINB>
+__global__ void __launch_bounds__(64 * WM * WN, MINB) chebyshev_step_f16(ZGemmParams p) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int MI = BM / (16 * WM), NJ = BN / (16 * WN);
+  constexpr int AQ = BM * 4 / NT, BQ = BN * 4 / NT;  // rows / columns of a slab per thread
+  static_assert(AQ >= 1 && BQ >= 1 && BM * 4 % NT == 0 && BN * 4 % NT == 0, "slab share");
+  extern __shared__ __attribute__((aligned(16))) _Float16 hsm[];
+  auto as_ = [&](int buf, int pl, int row) { return hsm + ((buf * 2 + pl) * BM + row) * HLD; };
+  auto bs_ = [&](int buf, int pl, int col) { return hsm + 4 * BM * HLD + ((buf * 2 + pl) * BN + col) * HLD; };
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int wm0 = (wave & 1) * 32, wn0 = (wave >> 1) * 32;
+  const int wm0 = (wave % WM) * (BM / WM), wn0 = (wave / WM) * (BN / WN);
 
   const int64_t t = xcd_tile_h(blockIdx.x, (int64_t)p.tiles_m * p.tiles_n);
-  const int64_t m0 = (t / p.tiles_n) * HB, n0 = (t % p.tiles_n) * HB;
+  const int64_t m0 = (t / p.tiles_n) * BM, n0 = (t % p.tiles_n) * BN;
   const int split = (int)blockIdx.y;
   const int64_t kbeg = (int64_t)split * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
@@ -62,54 +72,67 @@ __global__ void __launch_bounds__(HNT, 2) chebyshev_step_f16(ZGemmParams p) {
   const _Float16* __restrict__ Aim = Are + p.M * p.lda;
   const cc* __restrict__ B = static_cast<const cc*>(p.B);
 
-  // this thread's share of a slab: row (A) / column (B) tid / 4, eight
-  // consecutive k from 8 (tid % 4)
+  // this thread's share of a slab: rows (A) / columns (B) tid / 4 + q NT / 4,
+  // eight consecutive k from 8 (tid % 4)
   const int lrow = tid >> 2, lk8 = (tid & 3) * 8;
-  const int64_t gm = m0 + lrow, gn = n0 + lrow;
-  uint4 ra_re, ra_im;
-  h8v rb_re, rb_im;
+  uint4 ra_re[AQ], ra_im[AQ];
+  h8v rb_re[BQ], rb_im[BQ];
 
   auto load_slab = [&](int64_t k0) {
     const int64_t k = k0 + lk8;
     // A: rows are zero-padded to lda (a multiple of 64) and chunk ends are
     // multiples of the slab depth, so only the row needs a check
-    if (gm < p.M) {
-      ra_re = *reinterpret_cast<const uint4*>(Are + gm * p.lda + k);
-      ra_im = *reinterpret_cast<const uint4*>(Aim + gm * p.lda + k);
-    } else {
-      ra_re = make_uint4(0, 0, 0, 0);
-      ra_im = make_uint4(0, 0, 0, 0);
-    }
-    if (gn < p.N && k + 8 <= kend) {
-      const cc* col = B + gn * p.ldb + k;
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const cc v = col[j];
-        rb_re[j] = (_Float16)v.x;
-        rb_im[j] = (_Float16)v.y;
+    for (int q = 0; q < AQ; q++) {
+      const int64_t gm = m0 + lrow + q * (NT / 4);
+      if (gm < p.M) {
+        ra_re[q] = *reinterpret_cast<const uint4*>(Are + gm * p.lda + k);
+        ra_im[q] = *reinterpret_cast<const uint4*>(Aim + gm * p.lda + k);
+      } else {
+        ra_re[q] = make_uint4(0, 0, 0, 0);
+        ra_im[q] = make_uint4(0, 0, 0, 0);
       }
-    } else {
+    }
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        cc v = make_float2(0.f, 0.f);
-        if (gn < p.N && k + j < kend) v = B[gn * p.ldb + k + j];
-        rb_re[j] = (_Float16)v.x;
-        rb_im[j] = (_Float16)v.y;
+    for (int q = 0; q < BQ; q++) {
+      const int64_t gn = n0 + lrow + q * (NT / 4);
+      if (gn < p.N && k + 8 <= kend) {
+        const cc* col = B + gn * p.ldb + k;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const cc v = col[j];
+          rb_re[q][j] = (_Float16)v.x;
+          rb_im[q][j] = (_Float16)v.y;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          cc v = make_float2(0.f, 0.f);
+          if (gn < p.N && k + j < kend) v = B[gn * p.ldb + k + j];
+          rb_re[q][j] = (_Float16)v.x;
+          rb_im[q][j] = (_Float16)v.y;
+        }
       }
     }
   };
   auto store_slab = [&](int buf) {
-    *reinterpret_cast<uint4*>(&As[buf][0][lrow][lk8]) = ra_re;
-    *reinterpret_cast<uint4*>(&As[buf][1][lrow][lk8]) = ra_im;
-    *reinterpret_cast<h8v*>(&Bs[buf][0][lrow][lk8]) = rb_re;
-    *reinterpret_cast<h8v*>(&Bs[buf][1][lrow][lk8]) = rb_im;
+#pragma unroll
+    for (int q = 0; q < AQ; q++) {
+      *reinterpret_cast<uint4*>(as_(buf, 0, lrow + q * (NT / 4)) + lk8) = ra_re[q];
+      *reinterpret_cast<uint4*>(as_(buf, 1, lrow + q * (NT / 4)) + lk8) = ra_im[q];
+    }
+#pragma unroll
+    for (int q = 0; q < BQ; q++) {
+      *reinterpret_cast<h8v*>(bs_(buf, 0, lrow + q * (NT / 4)) + lk8) = rb_re[q];
+      *reinterpret_cast<h8v*>(bs_(buf, 1, lrow + q * (NT / 4)) + lk8) = rb_im[q];
+    }
   };
 
-  f4v accR[2][2], accI[2][2];
+  f4v accR[MI][NJ], accI[MI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; i++)
+  for (int i = 0; i < MI; i++)
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
+    for (int j = 0; j < NJ; j++) {
       accR[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
       accI[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
     }
@@ -121,36 +144,36 @@ __global__ void __launch_bounds__(HNT, 2) chebyshev_step_f16(ZGemmParams p) {
     for (int64_t s = 0; s < nslab; s++) {
       const int buf = (int)(s & 1);
       if (s + 1 < nslab) load_slab(kbeg + (s + 1) * HK);
-      h8v a_re[2], a_im[2], b_re[2], b_im[2], nb_im[2];
+      h8v a_re[MI], a_im[MI], b_re[NJ], b_im[NJ], nb_im[NJ];
 #pragma unroll
-      for (int i = 0; i < 2; i++) {
-        a_re[i] = *reinterpret_cast<const h8v*>(&As[buf][0][wm0 + 16 * i + lr][8 * lk]);
-        a_im[i] = *reinterpret_cast<const h8v*>(&As[buf][1][wm0 + 16 * i + lr][8 * lk]);
+      for (int i = 0; i < MI; i++) {
+        a_re[i] = *reinterpret_cast<const h8v*>(as_(buf, 0, wm0 + 16 * i + lr) + 8 * lk);
+        a_im[i] = *reinterpret_cast<const h8v*>(as_(buf, 1, wm0 + 16 * i + lr) + 8 * lk);
       }
 #pragma unroll
-      for (int j = 0; j < 2; j++) {
-        b_re[j] = *reinterpret_cast<const h8v*>(&Bs[buf][0][wn0 + 16 * j + lr][8 * lk]);
-        b_im[j] = *reinterpret_cast<const h8v*>(&Bs[buf][1][wn0 + 16 * j + lr][8 * lk]);
+      for (int j = 0; j < NJ; j++) {
+        b_re[j] = *reinterpret_cast<const h8v*>(bs_(buf, 0, wn0 + 16 * j + lr) + 8 * lk);
+        b_im[j] = *reinterpret_cast<const h8v*>(bs_(buf, 1, wn0 + 16 * j + lr) + 8 * lk);
         nb_im[j] = -b_im[j];
       }
       // D[n][m] += B[k][n] A[m][k]: re = Br Ar - Bi Ai, im = Bi Ar + Br Ai,
-      // issued type by type (dependent accumulations four instructions apart)
+      // issued type by type (dependent accumulations MI NJ instructions apart)
 #pragma unroll
-      for (int i = 0; i < 2; i++)
+      for (int i = 0; i < MI; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) accR[i][j] = mfma_h(b_re[j], a_re[i], accR[i][j]);
+        for (int j = 0; j < NJ; j++) accR[i][j] = mfma_h(b_re[j], a_re[i], accR[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; i++)
+      for (int i = 0; i < MI; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) accI[i][j] = mfma_h(b_im[j], a_re[i], accI[i][j]);
+        for (int j = 0; j < NJ; j++) accI[i][j] = mfma_h(b_im[j], a_re[i], accI[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; i++)
+      for (int i = 0; i < MI; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) accR[i][j] = mfma_h(nb_im[j], a_im[i], accR[i][j]);
+        for (int j = 0; j < NJ; j++) accR[i][j] = mfma_h(nb_im[j], a_im[i], accR[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; i++)
+      for (int i = 0; i < MI; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) accI[i][j] = mfma_h(b_re[j], a_im[i], accI[i][j]);
+        for (int j = 0; j < NJ; j++) accI[i][j] = mfma_h(b_re[j], a_im[i], accI[i][j]);
       // the next slab into the other buffer (last read before the previous barrier)
       if (s + 1 < nslab) store_slab(buf ^ 1);
       __syncthreads();
@@ -161,9 +184,9 @@ __global__ void __launch_bounds__(HNT, 2) chebyshev_step_f16(ZGemmParams p) {
   if (p.splitk > 1) {
     cc* P = static_cast<cc*>(p.P) + (int64_t)split * p.M * p.N;
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < MI; i++)
 #pragma unroll
-      for (int j = 0; j < 2; j++)
+      for (int j = 0; j < NJ; j++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
           const int64_t m = m0 + wm0 + 16 * i + lr;
@@ -178,9 +201,9 @@ __global__ void __launch_bounds__(HNT, 2) chebyshev_step_f16(ZGemmParams p) {
   const cc* Rf = static_cast<const cc*>(p.R);
   const float al = (float)p.alpha, be = (float)p.beta, ga = (float)p.gamma;
 #pragma unroll
-  for (int i = 0; i < 2; i++)
+  for (int i = 0; i < MI; i++)
 #pragma unroll
-    for (int j = 0; j < 2; j++)
+    for (int j = 0; j < NJ; j++)
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int64_t m = m0 + wm0 + 16 * i + lr;
@@ -267,6 +290,36 @@ void to_f16_planes(const zc* A, int64_t lda, int64_t n, void* out, hipStream_t s
   CHFSI_CHECK_LAUNCH();
 }
 
+namespace {
+
+template <int BM, int BN, int WM, int WN, int MINB>
+void launch_f16(ZGemmParams& p, const GemmOp& g, const GemmWork& w, hipStream_t st) {
+  constexpr size_t shm = (size_t)4 * (BM + BN) * HLD * sizeof(_Float16);
+  static std::once_flag attr;
+  std::call_once(attr, [&] {
+    CHFSI_HIP(hipFuncSetAttribute((const void*)chebyshev_step_f16<BM, BN, WM, WN, MINB>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  });
+  p.tiles_m = (int)cdiv(g.M, BM);
+  p.tiles_n = (int)cdiv(g.N, BN);
+  const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+  // K split: enough workgroups to fill the device several times over,
+  // chunks at least 256 deep, within the partial-tile scratch
+  const int64_t want = BM * BN >= 128 * 128 ? 512 : 1024;
+  int64_t sk = g.splitk > 0 ? g.splitk : std::min<int64_t>(16, cdiv(want, tiles));
+  sk = std::max<int64_t>(1, std::min<int64_t>(sk, g.K / 256));
+  const size_t cap = 2 * w.P_elems;  // complex FP32 elements
+  while (sk > 1 && (!w.P || (size_t)sk * g.M * g.N > cap)) sk--;
+  p.kchunk = cdiv(cdiv(g.K, sk), (int64_t)HK) * HK;
+  p.splitk = (int)cdiv(g.K, p.kchunk);
+  p.P = p.splitk > 1 ? (void*)w.P : nullptr;
+  hipLaunchKernelGGL((chebyshev_step_f16<BM, BN, WM, WN, MINB>), dim3((unsigned)tiles, (unsigned)p.splitk),
+                     dim3(64 * WM * WN), shm, st, p);
+  CHFSI_CHECK_LAUNCH();
+}
+
+}  // namespace
+
 void zgemm_f16_step(const GemmOp& g, const GemmWork& w, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return;
   if (g.opA != OP_N || g.opB != OP_N || g.flags || (g.batch > 1) || g.lda % 64 != 0 || g.lda < g.K ||
@@ -281,20 +334,17 @@ void zgemm_f16_step(const GemmOp& g, const GemmWork& w, hipStream_t st) {
   p.Z = g.Z; p.ldz = g.ldz;
   p.alpha = g.alpha; p.beta = g.beta; p.gamma = g.gamma;
   p.R = g.R; p.ldr = g.ldr; p.rs = g.rs;
-  p.tiles_m = (int)cdiv(g.M, HB);
-  p.tiles_n = (int)cdiv(g.N, HB);
-  const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
-  // K split: enough workgroups to fill the device several times over (four
-  // per CU), chunks at least 256 deep, within the partial-tile scratch
-  int64_t sk = g.splitk > 0 ? g.splitk : std::min<int64_t>(16, cdiv(1024, tiles));
-  sk = std::max<int64_t>(1, std::min<int64_t>(sk, g.K / 256));
-  const size_t cap = 2 * w.P_elems;  // complex FP32 elements
-  while (sk > 1 && (!w.P || (size_t)sk * g.M * g.N > cap)) sk--;
-  p.kchunk = cdiv(cdiv(g.K, sk), (int64_t)HK) * HK;
-  p.splitk = (int)cdiv(g.K, p.kchunk);
-  p.P = p.splitk > 1 ? (void*)w.P : nullptr;
-  hipLaunchKernelGGL(chebyshev_step_f16, dim3((unsigned)tiles, (unsigned)p.splitk), dim3(HNT), 0, st, p);
-  CHFSI_CHECK_LAUNCH();
+  // tile shape (the FP64 / FP32 numbering: 1 = 64 x 64, 4 = 128 x 64,
+  // 6 = 128 x 128); automatic: 128 x 64, the fastest or within 2 % at every
+  // width measured (16 to 600 columns at n = 4000 and 10000; 128 x 128 holds
+  // one workgroup per CU and trails it by 5-40 %)
+  const int cfg = g.cfg == 0 ? 4 : g.cfg;
+  switch (cfg) {
+    case 1: launch_f16<64, 64, 2, 2, 4>(p, g, w, st); break;    // 40 KB of LDS: four per CU
+    case 4: launch_f16<128, 64, 2, 2, 2>(p, g, w, st); break;   // 60 KB: two per CU
+    case 6: launch_f16<128, 128, 2, 4, 2>(p, g, w, st); break;  // 80 KB: two per CU
+    default: throw Error(ST_EINVAL, "FP16 step: tile configuration 0, 1, 4 or 6");
+  }
   if (p.splitk > 1) {
     hipLaunchKernelGGL(chebyshev_step_reduce_f16, dim3((unsigned)cdiv(g.M * g.N, 256)), dim3(256), 0, st, p);
     CHFSI_CHECK_LAUNCH();

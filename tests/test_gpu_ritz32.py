@@ -58,11 +58,12 @@ def _ritz_block(n, k, delta, seed):
 # (precision, n, k, tile, split): one tile of each family the FP32 step
 # takes, with and without a K split (the forcing term is added in the step's
 # epilogue or in the split-K combination), ragged row and column tails; the
-# FP16 step (one tile shape) with and without splits
+# FP16 step's three tile shapes (0: automatic, 128 x 64; 1: 64 x 64; 6:
+# 128 x 128) with and without splits
 CASES = [(2, 700, 70, 0, 0), (2, 700, 70, 1, 1), (2, 700, 70, 1, 4), (2, 650, 45, 10, 1), (2, 650, 45, 10, 3),
          (2, 900, 150, 12, 2), (2, 900, 150, 11, 1), (2, 900, 150, 3, 2),
          (3, 700, 70, 0, 0), (3, 700, 70, 0, 1), (3, 700, 70, 0, 4), (3, 650, 45, 0, 3), (3, 900, 150, 0, 2),
-         (3, 1100, 130, 0, 0)]
+         (3, 1100, 130, 0, 0), (3, 700, 70, 1, 0), (3, 650, 45, 1, 3), (3, 900, 150, 6, 2), (3, 1100, 130, 6, 0)]
 BOUND = {2: 1e-10, 3: 1e-7}
 # outer iterations allowed beyond the FP64 solve's (CPU emulations of both
 # forms took the FP64 count at n = 600 and 1500)
