@@ -136,7 +136,8 @@ struct chfsi_ctx_s {
   // n x n: standard form, Cholesky factor, its inverse, work; FP32 copy of A
   DBuf A, L, Linv, W, A32;
   // FP16 planes of A (precision 3: two planes of n rows, f16_plane_ld(n) halves each)
-  DBuf A16;
+  // and of the residual part's two iterates (each two planes of k columns)
+  DBuf A16, D16;
   // FP32 filter blocks (mixed precision); the FP32 filter on the Ritz
   // residual: its forcing R (n x k, FP32) and the scalar recurrence's table
   DBuf Y32, Y32b, R32, ctab;
@@ -307,7 +308,7 @@ struct chfsi_ctx_s {
   void sync() { CHFSI_HIP(hipStreamSynchronize(st)); }
 
   void free_all() {
-    for (DBuf* b : {&A32, &A16, &Y32, &Y32b, &R32, &ctab, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
+    for (DBuf* b : {&A32, &A16, &D16, &Y32, &Y32b, &R32, &ctab, &A, &L, &Linv, &W, &Y, &Yb, &F, &Qb, &Wk, &Wz, &G, &Z, &Z2, &G2, &Ztmp, &mu, &rho, &rank, &norms,
                     &flags, &P, &hpart, &htop, &tau, &Tall, &gram, &Vp, &Wt, &W2, &LV, &Lw, &Lh, &Lab, &mvpart, &Tsm,
                     &Tz, &Tz2, &Tw, &npart, &jint, &jrot, &bjv, &rf, &rfl, &rfc})
       b->release();
@@ -926,6 +927,19 @@ struct chfsi_ctx_s {
     cc* cur = (cc*)Y32b.p;
     cc* prev = (cc*)Y32.p;
     ritz_prepare(Y0, ldy, AY0, lday, mu_d, mu_h, ka, cs, cur);
+    // FP16 steps: each iterate also as FP16 planes (written by the step
+    // that forms it, read as the next step's operand); rows n .. ld16 - 1
+    // stay zero
+    const int64_t ld16 = f16_plane_ld(n), pl16 = ka * ld16;
+    _Float16 *h_cur = nullptr, *h_prev = nullptr;
+    if (half && m > 1) {
+      const size_t bytes = (size_t)4 * pl16 * sizeof(_Float16);
+      D16.ensure(bytes);
+      CHFSI_HIP(hipMemsetAsync(D16.p, 0, bytes, st));
+      h_cur = (_Float16*)D16.p;
+      h_prev = h_cur + 2 * pl16;
+      to_f16_cols(cur, n, n, ka, h_cur, ld16, pl16, st);
+    }
     if (prof) CHFSI_HIP(hipEventRecord(ev[0].a, st));
     for (int i = 1; i < m; i++) {
       GemmOp g;
@@ -943,7 +957,12 @@ struct chfsi_ctx_s {
       if (half) {
         g.cfg = opts.filter_tile;
         g.splitk = opts.filter_splitk;
+        g.B16 = h_cur;
+        g.C16 = i + 1 < m ? h_prev : nullptr;  // the last iterate feeds no product
+        g.ld16 = ld16;
+        g.pl16 = pl16;
         zgemm_f16_step(g, gw(), st);
+        std::swap(h_cur, h_prev);
       } else {
         g.cfg = opts.filter_tile;
         g.splitk = opts.filter_splitk;
@@ -1594,7 +1613,7 @@ size_t ctx_footprint(int64_t n, int64_t k, int precision, int degree) {
                   (size_t)64 * n);
   if (precision >= 1) b += sizeof(cc) * ((size_t)n * n + (size_t)2 * n * k);
   if (precision >= 2) b += sizeof(cc) * (size_t)n * k + sizeof(double) * (size_t)(degree + 2) * k;
-  if (precision == 3) b += (size_t)4 * n * f16_plane_ld(n);
+  if (precision == 3) b += (size_t)4 * n * f16_plane_ld(n) + (size_t)8 * k * f16_plane_ld(n);
   return b;
 }
 

@@ -49,6 +49,12 @@ struct GemmOp {
   // of the filter's Ritz-residual recurrence
   const void* R = nullptr; int64_t ldr = 0;
   const double* rs = nullptr;
+  // FP16 steps only: B also as FP16 planes (column n holding its k
+  // consecutively: re at B16 + n ld16, im pl16 halves further; zero from
+  // row K to ld16), and C also written there (C16, same layout), the next
+  // step's B; null: B read as FP32, no FP16 copy of C
+  const void* B16 = nullptr; void* C16 = nullptr;
+  int64_t ld16 = 0, pl16 = 0;
 };
 
 // Scratch for split-K partial tiles (P_elems complex FP64 elements; an FP32
@@ -73,6 +79,8 @@ struct ZGemmParams {
   int tiles_m, tiles_n;
   const void* R; int64_t ldr;  // FP32 only: out(:, j) += rs[j] R(:, j) (null: none)
   const double* rs;
+  const void* B16; void* C16;  // FP16 steps only: FP16 planes of B and of the output
+  int64_t ld16, pl16;
 };
 
 void zgemm(const GemmOp& g, const GemmWork& w, hipStream_t st);
@@ -99,6 +107,9 @@ void zgemm_grouped_reduce(int prec, const ZGemmParams* gp, const int64_t* elem0,
 int64_t f16_plane_ld(int64_t n);
 void to_f16_planes(const zc* A, int64_t lda, int64_t n, void* out, hipStream_t st);
 void zgemm_f16_step(const GemmOp& g, const GemmWork& w, hipStream_t st);
+// The FP16 planes (B16 layout above) of an m x ncols complex FP32 block.
+void to_f16_cols(const cc* D, int64_t ldd, int64_t m, int64_t ncols, void* out, int64_t ld16, int64_t pl16,
+                 hipStream_t st);
 // K slab depth of a tile configuration (0 if cfg is not one).
 int zgemm_config_bk(int cfg);
 // Whether cfg can run the grouped step; the grid that fills the device with it.

@@ -16,9 +16,12 @@
 // major).  One step computes
 //   C = alpha A B + beta X + gamma Z + R diag(rs)
 // over a 128 x 64 output tile per workgroup of four waves (2 x 2, 64 x 32
-// each as 4 x 2 fragments of 16 x 16; 64 x 64 and 128 x 128 tiles can be
-// asked for), K in slabs of 32 staged through LDS and double buffered; each
-// complex product is four real products.  As in
+// each as 4 x 2 fragments of 16 x 16), or 64 x 64 (32 x 32 per wave) for
+// 65-160 columns (a 128 x 128 tile can be asked for), K in slabs of 32
+// staged through LDS and double buffered; each complex product is four real
+// products.  B is read as FP16 planes that the previous step's epilogue
+// wrote beside its FP32 output (or, without them, as FP32 converted on the
+// way into LDS).  As in
 // the FP64 and FP32 steps, the product is formed transposed inside the
 // matrix instruction (the B fragment first), so a wave's result lanes run
 // down an output column.
@@ -71,6 +74,7 @@ __global__ void __launch_bounds__(64 * WM * WN, MINB) chebyshev_step_f16(ZGemmPa
   const _Float16* __restrict__ Are = static_cast<const _Float16*>(p.A);
   const _Float16* __restrict__ Aim = Are + p.M * p.lda;
   const cc* __restrict__ B = static_cast<const cc*>(p.B);
+  const _Float16* __restrict__ B16 = static_cast<const _Float16*>(p.B16);
 
   // this thread's share of a slab: rows (A) / columns (B) tid / 4 + q NT / 4,
   // eight consecutive k from 8 (tid % 4)
@@ -92,6 +96,22 @@ __global__ void __launch_bounds__(64 * WM * WN, MINB) chebyshev_step_f16(ZGemmPa
         ra_re[q] = make_uint4(0, 0, 0, 0);
         ra_im[q] = make_uint4(0, 0, 0, 0);
       }
+    }
+    if (B16) {
+      // the previous step's FP16 copy: zero from row K on, so only the
+      // column needs a check
+#pragma unroll
+      for (int q = 0; q < BQ; q++) {
+        const int64_t gn = n0 + lrow + q * (NT / 4);
+        if (gn < p.N) {
+          rb_re[q] = *reinterpret_cast<const h8v*>(B16 + gn * p.ld16 + k);
+          rb_im[q] = *reinterpret_cast<const h8v*>(B16 + p.pl16 + gn * p.ld16 + k);
+        } else {
+          rb_re[q] = h8v{};
+          rb_im[q] = h8v{};
+        }
+      }
+      return;
     }
 #pragma unroll
     for (int q = 0; q < BQ; q++) {
@@ -199,6 +219,7 @@ __global__ void __launch_bounds__(64 * WM * WN, MINB) chebyshev_step_f16(ZGemmPa
   const cc* X = static_cast<const cc*>(p.X);
   const cc* Z = static_cast<const cc*>(p.Z);
   const cc* Rf = static_cast<const cc*>(p.R);
+  _Float16* C16 = static_cast<_Float16*>(p.C16);
   const float al = (float)p.alpha, be = (float)p.beta, ga = (float)p.gamma;
 #pragma unroll
   for (int i = 0; i < MI; i++)
@@ -227,6 +248,10 @@ __global__ void __launch_bounds__(64 * WM * WN, MINB) chebyshev_step_f16(ZGemmPa
             vy += sc * rv.y;
           }
           C[m + n * p.ldc] = make_float2(vx, vy);
+          if (C16) {
+            C16[n * p.ld16 + m] = (_Float16)vx;
+            C16[p.pl16 + n * p.ld16 + m] = (_Float16)vy;
+          }
         }
       }
 }
@@ -263,6 +288,23 @@ __global__ void __launch_bounds__(256) chebyshev_step_reduce_f16(ZGemmParams p) 
     vy += sc * rv.y;
   }
   static_cast<cc*>(p.C)[m + n * p.ldc] = make_float2(vx, vy);
+  if (p.C16) {
+    _Float16* C16 = static_cast<_Float16*>(p.C16);
+    C16[n * p.ld16 + m] = (_Float16)vx;
+    C16[p.pl16 + n * p.ld16 + m] = (_Float16)vy;
+  }
+}
+
+// FP16 planes of an m x ncols complex FP32 block (column n: re at
+// out + n ld16, im pl16 further; rows m .. ld16 - 1 left as they are).
+__global__ void k_c2h_cols(const cc* D, int64_t ldd, int64_t m, int64_t ncols, _Float16* out, int64_t ld16,
+                           int64_t pl16) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * ncols) return;
+  const int64_t i = e % m, j = e / m;
+  const cc v = D[i + j * ldd];
+  out[j * ld16 + i] = (_Float16)v.x;
+  out[pl16 + j * ld16 + i] = (_Float16)v.y;
 }
 
 // out: the two FP16 planes of the n x n Hermitian A (column major, lda):
@@ -320,10 +362,19 @@ void launch_f16(ZGemmParams& p, const GemmOp& g, const GemmWork& w, hipStream_t 
 
 }  // namespace
 
+void to_f16_cols(const cc* D, int64_t ldd, int64_t m, int64_t ncols, void* out, int64_t ld16, int64_t pl16,
+                 hipStream_t st) {
+  if (m * ncols == 0) return;
+  hipLaunchKernelGGL(k_c2h_cols, dim3((unsigned)cdiv(m * ncols, 256)), dim3(256), 0, st, D, ldd, m, ncols,
+                     static_cast<_Float16*>(out), ld16, pl16);
+  CHFSI_CHECK_LAUNCH();
+}
+
 void zgemm_f16_step(const GemmOp& g, const GemmWork& w, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return;
   if (g.opA != OP_N || g.opB != OP_N || g.flags || (g.batch > 1) || g.lda % 64 != 0 || g.lda < g.K ||
-      g.ldb < g.K || (g.R && (!g.rs || g.ldr < g.M)))
+      g.ldb < g.K || (g.R && (!g.rs || g.ldr < g.M)) ||
+      ((g.B16 || g.C16) && (g.ld16 % 64 != 0 || g.ld16 < g.K || g.ld16 < g.M || g.pl16 < g.N * g.ld16)))
     throw Error(ST_EINVAL, "FP16 step: op = N, batch 1, no flags, lda a multiple of 64 and >= K");
   ZGemmParams p{};
   p.M = g.M; p.N = g.N; p.K = g.K;
@@ -334,11 +385,13 @@ void zgemm_f16_step(const GemmOp& g, const GemmWork& w, hipStream_t st) {
   p.Z = g.Z; p.ldz = g.ldz;
   p.alpha = g.alpha; p.beta = g.beta; p.gamma = g.gamma;
   p.R = g.R; p.ldr = g.ldr; p.rs = g.rs;
+  p.B16 = g.B16; p.C16 = g.C16; p.ld16 = g.ld16; p.pl16 = g.pl16;
   // tile shape (the FP64 / FP32 numbering: 1 = 64 x 64, 4 = 128 x 64,
-  // 6 = 128 x 128); automatic: 128 x 64, the fastest or within 2 % at every
-  // width measured (16 to 600 columns at n = 4000 and 10000; 128 x 128 holds
-  // one workgroup per CU and trails it by 5-40 %)
-  const int cfg = g.cfg == 0 ? 4 : g.cfg;
+  // 6 = 128 x 128); automatic: 64 x 64 for 65-160 columns (3-9 % faster
+  // there at n = 4000 and 10000), else 128 x 64 (the fastest or within 4 %
+  // at the other widths measured, 48 to 600; 128 x 128 holds one workgroup
+  // per CU and trails by up to 35 % at narrow widths)
+  const int cfg = g.cfg != 0 ? g.cfg : (g.N > 64 && g.N <= 160 ? 1 : 4);
   switch (cfg) {
     case 1: launch_f16<64, 64, 2, 2, 4>(p, g, w, st); break;    // 40 KB of LDS: four per CU
     case 4: launch_f16<128, 64, 2, 2, 2>(p, g, w, st); break;   // 60 KB: two per CU
