@@ -589,7 +589,7 @@ def run_serve(args):
               "nev": "uniform 3-20% of n", "nex": "nev/10", "arrival_rate_per_s": rate,
               "workers": args.workers, "hbm_budget_gb": args.budget_gb, "degree": 20, "tol": 1e-10}
     sp = args.serve_precision
-    pname = {1: "mixed precision", 2: "FP32 filter on the Ritz residual"}[sp]
+    pname = {1: "mixed precision", 2: "FP32 filter on the Ritz residual", 3: "FP16-operand filter on the Ritz residual"}[sp]
     if args.serve_paths != "both":
         plain_only = args.serve_paths == "plain"
         st, elapsed, res = (serve(1, 0, "plain FP64, one worker") if plain_only else
@@ -840,8 +840,9 @@ def main():
     ap.add_argument("--workers", type=int, default=4, help="serving workers")
     ap.add_argument("--batch-precision", type=int, choices=[1, 2], default=2,
                     help="batch form: the filter of both passes (1: FP32 with FP64 final sweeps, 2: FP32 on the Ritz residual)")
-    ap.add_argument("--serve-precision", type=int, choices=[1, 2], default=2,
-                    help="serve form: the server's filter (1: FP32 with FP64 final sweeps, 2: FP32 on the Ritz residual)")
+    ap.add_argument("--serve-precision", type=int, choices=[1, 2, 3], default=3,
+                    help="serve form: the server's filter (1: FP32 with FP64 final sweeps, 2: FP32 on the Ritz residual, "
+                         "3: FP16 operands on the Ritz residual)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving device-memory budget")
     ap.add_argument("--wc-n", type=int, default=4000, help="problem size of the warm/cold study")
     ap.add_argument("--gen-rng", choices=["host", "device"], default="host",

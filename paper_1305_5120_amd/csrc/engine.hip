@@ -1275,6 +1275,7 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
   zc* Qb = c->Qb.z();
   // start block
   bool warm = false;
+  bool start_ritz = false;  // Y holds Ritz vectors, their values in mu, A Y in Wz
   // the kept block survived the reduction (it is in the current standard form)
   const bool kept = use_state && c->warm_valid;
   if (explicit_warm) {
@@ -1302,16 +1303,23 @@ void solve_begin(chfsi_ctx c, SolveState& s) {
     s.a0 = c->warm_a0;
     s.a = c->warm_a;
   } else {
-    c->rayleigh_ritz(c->A.z(), n, Qb, n, k, Y, n, c->mu.d(), c->Wk.z(), nullptr);
+    // the filter on the Ritz residual takes this step's Ritz vectors, values
+    // and A Y (W Z) for its first iteration too
+    c->rayleigh_ritz(c->A.z(), n, Qb, n, k, Y, n, c->mu.d(), c->Wk.z(), s.ritz ? c->Wz.z() : nullptr);
     double* hb = c->hbuf;
     CHFSI_HIP(hipMemcpyAsync(hb, c->mu.d(), k * sizeof(double), hipMemcpyDeviceToHost, st));
     c->sync();
     s.a0 = std::min(inf.theta_min, hb[0]);
     s.a = hb[k - 1];
+    start_ritz = s.ritz;
   }
   inf.warm_start = warm ? 1 : 0;
   c->warm_valid = false;  // the block is being rewritten
   s.lam.assign(k, NAN);
+  if (start_ritz) {
+    std::copy(c->hbuf, c->hbuf + k, s.lam.begin());
+    s.wz_first = 0;
+  }
   s.rho_lock.assign(k, 0.0);
   s.rho_last.assign(k, INFINITY);
   s.cl = 0;
