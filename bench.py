@@ -327,8 +327,9 @@ def _exact_errors(p, evals):
 
 
 def run_precision(args):
-    """One n = 10000 problem solved cold in FP64 and with the two mixed filters
-    (precision 1: FP64 final sweeps; precision 2: FP32 on the Ritz residual)."""
+    """One n = 10000 problem solved cold in FP64 and with the three mixed
+    filters (precision 1: FP64 final sweeps; 2: FP32 on the Ritz residual;
+    3: FP16 operands on the Ritz residual)."""
     import torch
     from paper_1305_5120_amd import chfsi
     import workloads
@@ -336,7 +337,7 @@ def run_precision(args):
     p = workloads.make_problem_torch(n, 2, device="cuda")
     torch.cuda.synchronize()
     res = {}
-    for prec in (0, 1, 2):
+    for prec in (0, 1, 2, 3):
         ctx = chfsi.create(n, degree=m, seed=0, precision=prec, profile=1)
         times = []
         for i in range(args.warmup + args.steps):
@@ -357,9 +358,10 @@ def run_precision(args):
             f"; filter kernels FP64 {info['filter_kernel_seconds'] - info['filter_kernel_seconds_fp32']:.2f} s, "
             f"FP32 {info['filter_kernel_seconds_fp32']:.2f} s")
         ctx.release()
-    i64, i32, ir = res[0]["info"], res[1]["info"], res[2]["info"]
+    i64, i32, ir, ih = res[0]["info"], res[1]["info"], res[2]["info"], res[3]["info"]
     f32 = i32["filter_flops_fp32"] / i32["filter_kernel_seconds_fp32"] / 1e12 if i32["filter_kernel_seconds_fp32"] else None
     fr = ir["filter_flops_fp32"] / ir["filter_kernel_seconds_fp32"] / 1e12 if ir["filter_kernel_seconds_fp32"] else None
+    fh = ih["filter_flops_fp32"] / ih["filter_kernel_seconds_fp32"] / 1e12 if ih["filter_kernel_seconds_fp32"] else None
     f64 = i64["filter_flops"] / i64["filter_kernel_seconds"] / 1e12 if i64["filter_kernel_seconds"] else None
     out = _base("eigensolves/s, mixed-precision filter (FP32 MFMA) with FP64 final sweeps, residual <=1e-10",
                 1.0 / res[1]["t"], "solves/s", args.steps, args.warmup, 1e3 * res[1]["t"], "complex64 filter + f64",
@@ -377,6 +379,10 @@ def run_precision(args):
                            "max_eig_error_rel": res[2]["err"], "max_rel_residual": res[2]["res"],
                            "filter_tflops_fp32": fr, "phase_seconds": res[2]["phases"],
                            "filter_flops_fp32_share": ir["filter_flops_fp32"] / ir["filter_flops"]},
+                "ritz16": {"solves_per_s": 1.0 / res[3]["t"], "speedup_vs_fp64": res[0]["t"] / res[3]["t"],
+                           "iterations": ih["iterations"], "iterations_low_precision": ih["iterations_fp32"],
+                           "max_eig_error_rel": res[3]["err"], "max_rel_residual": res[3]["res"],
+                           "filter_tflops_fp16_operands": fh, "phase_seconds": res[3]["phases"]},
                 "roofline": {"bound": "mfma", "achieved": f32, "peak": 157.3, "unit": "TFLOP/s",
                              "frac": f32 / 157.3 if f32 else None, "flop_count": FLOP_COUNT_NOTE,
                              "matrix_core_frac": GAUSS3_SHARE * f32 / 157.3 if f32 else None, "traffic": None}})
