@@ -170,13 +170,13 @@ chfsi_status chfsi_copy_factors(chfsi_ctx ctx, void* A, int64_t lda, void* L, in
 /* Chebyshev filter (eq. (2), scaled and shifted): Y (device n x k) is
  * overwritten with p(A) Y, p(t) = C_m((t - c)/e) / C_m((a0 - c)/e),
  * c = (a + b)/2, e = (b - a)/2.  Requires b > a, m >= 1.  With the context's
- * precision 1 or 2 the recurrence runs in complex FP32 (A and Y rounded to
- * FP32, the result widened back to FP64; Y carries no Ritz values here, so
- * precision 2 filters like 1). */
+ * precision 1, 2 or 3 the recurrence runs in complex FP32 (A and Y rounded
+ * to FP32, the result widened back to FP64; Y carries no Ritz values here,
+ * so 2 and 3 filter like 1: chfsi_filter_ritz is their filter). */
 chfsi_status chfsi_filter(chfsi_ctx ctx, const void* A, int64_t lda, void* Y, int64_t ldy, int64_t k, int32_t m, double a,
                           double b, double a0);
 
-/* The same filter as the solver's precision 2 computes it (eq. (2) split by
+/* The same filter as the solver's precision 2 and 3 compute it (eq. (2) split by
  * linearity): Y (device n x k) holds Ritz vectors of A with Ritz values mu
  * (host, k FP64 values) and AY = A Y (device n x k, FP64, leading dimension
  * lday).  Y is overwritten with p(A) Y = Y diag(t_m(mu)) + D_m, where t_i is
