@@ -2508,7 +2508,6 @@ chfsi_status chfsi_filter_ritz(chfsi_ctx c, const void* A, int64_t lda, void* Y,
     }
     c->P_cap = std::max(c->P_cap, std::min(c->P_elems, (size_t)c->opts.filter_splitk * c->n * k));
     const int64_t n = c->n;
-    c->A32.ensure((size_t)n * n * sizeof(cc));
     c->Y32.ensure((size_t)n * k * sizeof(cc));
     c->Y32b.ensure((size_t)n * k * sizeof(cc));
     c->R32.ensure((size_t)n * k * sizeof(cc));
@@ -2517,6 +2516,7 @@ chfsi_status chfsi_filter_ritz(chfsi_ctx c, const void* A, int64_t lda, void* Y,
       c->A16.ensure((size_t)2 * n * f16_plane_ld(n) * sizeof(_Float16));
       to_f16_planes((const zc*)A, lda, n, c->A16.p, c->st);
     } else {
+      c->A32.ensure((size_t)n * n * sizeof(cc));
       to_f32((const zc*)A, lda, (cc*)c->A32.p, n, n, n, c->st);
     }
     std::vector<double> mu_h(mu, mu + k);
