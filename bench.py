@@ -799,9 +799,20 @@ def run_mixed_same_workload(args, cfg, probs, fp64_rate, precision=1):
             "filter_launches_fp32": sum(i["filter_launches_fp32"] for i in infos),
             "filter_tflops_fp64_part": f64f / f64s / 1e12 if f64s > 0 else None,
             "filter_flops_fp32_share": f32f / max(1.0, sum(i["filter_flops"] for i in infos)),
-            "fp32_roofline": {"bound": "mfma", "achieved": f32f / f32s / 1e12 if f32s else None, "peak": 157.3,
-                              "unit": "TFLOP/s", "frac": f32f / f32s / 1e12 / 157.3 if f32s else None},
+            "low_precision_roofline": low_precision_roofline(precision, f32f, f32s),
             "phase_seconds_per_solve": phase}
+
+
+def low_precision_roofline(precision, flops, seconds):
+    """Roofline of a mixed form's lower-precision filter steps against the
+    matrix peak of their operand type: FP32 (157.3 TFLOP/s dense) for
+    precision 1 and 2, FP16 (2500 TFLOP/s dense) for precision 3."""
+    peak, operands = (2500.0, "fp16") if precision == 3 else (157.3, "fp32")
+    achieved = flops / seconds / 1e12 if seconds else None
+    note = ("8 real flops per complex multiply-add; the FP16 steps execute all 8 (four real products)"
+            if precision == 3 else FLOP_COUNT_NOTE)
+    return {"bound": "mfma", "operands": operands, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak if achieved else None, "flop_count": note}
 
 
 def _eig_report(lam_exact, ev64, others, anorm):

@@ -144,3 +144,12 @@ def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
                UBSAN_OPTIONS="print_stacktrace=1")
     r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env, timeout=120)
     assert r.returncode == 0 and "oracle sanitizer run ok" in r.stdout, r.stdout
+
+
+def test_low_precision_roofline_takes_the_operand_peak():
+    r2 = bench.low_precision_roofline(2, 2.0e14, 1.5)
+    r3 = bench.low_precision_roofline(3, 2.0e14, 0.4)
+    assert r2["peak"] == 157.3 and r2["operands"] == "fp32"
+    assert r3["peak"] == 2500.0 and r3["operands"] == "fp16"
+    assert r3["achieved"] == pytest.approx(500.0) and r3["frac"] == pytest.approx(0.2)
+    assert bench.low_precision_roofline(1, 0.0, 0.0)["achieved"] is None
