@@ -75,3 +75,50 @@ def test_residual_part_is_small_for_near_eigenvectors():
     F, D = _split_filter(p.A, Yr, mu, m, a, b, a0)
     ratio = np.abs(D).max() / np.abs(F).max()
     assert 1e-9 < ratio < 1e-4, ratio
+
+
+def _h(z):
+    # complex values with real and imaginary parts rounded to FP16
+    return z.real.astype(np.float16).astype(np.float64) + 1j * z.imag.astype(np.float16).astype(np.float64)
+
+
+@pytest.mark.parametrize("delta", [1e-2, 1e-5])
+def test_fp16_operands_on_the_residual_part_keep_errors_relative_to_it(delta):
+    """The reading behind the FP16 form, checked in emulation against the
+    oracle's FP64 filter: with the products' operands (A and each iterate
+    D_i, the latter scaled per column by a power of two) rounded to FP16 and
+    everything else exact, the filtered block's error scales with |D| / |F|
+    (about delta for Ritz vectors of a block delta away from an invariant
+    subspace), while rounding Y_i itself to FP16 errs at FP16's level
+    whatever delta is."""
+    n, k, m = 150, 12, 8
+    p = workloads.make_problem(n, 23)
+    order = np.argsort(p.lam)
+    rng = np.random.default_rng(7)
+    E = rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k))
+    Q, _ = np.linalg.qr(p.Q[:, order[:k]] + delta * E / np.linalg.norm(E, axis=0)[None, :])
+    mu, Y0 = oracle.rayleigh_ritz(p.A, Q)
+    a, b, a0 = float(mu[-1]), float(p.lam.max()) * 1.001, float(p.lam.min())
+    ref = oracle.chebyshev_filter(p.A, Y0, m, a, b, a0)
+    cs = _schedule(m, a, b, a0)
+    A16 = _h(p.A)
+    # split form, FP16 operands for the residual part
+    R = p.A @ Y0 - Y0 * mu[None, :]
+    s = 2.0 ** np.ceil(np.log2(np.abs(np.concatenate([R.real, R.imag])).max(axis=0)))
+    Rs = R / s[None, :]
+    t_prev, t = np.ones_like(mu), cs[0][0] * mu + cs[0][1]
+    D_prev, D = np.zeros_like(Rs), cs[0][0] * Rs
+    for al, be, ga in cs[1:]:
+        D_next = al * (A16 @ _h(D)) + be * D + ga * D_prev + Rs * (al * t)[None, :]
+        t_prev, t = t, al * mu * t + be * t + ga * t_prev
+        D_prev, D = D, D_next
+    F = Y0 * t[None, :] + D * s[None, :]
+    # the plain recurrence with FP16 operands
+    Yp, Yc = Y0, cs[0][0] * (A16 @ _h(Y0)) + cs[0][1] * Y0
+    for al, be, ga in cs[1:]:
+        Yp, Yc = Yc, al * (A16 @ _h(Yc)) + be * Yc + ga * Yp
+    scale = np.abs(ref).max()
+    err_split = np.abs(F - ref).max() / scale
+    err_plain = np.abs(Yc - ref).max() / scale
+    assert err_plain > 1e-5, err_plain
+    assert err_split < 0.1 * delta, (err_split, delta)
